@@ -1,0 +1,290 @@
+"""Seeded synthetic inputs for MFA volume rendering.
+
+This module only *draws* inputs: control-point grids, knot vectors, cameras,
+transfer-function tables, render parameters and pixel subsets.  It holds
+none of the renderer's arithmetic and is shared, as plain numpy arrays and
+numbers, by the HIP library's tests and benchmark and by the CPU oracle.
+
+Least-squares fits of the synthetic test field use scipy's B-spline
+collocation matrices (an independent library routine); the fitting step is
+input preparation, the MFA encoder itself being an offline step outside the
+renderer (Sect. 3: the encoded model is the renderer's input).
+
+All random draws use ``numpy.random.default_rng(seed)`` (PCG64).
+
+Workloads (sizes of the paper-shaped synthetic configurations):
+
+* ``c1``: degree 2, 16^3 control points i.i.d. U[0,1] (seed 0), clamped
+  uniform knots; 128^2 orthographic image looking down -z; step 1/256;
+  256-entry linear-ramp RGBA table over [0, 1].
+* ``c2``: degree 3, 64^3 control points = least-squares fit of
+  ``sin(6x) cos(5y) sin(7z) + 0.3 exp(-40 |r - 0.5|^2)`` sampled on a 128^3
+  grid; clamped uniform knots; 512^2 perspective image (60 deg vertical
+  field of view, orbit radius 2, azimuth 30 deg, elevation 20 deg);
+  step 1/512; 8-node piecewise-linear RGBA table (seed 2) rasterised to 256
+  entries over [min P, max P].
+* ``c3``: degree 3, 256^3 control points = the same field fitted on a 512^3
+  grid, plus N(0, 0.01^2) noise (seed 3); same camera at 1024^2; step
+  1/1024; table as in c2 over this model's range; 4096-pixel subset drawn
+  without replacement (seed 4).
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+# ---------------------------------------------------------------------------
+# plain input records (numpy / python scalars only)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class ModelSpec:
+    degree: tuple                      # (p_x, p_y, p_z)
+    knots: tuple                       # three float64 arrays
+    ctrl: np.ndarray                   # float64 (n_z, n_y, n_x), x fastest
+    lo: tuple = (0.0, 0.0, 0.0)
+    hi: tuple = (1.0, 1.0, 1.0)
+
+    @property
+    def n(self):
+        nz, ny, nx = self.ctrl.shape
+        return (nx, ny, nz)
+
+
+@dataclass
+class CameraSpec:
+    kind: str                          # "ortho" | "persp"
+    eye: tuple
+    target: tuple
+    up: tuple
+    width: int
+    height: int
+    fov_y_deg: float = 60.0
+    ortho_half_w: float = 0.5
+    ortho_half_h: float = 0.5
+
+
+@dataclass
+class TFSpec:
+    table: np.ndarray                  # float32 (n, 4) RGBA
+    v_lo: float
+    v_hi: float
+
+
+@dataclass
+class ParamSpec:
+    step: float
+    ert_alpha: float = 0.99
+    shading: bool = True
+    ka: float = 0.1
+    kd: float = 0.7
+    ks: float = 0.2
+    shininess: int = 10
+    headlight: bool = True
+    light_dir: tuple = (0.0, 0.0, 1.0)
+
+
+@dataclass
+class Workload:
+    name: str
+    model: ModelSpec
+    camera: CameraSpec
+    tf: TFSpec
+    params: ParamSpec
+    subset: np.ndarray | None = None   # flat pixel indices, or None = full
+    extra: dict = field(default_factory=dict)
+
+
+# ---------------------------------------------------------------------------
+# knot vectors
+# ---------------------------------------------------------------------------
+
+def clamped_uniform_knots(n: int, p: int) -> np.ndarray:
+    """``p+1`` zeros, interior knots ``k/(n-p)``, ``p+1`` ones."""
+    m = n - p
+    inner = np.array([k / m for k in range(1, m)], dtype=np.float64)
+    return np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)])
+
+
+def clamped_beta_knots(n: int, p: int, rng: np.random.Generator,
+                       a: float = 2.0, b: float = 5.0) -> np.ndarray:
+    """Clamped knots whose ``n-p`` spacings are i.i.d. Beta(a, b) draws,
+    normalised to sum 1; a spacing below ``1e-3/(n-p)`` is redrawn."""
+    m = n - p
+    d = rng.beta(a, b, size=m)
+    while True:
+        small = d < 1e-3 / m
+        if not small.any():
+            break
+        d[small] = rng.beta(a, b, size=int(small.sum()))
+    d = d / d.sum()
+    inner = np.cumsum(d)[:-1]
+    inner = np.minimum(inner, np.nextafter(1.0, 0.0))
+    return np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)])
+
+
+# ---------------------------------------------------------------------------
+# least-squares fits of the synthetic field (scipy collocation matrices)
+# ---------------------------------------------------------------------------
+
+def _pinv_apply(knots: np.ndarray, p: int, xs: np.ndarray, ys: np.ndarray) -> np.ndarray:
+    """Least-squares 1-D coefficients c minimising |B c - ys| where B is the
+    collocation matrix of the spline space at the sites xs."""
+    from scipy.interpolate import BSpline
+    B = BSpline.design_matrix(xs, knots, p).toarray()
+    c, *_ = np.linalg.lstsq(B, ys, rcond=None)
+    return c
+
+
+def fit_test_field(n: int, p: int, grid: int) -> tuple[np.ndarray, np.ndarray]:
+    """Separable least-squares fit of
+    ``f = sin(6x) cos(5y) sin(7z) + 0.3 exp(-40 |r - 0.5|^2)`` sampled at
+    ``x_g = g/(grid-1)`` on a ``grid^3`` lattice, with ``n^3`` control points
+    on clamped uniform knots.
+
+    Both terms are products of one-dimensional factors, and the least-squares
+    operator of a tensor-product collocation matrix is the tensor product of
+    the per-axis pseudo-inverses, so the 3-D fit equals the sum of outer
+    products of 1-D fits (exactly, in exact arithmetic).
+    Returns (control points (n,n,n) x fastest, knots).
+    """
+    U = clamped_uniform_knots(n, p)
+    xs = np.arange(grid, dtype=np.float64) / (grid - 1)
+    g = np.exp(-40.0 * (xs - 0.5) ** 2)
+    ax = _pinv_apply(U, p, xs, np.sin(6.0 * xs))
+    by = _pinv_apply(U, p, xs, np.cos(5.0 * xs))
+    cz = _pinv_apply(U, p, xs, np.sin(7.0 * xs))
+    gx = _pinv_apply(U, p, xs, g)
+    # P[k, j, i] = a_i b_j c_k + 0.3 g_i g_j g_k
+    P = (cz[:, None, None] * by[None, :, None] * ax[None, None, :]
+         + 0.3 * gx[:, None, None] * gx[None, :, None] * gx[None, None, :])
+    return P, U
+
+
+def test_field(x, y, z):
+    """The analytic field the c2/c3 models are fitted to."""
+    r2 = (x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2
+    return np.sin(6 * x) * np.cos(5 * y) * np.sin(7 * z) + 0.3 * np.exp(-40 * r2)
+
+
+# ---------------------------------------------------------------------------
+# transfer functions and cameras
+# ---------------------------------------------------------------------------
+
+def ramp_tf(n: int = 256, v_lo: float = 0.0, v_hi: float = 1.0) -> TFSpec:
+    e = np.arange(n, dtype=np.float64) / (n - 1)
+    table = np.repeat(e[:, None], 4, axis=1).astype(np.float32)
+    return TFSpec(table, v_lo, v_hi)
+
+
+def pwl_tf(seed: int, v_lo: float, v_hi: float, nodes: int = 8, n: int = 256,
+           alpha_max: float = 0.05) -> TFSpec:
+    """``nodes`` equally spaced nodes, RGB ~ U[0,1], alpha ~ U[0, alpha_max],
+    rasterised (FP64 linear interpolation) to ``n`` entries at e/(n-1)."""
+    rng = np.random.default_rng(seed)
+    rgb = rng.random((nodes, 3))
+    alpha = rng.random(nodes) * alpha_max
+    xn = np.linspace(0.0, 1.0, nodes)
+    xe = np.arange(n, dtype=np.float64) / (n - 1)
+    table = np.empty((n, 4))
+    for ch in range(3):
+        table[:, ch] = np.interp(xe, xn, rgb[:, ch])
+    table[:, 3] = np.interp(xe, xn, alpha)
+    return TFSpec(table.astype(np.float32), float(v_lo), float(v_hi))
+
+
+def orbit_camera(width: int, height: int, az_deg: float, el_deg: float,
+                 radius: float = 2.0, fov_y_deg: float = 60.0,
+                 target=(0.5, 0.5, 0.5)) -> CameraSpec:
+    az = math.radians(az_deg)
+    el = math.radians(el_deg)
+    eye = (target[0] + radius * math.cos(el) * math.sin(az),
+           target[1] + radius * math.sin(el),
+           target[2] + radius * math.cos(el) * math.cos(az))
+    return CameraSpec("persp", eye, tuple(target), (0.0, 1.0, 0.0), width, height,
+                      fov_y_deg=fov_y_deg)
+
+
+def random_orbit_camera(rng: np.random.Generator, width: int, height: int,
+                        radius: float = 2.0) -> CameraSpec:
+    az = rng.uniform(0.0, 360.0)
+    el = rng.uniform(-60.0, 60.0)
+    return orbit_camera(width, height, az, el, radius)
+
+
+# ---------------------------------------------------------------------------
+# the named workloads
+# ---------------------------------------------------------------------------
+
+def c1() -> Workload:
+    n, p = 16, 2
+    rng = np.random.default_rng(0)
+    ctrl = rng.random(n ** 3).reshape(n, n, n)
+    U = clamped_uniform_knots(n, p)
+    model = ModelSpec((p, p, p), (U, U.copy(), U.copy()), ctrl)
+    cam = CameraSpec("ortho", (0.5, 0.5, 2.0), (0.5, 0.5, 0.5), (0.0, 1.0, 0.0),
+                     128, 128, ortho_half_w=0.5, ortho_half_h=0.5)
+    return Workload("c1", model, cam, ramp_tf(256, 0.0, 1.0), ParamSpec(step=1.0 / 256))
+
+
+_C2_CACHE: dict = {}
+
+
+def c2() -> Workload:
+    if "c2" not in _C2_CACHE:
+        _C2_CACHE["c2"] = fit_test_field(64, 3, 128)
+    P, U = _C2_CACHE["c2"]
+    model = ModelSpec((3, 3, 3), (U, U.copy(), U.copy()), P.copy())
+    cam = orbit_camera(512, 512, 30.0, 20.0)
+    tf = pwl_tf(2, float(P.min()), float(P.max()))
+    return Workload("c2", model, cam, tf, ParamSpec(step=1.0 / 512))
+
+
+def c3(subset_size: int = 4096) -> Workload:
+    P, U = fit_test_field(256, 3, 512)
+    rng = np.random.default_rng(3)
+    P = P + rng.normal(0.0, 0.01, size=P.size).reshape(P.shape)
+    model = ModelSpec((3, 3, 3), (U, U.copy(), U.copy()), P)
+    cam = orbit_camera(1024, 1024, 30.0, 20.0)
+    tf = pwl_tf(2, float(P.min()), float(P.max()))
+    sub = np.sort(np.random.default_rng(4).choice(1024 * 1024, size=subset_size,
+                                                  replace=False))
+    return Workload("c3", model, cam, tf, ParamSpec(step=1.0 / 1024), subset=sub)
+
+
+def random_model(rng: np.random.Generator, n=(9, 7, 8), degree=(3, 2, 1),
+                 beta_knots=False, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                 smooth=True) -> ModelSpec:
+    """A small random model for parity cases (any degree, non-uniform knots,
+    non-unit box).  ``smooth`` adds a low-frequency trend to the noise so
+    that shading sees a meaningful gradient."""
+    knots = []
+    for k in range(3):
+        if beta_knots:
+            knots.append(clamped_beta_knots(n[k], degree[k], rng))
+        else:
+            knots.append(clamped_uniform_knots(n[k], degree[k]))
+    nx, ny, nz = n
+    ctrl = rng.random(nx * ny * nz).reshape(nz, ny, nx)
+    if smooth:
+        zz, yy, xx = np.meshgrid(np.linspace(0, 1, nz), np.linspace(0, 1, ny),
+                                 np.linspace(0, 1, nx), indexing="ij")
+        ctrl = 0.3 * ctrl + 0.7 * (np.sin(3 * xx) * np.cos(2 * yy) + zz)
+    return ModelSpec(tuple(degree), tuple(knots), ctrl, tuple(map(float, lo)),
+                     tuple(map(float, hi)))
+
+
+def pixel_subset(width: int, height: int, size: int, seed: int) -> np.ndarray:
+    return np.sort(np.random.default_rng(seed).choice(width * height, size=size,
+                                                      replace=False))
+
+
+def uniform_points(rng: np.random.Generator, m: int, lo=(0.0, 0.0, 0.0),
+                   hi=(1.0, 1.0, 1.0)) -> np.ndarray:
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    return lo + rng.random((m, 3)) * (hi - lo)
