@@ -1,0 +1,276 @@
+#!/usr/bin/env python3
+"""Benchmark of the MFA ray caster on one MI355X.
+
+A step is one frame: one launch of the fused render kernel over the whole
+image (ray setup, span location, basis and derivatives, (p+1)^3 contraction
+to value and gradient, transfer function, Phong shading, compositing with
+early termination).  The workload is the 256^3-control-point degree-3 model
+(least-squares fit plus N(0, 0.01^2) noise), 1024x1024 perspective frame,
+step 1/1024, with the control points stored once in FP32 and once in BF16.
+
+Printed: one JSON line with MFA samples/s (samples actually composited,
+value + gradient each), frames/s, p50/p99 frame latency (HIP events on the
+render stream), the roofline of the render kernel, and the FP64 CPU oracle
+timed on this host on a bounded sample of the same frame (whose pixels also
+give the accuracy of the GPU frame).
+"""
+
+from __future__ import annotations
+
+import argparse
+import copy
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_2204_11762_amd import workloads as wl  # noqa: E402
+
+METRIC = "MFA samples/s (value+grad) BF16 vs FP32 at stated err; p50/p99 frame latency"
+PEAK_FP32_VALU = 157.3e12     # MI355X FP32 vector peak (packed issue)
+
+
+def flops_per_sample(p: int) -> int:
+    """Algorithmic FP32 operations per sample at degree p: sum-factorised
+    contraction to value + 3 derivatives, basis and derivative triangles on
+    three axes, and ~50 for position, transfer function, shading and
+    compositing."""
+    q = p + 1
+    contraction = 2 * (2 * q ** 3 + 3 * q ** 2 + 4 * q)
+    basis = 3 * (2 * p + 5 * p * (p + 1) // 2 + 3 * q)
+    return contraction + basis + 50
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on host cores (before the GPU is touched)
+# ---------------------------------------------------------------------------
+
+_ORACLE_STATE = {}
+
+
+def _oracle_chunk(pix):
+    from oracle import raycast as orc
+    M, cam, tf, prm = _ORACLE_STATE["args"]
+    res = orc.render_pixels(M, cam, tf, prm, pix)
+    return pix, res.rgba, res.samples
+
+
+def cpu_baseline(wk, n_rays: int, seed: int, workers: int):
+    import multiprocessing as mp
+
+    from oracle import bspline as ob
+    from oracle import raycast as orc
+    m = wk.model
+    M = ob.Model(tuple(m.degree), tuple(np.asarray(k) for k in m.knots), np.asarray(m.ctrl),
+                 np.asarray(m.lo, float), np.asarray(m.hi, float))
+    c = wk.camera
+    cam = orc.Camera(c.kind, c.eye, c.target, c.up, c.width, c.height, c.fov_y_deg,
+                     c.ortho_half_w, c.ortho_half_h)
+    tf = orc.TransferFunction(wk.tf.table, wk.tf.v_lo, wk.tf.v_hi)
+    p = wk.params
+    prm = orc.RenderParams(step=p.step, ert_alpha=p.ert_alpha, shading=p.shading, ka=p.ka,
+                           kd=p.kd, ks=p.ks, shininess=p.shininess, headlight=p.headlight,
+                           light_dir=p.light_dir)
+    # sample among the pixels whose ray meets the volume
+    allpix = np.arange(c.width * c.height)
+    r, cc = np.divmod(allpix, c.width)
+    o, d = orc.camera_rays(cam, r, cc)
+    t0, t1, hit = orc.slab(o, d, M.lo, M.hi)
+    rng = np.random.default_rng(seed)
+    pix = np.sort(rng.choice(np.nonzero(hit)[0], size=n_rays, replace=False))
+    _ORACLE_STATE["args"] = (M, cam, tf, prm)
+    chunks = np.array_split(pix, max(workers * 4, 1))
+    t_start = time.perf_counter()
+    if workers > 1:
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_oracle_chunk, chunks)
+    else:
+        parts = [_oracle_chunk(ch) for ch in chunks]
+    wall = time.perf_counter() - t_start
+    rgba = np.concatenate([q[1] for q in parts])
+    samples = int(sum(q[2].sum() for q in parts))
+    return {"pix": pix, "rgba": rgba, "samples": samples, "wall": wall}
+
+
+def host_cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# ---------------------------------------------------------------------------
+# GPU leg
+# ---------------------------------------------------------------------------
+
+def gpu_leg(b, ctx, wk, store: int, steps: int, warmup: int, log):
+    import torch
+    cam = wk.camera
+    h = b.mfa_model_upload(ctx, wk.model, store)
+    try:
+        out = torch.zeros((cam.height, cam.width, 4), dtype=torch.float32, device="cuda")
+        cnt = torch.zeros((1,), dtype=torch.int64, device="cuda")
+        b.mfa_render(ctx, h, cam, wk.tf, wk.params, out, cnt)
+        torch.cuda.synchronize()
+        samples = int(cnt.item())
+        image = out.cpu().numpy()
+        nominal_prm = copy.copy(wk.params)
+        nominal_prm.ert_alpha = 1.0
+        b.mfa_render(ctx, h, cam, wk.tf, nominal_prm, out, cnt)
+        torch.cuda.synchronize()
+        nominal = int(cnt.item())
+        for _ in range(warmup):
+            b.mfa_render(ctx, h, cam, wk.tf, wk.params, out, None)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            ev0[i].record(stream)
+            b.mfa_render(ctx, h, cam, wk.tf, wk.params, out, None, stream=stream)
+            ev1[i].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = np.array([a.elapsed_time(e) for a, e in zip(ev0, ev1)])  # ms
+        # nominal (no termination) frames, a few, for the ERT-free rate
+        nsteps = max(3, steps // 10)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(nsteps):
+            b.mfa_render(ctx, h, cam, wk.tf, nominal_prm, out, None, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        nominal_ms = e0.elapsed_time(e1) / nsteps
+        log(f"store={'fp32' if store == 0 else 'bf16'}: {samples} samples/frame, "
+            f"{wall / steps * 1e3:.3f} ms/frame wall, kernel p50 {np.median(lat):.3f} ms")
+        return {"samples": samples, "nominal": nominal, "wall": wall, "lat": lat,
+                "nominal_ms": nominal_ms, "image": image,
+                "model_bytes": b.mfa_model_bytes(ctx, h)}
+    finally:
+        b.mfa_model_free(ctx, h)
+
+
+def rmse_on(image, base):
+    if base is None:
+        return None
+    got = image.reshape(-1, 4)[base["pix"]].astype(np.float64)
+    err = got - base["rgba"]
+    return {"rmse": float(np.sqrt((err ** 2).mean())), "max_abs": float(np.abs(err).max()),
+            "pixels": int(len(base["pix"])), "reference": "FP64 oracle, ERT on"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--store", choices=["bf16", "fp32"], default="bf16",
+                    help="storage of the headline number (both are measured)")
+    ap.add_argument("--cpu-rays", type=int, default=24576,
+                    help="rays of the oracle's bounded sample (0 = skip the CPU leg)")
+    ap.add_argument("--cpu-workers", type=int, default=0, help="0 = host cores, at most 16")
+    ap.add_argument("--seed", type=int, default=5)
+    args = ap.parse_args()
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the ray caster shards "
+              "by image tiles across GPUs, which this build does not launch.", file=sys.stderr)
+        sys.exit(2)
+
+    log("generating the 256^3 degree-3 workload")
+    wk = wl.c3()
+    p = int(max(wk.model.degree))
+
+    base = None
+    cores = 0
+    if args.cpu_rays > 0:
+        cores = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
+        log(f"CPU oracle on {args.cpu_rays} rays with {cores} processes")
+        base = cpu_baseline(wk, args.cpu_rays, args.seed, cores)
+        log(f"CPU oracle: {base['samples']} samples in {base['wall']:.2f} s")
+
+    import torch
+
+    from paper_2204_11762_amd import binding as b
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ctx = b.mfa_create(0)
+    try:
+        legs = {}
+        for name, store in (("fp32", 0), ("bf16", 1)):
+            legs[name] = gpu_leg(b, ctx, wk, store, args.steps, args.warmup, log)
+    finally:
+        b.mfa_destroy(ctx)
+
+    head = legs[args.store]
+    other = legs["fp32" if args.store == "bf16" else "bf16"]
+    fps = args.steps / head["wall"]
+    value = head["samples"] * fps
+    kern_ms = float(head["lat"].mean())
+    flops = head["samples"] * flops_per_sample(p)
+    achieved = flops / (kern_ms * 1e-3)
+
+    def summary(leg, name):
+        return {"store": name, "samples_per_frame": leg["samples"],
+                "samples_per_s": leg["samples"] * args.steps / leg["wall"],
+                "ms_per_frame": leg["wall"] / args.steps * 1e3,
+                "p50_ms": float(np.percentile(leg["lat"], 50)),
+                "p99_ms": float(np.percentile(leg["lat"], 99)),
+                "nominal_samples_per_frame": leg["nominal"],
+                "nominal_samples_per_s": leg["nominal"] / (leg["nominal_ms"] * 1e-3),
+                "model_bytes": leg["model_bytes"],
+                "error": rmse_on(leg["image"], base)}
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["wall"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "mfa-256^3-p3-1024x1024-persp-step1/1024 "
+                               "(LS fit of sin6x cos5y sin7z + 0.3 exp(-40|r-0.5|^2) + N(0,0.01^2))",
+                   "store": args.store, "degree": p, "image": [1024, 1024],
+                   "step": wk.params.step, "ert_alpha": wk.params.ert_alpha,
+                   "shading": "phong"},
+        "frames_per_s": fps,
+        "p50_ms": float(np.percentile(head["lat"], 50)),
+        "p99_ms": float(np.percentile(head["lat"], 99)),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                     "kernel": "render_kernel<3,%s,shade>" % ("1" if args.store == "bf16" else "0"),
+                     "kernel_ms": kern_ms, "flops_per_sample": flops_per_sample(p)},
+        "legs": {"fp32": summary(legs["fp32"], "fp32"), "bf16": summary(legs["bf16"], "bf16")},
+    }
+    if base is not None:
+        line["cpu_baseline"] = {"value": base["samples"] / base["wall"], "unit": "samples/s",
+                                "cores": cores, "kind": "oracle",
+                                "sample": f"{len(base['pix'])} seeded hit rays of the same frame, "
+                                          f"{base['samples']} samples, {base['wall']:.1f} s wall",
+                                "host_cpu": host_cpu_model()}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

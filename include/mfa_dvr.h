@@ -1,0 +1,202 @@
+/*
+ * mfa_dvr.h -- C ABI of the MI355X (gfx950) MFA direct volume renderer.
+ *
+ * The library ray-casts a multivariate functional approximation (MFA): a
+ * non-rational tensor-product B-spline volume given by a degree and a
+ * clamped knot vector per axis and a grid of control points (Sect. 2.3 of
+ * "MFA-DVR: direct volume rendering of MFA models").  Rendering follows
+ * Sect. 3.1 and Algorithm 1: one ray per pixel, constant-distance samples
+ * between the first and last sample inside the volume, normalisation to
+ * the unit cube, the value query, the transfer function, the gradient
+ * query with Phong shading, front-to-back compositing and early ray
+ * termination.  All work runs in HIP kernels on the GPU.
+ *
+ * Conventions common to every entry point:
+ *  - Return value: MFA_OK (0) or a negative mfa_status.  On error nothing
+ *    is enqueued, output buffers are untouched, and mfa_last_error()
+ *    describes the failure.
+ *  - Host pointers inside descriptors (knots, control points, transfer
+ *    function table) are owned by the caller and are only read during the
+ *    call; the caller may free them as soon as the call returns.
+ *  - Device pointers (images, points, values, gradients, counters) are
+ *    owned by the caller, must be device memory of the context's GPU, and
+ *    must stay valid until the work enqueued on the given stream has
+ *    completed.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Render and
+ *    evaluation calls are asynchronous on that stream.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef MFA_DVR_H
+#define MFA_DVR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mfa_status;
+#define MFA_OK 0
+#define MFA_ERR_INVALID (-1) /* bad argument: sizes, camera, TF, step, pointers */
+#define MFA_ERR_MODEL (-2)   /* malformed model descriptor */
+#define MFA_ERR_NOMEM (-3)   /* device memory or the context budget exhausted */
+#define MFA_ERR_DEVICE (-4)  /* HIP runtime error (including an earlier fault) */
+#define MFA_ERR_HANDLE (-5)  /* unknown context or model handle */
+
+/* Storage precision of the control points on the device.  Basis functions
+ * and all accumulation are FP32 in either case. */
+#define MFA_STORE_F32 0
+#define MFA_STORE_BF16 1 /* FP64 -> FP32 -> BF16, each step round-to-nearest-even */
+
+#define MFA_CAMERA_ORTHO 0
+#define MFA_CAMERA_PERSP 1
+
+#define MFA_MAX_DEGREE 4
+#define MFA_MAX_TF 4096
+
+/* MFA model (Sect. 2.3): per axis a degree p in [1, MFA_MAX_DEGREE], n >= p+1
+ * control points and a knot vector of n+p+1 FP64 values that is
+ * non-decreasing and clamped (p+1 zeros first, p+1 ones last; interior
+ * knots in (0,1) with multiplicity <= p).  Control points are FP64, finite,
+ * x fastest: P[i,j,k] = ctrl[i + n0*(j + n1*k)].  The model maps the box
+ * [lo, hi] (lo < hi per axis) affinely onto the unit parameter cube. */
+typedef struct mfa_model_desc {
+  int32_t degree[3];
+  int32_t store; /* MFA_STORE_F32 or MFA_STORE_BF16 */
+  int64_t n_ctrl[3];
+  const double* knots[3];
+  const double* ctrl;
+  double lo[3];
+  double hi[3];
+} mfa_model_desc;
+
+/* Fixed-point ray-cast camera (Sect. 3.1): one ray through the centre of
+ * every pixel, row 0 at the top of the image.  F = unit(target - eye),
+ * R = unit(F x up), V = R x F.
+ *  - MFA_CAMERA_ORTHO: origin eye + a*half_w*R + b*half_h*V, direction F;
+ *  - MFA_CAMERA_PERSP: origin eye, direction
+ *    unit(F + a*tan(fov/2)*(W/H)*R + b*tan(fov/2)*V),
+ *  with a = 2(c+1/2)/W - 1 and b = 1 - 2(r+1/2)/H for column c, row r.
+ * fov_y_deg is the vertical field of view in (0, 180). */
+typedef struct mfa_camera {
+  int32_t kind;
+  int32_t width;
+  int32_t height;
+  int32_t reserved;
+  double eye[3];
+  double target[3];
+  double up[3];
+  double fov_y_deg;
+  double ortho_half_w;
+  double ortho_half_h;
+} mfa_camera;
+
+/* Transfer function (Algorithm 1: colour and opacity transfer functions),
+ * as one RGBA table of n entries (2 <= n <= MFA_MAX_TF), host memory,
+ * linearly interpolated over [v_lo, v_hi] (v_lo < v_hi); values outside
+ * the range clamp to the end entries. */
+typedef struct mfa_tf {
+  int32_t n;
+  int32_t reserved;
+  const float* rgba; /* n*4 floats */
+  double v_lo;
+  double v_hi;
+} mfa_tf;
+
+/* Sampling, shading and termination (Sect. 3.1, Algorithm 1).
+ *  step       constant world-space distance between samples (> 0);
+ *             a ray with entry/exit parameters t0 < t1 takes
+ *             floor((t1 - t0)/step) samples at t0 + (s + 1/2)*step;
+ *  ert_alpha  early ray termination: a ray stops once its accumulated
+ *             opacity exceeds this value, tested after compositing a
+ *             sample; >= 1 disables termination;
+ *  shading    0: unshaded colour; 1: Phong from the analytic gradient,
+ *             c' = min(1, (ka + kd*|n.l|)*c + ks*max(0, r.v)^shininess),
+ *             n = g / max(|g|, 1e-6), r = 2(n.l)n - l, v = -ray direction;
+ *  headlight  1: l = -F (light along the view axis); 0: l = light_dir
+ *             (normalised by the library);
+ *  shininess  integer exponent in [0, 256]. */
+typedef struct mfa_render_params {
+  double step;
+  double ert_alpha;
+  int32_t shading;
+  int32_t shininess;
+  int32_t headlight;
+  int32_t reserved;
+  double ka;
+  double kd;
+  double ks;
+  double light_dir[3];
+} mfa_render_params;
+
+typedef struct mfa_ctx mfa_ctx;
+
+/* Create a context bound to HIP device `device`.  Errors: MFA_ERR_INVALID
+ * (null ctx_out), MFA_ERR_DEVICE (no such device / HIP failure). */
+mfa_status mfa_create(int32_t device, mfa_ctx** ctx_out);
+
+/* Synchronise the device, free every model and internal buffer, and
+ * destroy the context.  Null is accepted and ignored. */
+mfa_status mfa_destroy(mfa_ctx* ctx);
+
+/* Cap the device bytes that the context's models may occupy (0 = only the
+ * device's free memory limits uploads).  Errors: MFA_ERR_HANDLE,
+ * MFA_ERR_INVALID (negative). */
+mfa_status mfa_set_memory_budget(mfa_ctx* ctx, int64_t bytes);
+
+/* Validate, convert and upload an MFA model (Sect. 3: the encoded model is
+ * the renderer's input).  Control points are rounded to the storage
+ * precision (RNE); per-span knot differences and their reciprocals are
+ * tabulated in FP32 for the basis recursion.  No gradient table is built:
+ * gradients are evaluated on demand (Sect. 3.1).  Synchronous: the model
+ * is resident and immutable when the call returns; *model_out receives a
+ * handle > 0.  Errors: MFA_ERR_MODEL (see mfa_model_desc), MFA_ERR_NOMEM,
+ * MFA_ERR_DEVICE, MFA_ERR_HANDLE, MFA_ERR_INVALID (null pointers, more
+ * than 2^31 bytes of control points). */
+mfa_status mfa_model_upload(mfa_ctx* ctx, const mfa_model_desc* desc, int64_t* model_out);
+
+/* Release a model after synchronising the device.  Errors: MFA_ERR_HANDLE. */
+mfa_status mfa_model_free(mfa_ctx* ctx, int64_t model);
+
+/* Device bytes held by a model.  Errors: MFA_ERR_HANDLE, MFA_ERR_INVALID. */
+mfa_status mfa_model_bytes(mfa_ctx* ctx, int64_t model, int64_t* bytes_out);
+
+/* Render an image (Algorithm 1) into rgba_dev: width*height*4 FP32,
+ * row-major, row 0 at the top, premultiplied (C_r, C_g, C_b, A).  A ray
+ * that misses the box yields (0,0,0,0).  If samples_dev is not null it
+ * receives (overwritten, one int64) the number of samples composited over
+ * the whole image, early-terminated rays counting up to and including
+ * their last sample.  Asynchronous on `stream`.  Errors: MFA_ERR_INVALID
+ * (camera, TF or parameters, null rgba_dev), MFA_ERR_HANDLE,
+ * MFA_ERR_DEVICE. */
+mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* camera, const mfa_tf* tf,
+                      const mfa_render_params* params, float* rgba_dev, int64_t* samples_dev,
+                      void* stream);
+
+/* Value and world-space gradient queries (Algorithm 1: value query and
+ * gradient query, all three derivatives at once) at n world points
+ * xyz_dev (n*3 FP64, point-major).  Points outside the box are clamped to
+ * it.  value_dev: n FP32; grad_dev: n*3 FP32 or null for value only.
+ * n = 0 is a no-op.  Asynchronous on `stream`.  Errors: MFA_ERR_INVALID
+ * (n < 0, null buffers with n > 0), MFA_ERR_HANDLE, MFA_ERR_DEVICE. */
+mfa_status mfa_eval_points(mfa_ctx* ctx, int64_t model, int64_t n, const double* xyz_dev,
+                           float* value_dev, float* grad_dev, void* stream);
+
+/* Host-only validation, callable without a GPU; the same checks that
+ * mfa_model_upload and mfa_render run before touching the device. */
+mfa_status mfa_validate_model(const mfa_model_desc* desc);
+mfa_status mfa_validate_render(const mfa_camera* camera, const mfa_tf* tf,
+                               const mfa_render_params* params);
+
+/* Message of the last failed call on this host thread (empty if none).
+ * Valid until the next library call on the same thread. */
+const char* mfa_last_error(void);
+
+/* Library version string. */
+const char* mfa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFA_DVR_H */

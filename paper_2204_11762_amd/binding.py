@@ -1,0 +1,276 @@
+"""ctypes binding of ``libmfadvr.so`` (C ABI declared in include/mfa_dvr.h).
+
+Argument marshalling only: every step of rendering and evaluation runs in
+the library's HIP kernels.  The functions carry the C names; descriptors are
+built from any object with the fields of the C structs (for example the
+records in ``workloads``), device buffers are torch CUDA tensors, and a
+non-zero status raises ``MFAError``.  The library must have been built
+(``python -m paper_2204_11762_amd.build``); importing this module without it
+raises, there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmfadvr.so")
+
+MFA_OK = 0
+MFA_ERR_INVALID = -1
+MFA_ERR_MODEL = -2
+MFA_ERR_NOMEM = -3
+MFA_ERR_DEVICE = -4
+MFA_ERR_HANDLE = -5
+STATUS_NAMES = {0: "MFA_OK", -1: "MFA_ERR_INVALID", -2: "MFA_ERR_MODEL", -3: "MFA_ERR_NOMEM",
+                -4: "MFA_ERR_DEVICE", -5: "MFA_ERR_HANDLE"}
+MFA_STORE_F32 = 0
+MFA_STORE_BF16 = 1
+MFA_CAMERA_ORTHO = 0
+MFA_CAMERA_PERSP = 1
+
+EXPORTED = ("mfa_create", "mfa_destroy", "mfa_set_memory_budget", "mfa_model_upload",
+            "mfa_model_free", "mfa_model_bytes", "mfa_render", "mfa_eval_points",
+            "mfa_validate_model", "mfa_validate_render", "mfa_last_error", "mfa_version")
+
+
+class MFAError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [("degree", C.c_int32 * 3), ("store", C.c_int32), ("n_ctrl", C.c_int64 * 3),
+                ("knots", C.POINTER(C.c_double) * 3), ("ctrl", C.POINTER(C.c_double)),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
+                ("reserved", C.c_int32), ("eye", C.c_double * 3), ("target", C.c_double * 3),
+                ("up", C.c_double * 3), ("fov_y_deg", C.c_double), ("ortho_half_w", C.c_double),
+                ("ortho_half_h", C.c_double)]
+
+
+class TF(C.Structure):
+    _fields_ = [("n", C.c_int32), ("reserved", C.c_int32), ("rgba", C.POINTER(C.c_float)),
+                ("v_lo", C.c_double), ("v_hi", C.c_double)]
+
+
+class RenderParams(C.Structure):
+    _fields_ = [("step", C.c_double), ("ert_alpha", C.c_double), ("shading", C.c_int32),
+                ("shininess", C.c_int32), ("headlight", C.c_int32), ("reserved", C.c_int32),
+                ("ka", C.c_double), ("kd", C.c_double), ("ks", C.c_double),
+                ("light_dir", C.c_double * 3)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2204_11762_amd.build` (no CPU fallback exists)")
+    lib = C.CDLL(LIB_PATH)
+    st = C.c_int32
+    vp = C.c_void_p
+    i64 = C.c_int64
+    sig = {
+        "mfa_create": (st, [C.c_int32, C.POINTER(vp)]),
+        "mfa_destroy": (st, [vp]),
+        "mfa_set_memory_budget": (st, [vp, i64]),
+        "mfa_model_upload": (st, [vp, C.POINTER(ModelDesc), C.POINTER(i64)]),
+        "mfa_model_free": (st, [vp, i64]),
+        "mfa_model_bytes": (st, [vp, i64, C.POINTER(i64)]),
+        "mfa_render": (st, [vp, i64, C.POINTER(Camera), C.POINTER(TF), C.POINTER(RenderParams),
+                            vp, vp, vp]),
+        "mfa_eval_points": (st, [vp, i64, i64, vp, vp, vp, vp]),
+        "mfa_validate_model": (st, [C.POINTER(ModelDesc)]),
+        "mfa_validate_render": (st, [C.POINTER(Camera), C.POINTER(TF), C.POINTER(RenderParams)]),
+        "mfa_last_error": (C.c_char_p, []),
+        "mfa_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return lib.mfa_last_error().decode()
+
+
+def _check(status: int) -> None:
+    if status != MFA_OK:
+        raise MFAError(status, last_error())
+
+
+# ---------------------------------------------------------------------------
+# descriptor marshalling
+# ---------------------------------------------------------------------------
+
+class _Keep:
+    """Host arrays referenced by a descriptor, kept alive for the call."""
+
+    def __init__(self):
+        self.refs = []
+
+    def f64(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        self.refs.append(a)
+        return a.ctypes.data_as(C.POINTER(C.c_double))
+
+    def f32(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        self.refs.append(a)
+        return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def model_desc(spec, store: int = MFA_STORE_F32, keep: _Keep | None = None) -> tuple:
+    """(ModelDesc, keep) from an object with degree, knots, ctrl, lo, hi.
+    ``ctrl`` is (n_z, n_y, n_x), x fastest."""
+    keep = keep or _Keep()
+    d = ModelDesc()
+    ctrl = np.asarray(spec.ctrl)
+    nz, ny, nx = ctrl.shape
+    for k in range(3):
+        d.degree[k] = int(spec.degree[k])
+        d.knots[k] = keep.f64(spec.knots[k])
+        d.lo[k] = float(spec.lo[k])
+        d.hi[k] = float(spec.hi[k])
+    d.n_ctrl[0], d.n_ctrl[1], d.n_ctrl[2] = nx, ny, nz
+    d.ctrl = keep.f64(ctrl.reshape(-1))
+    d.store = int(store)
+    return d, keep
+
+
+def camera_struct(cam) -> Camera:
+    c = Camera()
+    c.kind = MFA_CAMERA_ORTHO if cam.kind == "ortho" else MFA_CAMERA_PERSP
+    c.width, c.height = int(cam.width), int(cam.height)
+    for k in range(3):
+        c.eye[k] = float(cam.eye[k])
+        c.target[k] = float(cam.target[k])
+        c.up[k] = float(cam.up[k])
+    c.fov_y_deg = float(cam.fov_y_deg)
+    c.ortho_half_w = float(cam.ortho_half_w)
+    c.ortho_half_h = float(cam.ortho_half_h)
+    return c
+
+
+def tf_struct(tf, keep: _Keep | None = None) -> tuple:
+    keep = keep or _Keep()
+    t = TF()
+    table = np.asarray(tf.table, dtype=np.float32)
+    t.n = int(table.shape[0])
+    t.rgba = keep.f32(table.reshape(-1))
+    t.v_lo = float(tf.v_lo)
+    t.v_hi = float(tf.v_hi)
+    return t, keep
+
+
+def params_struct(p) -> RenderParams:
+    r = RenderParams()
+    r.step = float(p.step)
+    r.ert_alpha = float(p.ert_alpha)
+    r.shading = int(bool(p.shading))
+    r.shininess = int(p.shininess)
+    r.headlight = int(bool(p.headlight))
+    r.ka, r.kd, r.ks = float(p.ka), float(p.kd), float(p.ks)
+    for k in range(3):
+        r.light_dir[k] = float(p.light_dir[k])
+    return r
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+
+def mfa_version() -> str:
+    return lib.mfa_version().decode()
+
+
+def mfa_create(device: int = 0) -> int:
+    ctx = C.c_void_p()
+    _check(lib.mfa_create(int(device), C.byref(ctx)))
+    return ctx.value
+
+
+def mfa_destroy(ctx: int) -> None:
+    _check(lib.mfa_destroy(ctx))
+
+
+def mfa_set_memory_budget(ctx: int, nbytes: int) -> None:
+    _check(lib.mfa_set_memory_budget(ctx, int(nbytes)))
+
+
+def mfa_validate_model(spec, store: int = MFA_STORE_F32) -> None:
+    d, keep = model_desc(spec, store)
+    _check(lib.mfa_validate_model(C.byref(d)))
+
+
+def mfa_validate_render(camera, tf, params) -> None:
+    t, keep = tf_struct(tf)
+    _check(lib.mfa_validate_render(C.byref(camera_struct(camera)), C.byref(t),
+                                   C.byref(params_struct(params))))
+
+
+def mfa_model_upload(ctx: int, spec, store: int = MFA_STORE_F32) -> int:
+    d, keep = model_desc(spec, store)
+    h = C.c_int64()
+    _check(lib.mfa_model_upload(ctx, C.byref(d), C.byref(h)))
+    return h.value
+
+
+def mfa_model_free(ctx: int, model: int) -> None:
+    _check(lib.mfa_model_free(ctx, int(model)))
+
+
+def mfa_model_bytes(ctx: int, model: int) -> int:
+    b = C.c_int64()
+    _check(lib.mfa_model_bytes(ctx, int(model), C.byref(b)))
+    return b.value
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _dev_tensor(t, dtype, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {tuple(shape)}")
+    return t.data_ptr()
+
+
+def mfa_render(ctx: int, model: int, camera, tf, params, rgba, samples=None, stream=None) -> None:
+    """Render into ``rgba`` (H, W, 4) float32; ``samples`` an int64 tensor of
+    one element or None."""
+    import torch
+    out = _dev_tensor(rgba, torch.float32, (camera.height, camera.width, 4), "rgba")
+    sp = None
+    if samples is not None:
+        sp = _dev_tensor(samples, torch.int64, (1,), "samples")
+    t, keep = tf_struct(tf)
+    _check(lib.mfa_render(ctx, int(model), C.byref(camera_struct(camera)), C.byref(t),
+                          C.byref(params_struct(params)), out, sp, _stream_ptr(stream)))
+
+
+def mfa_eval_points(ctx: int, model: int, xyz, value, grad=None, stream=None) -> None:
+    """Value (n,) and world gradient (n, 3) float32 at world points xyz (n, 3) float64."""
+    import torch
+    n = int(xyz.shape[0])
+    px = _dev_tensor(xyz, torch.float64, (n, 3), "xyz")
+    pv = _dev_tensor(value, torch.float32, (n,), "value")
+    pg = None if grad is None else _dev_tensor(grad, torch.float32, (n, 3), "grad")
+    _check(lib.mfa_eval_points(ctx, int(model), n, px, pv, pg, _stream_ptr(stream)))

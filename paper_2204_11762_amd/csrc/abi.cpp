@@ -1,0 +1,646 @@
+// C ABI of the MFA ray-casting library: argument validation, model
+// preparation and residency, transfer-function staging and kernel launches.
+// The arithmetic of rendering lives in kernels.hip; this file only checks,
+// converts and moves data, and fills the launch records.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "mfa_dev.h"
+#include "mfa_dvr.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mfa_status fail(mfa_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+std::string hip_msg(const char* what, hipError_t e) {
+  return std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+}
+
+constexpr int64_t kMaxCtrlBytes = (int64_t(1) << 31) - 1;
+constexpr int64_t kMaxCount = int64_t(1) << 24;  // control points per axis
+constexpr int kCtrlPadElems = 16;                // zero padding after the control points
+constexpr int64_t kMaxPixels = int64_t(1) << 26;
+constexpr int kMaxImageSide = 1 << 15;
+constexpr int64_t kMaxEvalPoints = int64_t(1) << 38;
+constexpr size_t kMaxCachedTF = 64;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// --------------------------------------------------------------------------
+// validation (host only)
+// --------------------------------------------------------------------------
+
+mfa_status check_axis(const mfa_model_desc* d, int k, std::string& msg) {
+  const int p = d->degree[k];
+  const int64_t n = d->n_ctrl[k];
+  const char ax = "xyz"[k];
+  if (p < 1 || p > MFA_MAX_DEGREE) {
+    msg = std::string("degree of axis ") + ax + " must be in [1, 4]";
+    return MFA_ERR_MODEL;
+  }
+  if (n < p + 1 || n > kMaxCount) {
+    msg = std::string("axis ") + ax + ": need p+1 <= n <= 2^24 control points";
+    return MFA_ERR_MODEL;
+  }
+  const double* U = d->knots[k];
+  if (U == nullptr) {
+    msg = std::string("axis ") + ax + ": null knot vector";
+    return MFA_ERR_MODEL;
+  }
+  const int64_t m = n + p + 1;
+  for (int64_t i = 0; i < m; ++i) {
+    if (!std::isfinite(U[i])) {
+      msg = std::string("axis ") + ax + ": non-finite knot";
+      return MFA_ERR_MODEL;
+    }
+    if (i > 0 && U[i] < U[i - 1]) {
+      msg = std::string("axis ") + ax + ": knots must be non-decreasing";
+      return MFA_ERR_MODEL;
+    }
+  }
+  for (int i = 0; i <= p; ++i) {
+    if (U[i] != 0.0 || U[n + i] != 1.0) {
+      msg = std::string("axis ") + ax + ": knot vector must be clamped to [0, 1] (p+1 zeros, p+1 ones)";
+      return MFA_ERR_MODEL;
+    }
+  }
+  int64_t run = 0;
+  for (int64_t i = p + 1; i < n; ++i) {
+    if (!(U[i] > 0.0 && U[i] < 1.0)) {
+      msg = std::string("axis ") + ax + ": interior knots must lie in (0, 1)";
+      return MFA_ERR_MODEL;
+    }
+    run = (i > p + 1 && U[i] == U[i - 1]) ? run + 1 : 1;
+    if (run > p) {
+      msg = std::string("axis ") + ax + ": interior knot multiplicity exceeds the degree";
+      return MFA_ERR_MODEL;
+    }
+  }
+  if (!(std::isfinite(d->lo[k]) && std::isfinite(d->hi[k]) && d->lo[k] < d->hi[k])) {
+    msg = std::string("axis ") + ax + ": need finite lo < hi";
+    return MFA_ERR_MODEL;
+  }
+  return MFA_OK;
+}
+
+mfa_status validate_model(const mfa_model_desc* d, std::string& msg) {
+  if (d == nullptr) {
+    msg = "null model descriptor";
+    return MFA_ERR_INVALID;
+  }
+  if (d->store != MFA_STORE_F32 && d->store != MFA_STORE_BF16) {
+    msg = "unknown storage precision";
+    return MFA_ERR_MODEL;
+  }
+  for (int k = 0; k < 3; ++k) {
+    const mfa_status st = check_axis(d, k, msg);
+    if (st != MFA_OK) return st;
+  }
+  if (d->ctrl == nullptr) {
+    msg = "null control points";
+    return MFA_ERR_MODEL;
+  }
+  const int64_t nx = d->n_ctrl[0], ny = d->n_ctrl[1], nz = d->n_ctrl[2];
+  const int64_t elem = d->store == MFA_STORE_F32 ? 4 : 2;
+  const int pmax = std::max(d->degree[0], std::max(d->degree[1], d->degree[2]));
+  // every element index a row load can form, including the zero-weight
+  // rows of a lower-degree axis, must stay addressable with 32-bit offsets
+  const double reach = double(nx) * double(ny) * double(nz) +
+                       double(pmax) * (double(nx) * double(ny) + double(nx) + 1.0) +
+                       double(kCtrlPadElems);
+  if (reach * double(elem) > double(kMaxCtrlBytes)) {
+    msg = "model too large: control points must fit in 2^31 bytes";
+    return MFA_ERR_INVALID;
+  }
+  const int64_t total = nx * ny * nz;
+  for (int64_t i = 0; i < total; ++i) {
+    const double v = d->ctrl[i];
+    if (!std::isfinite(v) || !std::isfinite(float(v))) {
+      msg = "control points must be finite and within FP32 range";
+      return MFA_ERR_MODEL;
+    }
+  }
+  return MFA_OK;
+}
+
+bool finite3(const double* v) {
+  return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+struct Frame {
+  double F[3], R[3], V[3];
+};
+
+// F = unit(target - eye), R = unit(F x up), V = R x F.  Each unit vector is
+// x / sqrt(x.x) with the dot product summed left to right.
+bool camera_frame(const mfa_camera* c, Frame& fr) {
+  double f[3] = {c->target[0] - c->eye[0], c->target[1] - c->eye[1], c->target[2] - c->eye[2]};
+  const double lf = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  if (!(lf > 0.0) || !std::isfinite(lf)) return false;
+  for (int k = 0; k < 3; ++k) fr.F[k] = f[k] / lf;
+  const double* u = c->up;
+  const double r[3] = {fr.F[1] * u[2] - fr.F[2] * u[1], fr.F[2] * u[0] - fr.F[0] * u[2],
+                       fr.F[0] * u[1] - fr.F[1] * u[0]};
+  const double lr = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  if (!(lr > 0.0) || !std::isfinite(lr)) return false;
+  for (int k = 0; k < 3; ++k) fr.R[k] = r[k] / lr;
+  fr.V[0] = fr.R[1] * fr.F[2] - fr.R[2] * fr.F[1];
+  fr.V[1] = fr.R[2] * fr.F[0] - fr.R[0] * fr.F[2];
+  fr.V[2] = fr.R[0] * fr.F[1] - fr.R[1] * fr.F[0];
+  return true;
+}
+
+mfa_status validate_render(const mfa_camera* c, const mfa_tf* tf, const mfa_render_params* p,
+                           std::string& msg) {
+  if (c == nullptr || tf == nullptr || p == nullptr) {
+    msg = "null camera, transfer function or parameters";
+    return MFA_ERR_INVALID;
+  }
+  if (c->kind != MFA_CAMERA_ORTHO && c->kind != MFA_CAMERA_PERSP) {
+    msg = "unknown camera kind";
+    return MFA_ERR_INVALID;
+  }
+  if (c->width < 1 || c->height < 1 || c->width > kMaxImageSide || c->height > kMaxImageSide ||
+      int64_t(c->width) * int64_t(c->height) > kMaxPixels) {
+    msg = "image size must be positive, at most 32768 per side and 2^26 pixels";
+    return MFA_ERR_INVALID;
+  }
+  if (!finite3(c->eye) || !finite3(c->target) || !finite3(c->up)) {
+    msg = "camera vectors must be finite";
+    return MFA_ERR_INVALID;
+  }
+  Frame fr;
+  if (!camera_frame(c, fr)) {
+    msg = "degenerate camera (eye == target or up parallel to the view axis)";
+    return MFA_ERR_INVALID;
+  }
+  if (c->kind == MFA_CAMERA_PERSP) {
+    if (!(c->fov_y_deg > 0.0 && c->fov_y_deg < 180.0)) {
+      msg = "perspective field of view must be in (0, 180) degrees";
+      return MFA_ERR_INVALID;
+    }
+  } else if (!(c->ortho_half_w > 0.0 && c->ortho_half_h > 0.0 && std::isfinite(c->ortho_half_w) &&
+               std::isfinite(c->ortho_half_h))) {
+    msg = "orthographic half extents must be positive";
+    return MFA_ERR_INVALID;
+  }
+  if (tf->n < 2 || tf->n > MFA_MAX_TF || tf->rgba == nullptr) {
+    msg = "transfer function needs 2..4096 entries";
+    return MFA_ERR_INVALID;
+  }
+  if (!(std::isfinite(tf->v_lo) && std::isfinite(tf->v_hi) && tf->v_lo < tf->v_hi)) {
+    msg = "transfer function range needs finite v_lo < v_hi";
+    return MFA_ERR_INVALID;
+  }
+  for (int i = 0; i < 4 * tf->n; ++i) {
+    if (!std::isfinite(tf->rgba[i])) {
+      msg = "transfer function entries must be finite";
+      return MFA_ERR_INVALID;
+    }
+  }
+  if (!(p->step > 0.0) || !std::isfinite(p->step)) {
+    msg = "step must be positive";
+    return MFA_ERR_INVALID;
+  }
+  if (!std::isfinite(p->ert_alpha)) {
+    msg = "ert_alpha must be finite";
+    return MFA_ERR_INVALID;
+  }
+  if ((p->shading != 0 && p->shading != 1) || (p->headlight != 0 && p->headlight != 1)) {
+    msg = "shading and headlight must be 0 or 1";
+    return MFA_ERR_INVALID;
+  }
+  if (p->shininess < 0 || p->shininess > 256) {
+    msg = "shininess must be in [0, 256]";
+    return MFA_ERR_INVALID;
+  }
+  if (!std::isfinite(p->ka) || !std::isfinite(p->kd) || !std::isfinite(p->ks)) {
+    msg = "lighting coefficients must be finite";
+    return MFA_ERR_INVALID;
+  }
+  if (!p->headlight) {
+    const double* l = p->light_dir;
+    if (!finite3(l) || !(l[0] * l[0] + l[1] * l[1] + l[2] * l[2] > 0.0)) {
+      msg = "light direction must be finite and non-zero";
+      return MFA_ERR_INVALID;
+    }
+  }
+  return MFA_OK;
+}
+
+// --------------------------------------------------------------------------
+// model preparation
+// --------------------------------------------------------------------------
+
+uint16_t to_bf16(double x) {
+  const float f = float(x);  // round to nearest even
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even on the upper half
+  return uint16_t(u >> 16);
+}
+
+// Per-span table rows (layout in mfa_dev.h), computed in FP64 and rounded
+// once to FP32.  Empty spans (never located) get zero rows.
+void build_table(const double* U, int64_t n, int p, float* out) {
+  const int S = mfa::table_stride(p);
+  for (int64_t s = p; s < n; ++s) {
+    float* row = out + (s - p) * S;
+    std::memset(row, 0, sizeof(float) * S);
+    if (!(U[s] < U[s + 1])) continue;
+    for (int j = 2; j <= p; ++j) row[mfa::table_dl(p, j)] = float(U[s] - U[s + 1 - j]);
+    for (int j = 1; j <= p; ++j) row[mfa::table_dr(p, j)] = float(U[s + j] - U[s]);
+    for (int q = 1; q <= p; ++q)
+      for (int r = 0; r < q; ++r)
+        row[mfa::table_inv(p, q, r)] = float(1.0 / (U[s + r + 1] - U[s + 1 - q + r]));
+  }
+}
+
+struct DeviceModel {
+  void* mem = nullptr;
+  int64_t bytes = 0;
+  mfa::ModelDev md{};
+  double lo[3], hi[3];
+};
+
+struct TFEntry {
+  std::vector<float> host;
+  float4* dev = nullptr;
+};
+
+uint64_t fnv1a(const void* p, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    ok_ = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev_ >= 0) (void)hipSetDevice(prev_);
+  }
+  bool ok() const { return ok_; }
+
+ private:
+  int prev_ = -1;
+  bool ok_ = false;
+};
+
+}  // namespace
+
+struct mfa_ctx {
+  int device = 0;
+  int64_t budget = 0;
+  int64_t used = 0;
+  int64_t next_id = 1;
+  std::unordered_map<int64_t, DeviceModel> models;
+  std::unordered_map<uint64_t, std::vector<TFEntry>> tfs;
+  size_t n_tf = 0;
+
+  void free_tfs() {
+    for (auto& kv : tfs)
+      for (auto& e : kv.second) (void)hipFree(e.dev);
+    tfs.clear();
+    n_tf = 0;
+  }
+};
+
+namespace {
+
+// Device copy of a transfer-function table, cached by content.  Entries are
+// never modified; when the cache is full the device is synchronised before
+// the old entries are released.
+mfa_status tf_device(mfa_ctx* ctx, const mfa_tf* tf, float4** out) {
+  const size_t nfl = size_t(tf->n) * 4;
+  const uint64_t h = fnv1a(tf->rgba, nfl * sizeof(float));
+  auto it = ctx->tfs.find(h);
+  if (it != ctx->tfs.end()) {
+    for (auto& e : it->second) {
+      if (e.host.size() == nfl && std::memcmp(e.host.data(), tf->rgba, nfl * sizeof(float)) == 0) {
+        *out = e.dev;
+        return MFA_OK;
+      }
+    }
+  }
+  if (ctx->n_tf >= kMaxCachedTF) {
+    const hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("hipDeviceSynchronize", e));
+    ctx->free_tfs();
+  }
+  TFEntry ent;
+  ent.host.assign(tf->rgba, tf->rgba + nfl);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&ent.dev), nfl * sizeof(float));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MFA_ERR_NOMEM, hip_msg("hipMalloc (transfer function)", e));
+  }
+  e = hipMemcpy(ent.dev, ent.host.data(), nfl * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(ent.dev);
+    return fail(MFA_ERR_DEVICE, hip_msg("hipMemcpy (transfer function)", e));
+  }
+  *out = ent.dev;
+  ctx->tfs[h].push_back(std::move(ent));
+  ctx->n_tf += 1;
+  return MFA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mfa_last_error(void) { return g_last_error.c_str(); }
+
+const char* mfa_version(void) { return "mfa-dvr-gfx950 0.1"; }
+
+mfa_status mfa_validate_model(const mfa_model_desc* desc) {
+  g_last_error.clear();
+  std::string msg;
+  const mfa_status st = validate_model(desc, msg);
+  if (st != MFA_OK) return fail(st, msg);
+  return MFA_OK;
+}
+
+mfa_status mfa_validate_render(const mfa_camera* camera, const mfa_tf* tf,
+                               const mfa_render_params* params) {
+  g_last_error.clear();
+  std::string msg;
+  const mfa_status st = validate_render(camera, tf, params, msg);
+  if (st != MFA_OK) return fail(st, msg);
+  return MFA_OK;
+}
+
+mfa_status mfa_create(int32_t device, mfa_ctx** ctx_out) {
+  g_last_error.clear();
+  if (ctx_out == nullptr) return fail(MFA_ERR_INVALID, "null ctx_out");
+  int count = 0;
+  const hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("hipGetDeviceCount", e));
+  if (device < 0 || device >= count) return fail(MFA_ERR_DEVICE, "no such HIP device");
+  DeviceGuard g(device);
+  if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
+  mfa_ctx* ctx = new mfa_ctx();
+  ctx->device = device;
+  *ctx_out = ctx;
+  return MFA_OK;
+}
+
+mfa_status mfa_destroy(mfa_ctx* ctx) {
+  g_last_error.clear();
+  if (ctx == nullptr) return MFA_OK;
+  mfa_status st = MFA_OK;
+  {
+    DeviceGuard g(ctx->device);
+    const hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) st = fail(MFA_ERR_DEVICE, hip_msg("hipDeviceSynchronize", e));
+    for (auto& kv : ctx->models) (void)hipFree(kv.second.mem);
+    ctx->models.clear();
+    ctx->free_tfs();
+  }
+  delete ctx;
+  return st;
+}
+
+mfa_status mfa_set_memory_budget(mfa_ctx* ctx, int64_t bytes) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  if (bytes < 0) return fail(MFA_ERR_INVALID, "negative budget");
+  ctx->budget = bytes;
+  return MFA_OK;
+}
+
+mfa_status mfa_model_upload(mfa_ctx* ctx, const mfa_model_desc* d, int64_t* model_out) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  if (model_out == nullptr) return fail(MFA_ERR_INVALID, "null model_out");
+  std::string msg;
+  const mfa_status st = validate_model(d, msg);
+  if (st != MFA_OK) return fail(st, msg);
+
+  const int64_t n[3] = {d->n_ctrl[0], d->n_ctrl[1], d->n_ctrl[2]};
+  const int64_t total = n[0] * n[1] * n[2];
+  const size_t elem = d->store == MFA_STORE_F32 ? 4 : 2;
+  size_t off_knots[3], off_tab[3], off = 0;
+  for (int k = 0; k < 3; ++k) {
+    off_knots[k] = off;
+    off = align256(off + sizeof(double) * size_t(n[k] + d->degree[k] + 1));
+  }
+  for (int k = 0; k < 3; ++k) {
+    off_tab[k] = off;
+    off = align256(off + sizeof(float) * size_t(n[k] - d->degree[k]) *
+                             size_t(mfa::table_stride(d->degree[k])));
+  }
+  const size_t off_ctrl = off;
+  const size_t ctrl_bytes = elem * size_t(total + kCtrlPadElems);
+  const size_t bytes = align256(off_ctrl + ctrl_bytes);
+
+  if (ctx->budget > 0 && ctx->used + int64_t(bytes) > ctx->budget)
+    return fail(MFA_ERR_NOMEM, "model exceeds the context's memory budget");
+
+  std::vector<unsigned char> host(bytes, 0);
+  for (int k = 0; k < 3; ++k) {
+    std::memcpy(host.data() + off_knots[k], d->knots[k],
+                sizeof(double) * size_t(n[k] + d->degree[k] + 1));
+    build_table(d->knots[k], n[k], d->degree[k],
+                reinterpret_cast<float*>(host.data() + off_tab[k]));
+  }
+  if (d->store == MFA_STORE_F32) {
+    float* c = reinterpret_cast<float*>(host.data() + off_ctrl);
+    for (int64_t i = 0; i < total; ++i) c[i] = float(d->ctrl[i]);
+  } else {
+    uint16_t* c = reinterpret_cast<uint16_t*>(host.data() + off_ctrl);
+    for (int64_t i = 0; i < total; ++i) c[i] = to_bf16(d->ctrl[i]);
+  }
+
+  DeviceGuard g(ctx->device);
+  if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
+  void* mem = nullptr;
+  hipError_t e = hipMalloc(&mem, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MFA_ERR_NOMEM, hip_msg("hipMalloc (model)", e));
+  }
+  e = hipMemcpy(mem, host.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(mem);
+    return fail(MFA_ERR_DEVICE, hip_msg("hipMemcpy (model)", e));
+  }
+
+  DeviceModel dm;
+  dm.mem = mem;
+  dm.bytes = int64_t(bytes);
+  unsigned char* base = static_cast<unsigned char*>(mem);
+  int pmax = 0;
+  for (int k = 0; k < 3; ++k) {
+    mfa::AxisDev& A = dm.md.ax[k];
+    A.knots = reinterpret_cast<const double*>(base + off_knots[k]);
+    A.tab = reinterpret_cast<const float*>(base + off_tab[k]);
+    A.n = int32_t(n[k]);
+    A.p = d->degree[k];
+    A.lo = d->lo[k];
+    A.inv_ext = 1.0 / (d->hi[k] - d->lo[k]);
+    A.gscale = float(1.0 / (d->hi[k] - d->lo[k]));
+    dm.lo[k] = d->lo[k];
+    dm.hi[k] = d->hi[k];
+    pmax = std::max(pmax, int(A.p));
+  }
+  dm.md.ctrl = base + off_ctrl;
+  dm.md.ctrl_bytes = uint32_t(ctrl_bytes);
+  dm.md.store = d->store;
+  dm.md.nx = int32_t(n[0]);
+  dm.md.nxy = int32_t(n[0] * n[1]);
+  dm.md.pmax = pmax;
+
+  const int64_t id = ctx->next_id++;
+  ctx->models.emplace(id, dm);
+  ctx->used += dm.bytes;
+  *model_out = id;
+  return MFA_OK;
+}
+
+mfa_status mfa_model_free(mfa_ctx* ctx, int64_t model) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  auto it = ctx->models.find(model);
+  if (it == ctx->models.end()) return fail(MFA_ERR_HANDLE, "unknown model handle");
+  DeviceGuard g(ctx->device);
+  const hipError_t e = hipDeviceSynchronize();
+  (void)hipFree(it->second.mem);
+  ctx->used -= it->second.bytes;
+  ctx->models.erase(it);
+  if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("hipDeviceSynchronize", e));
+  return MFA_OK;
+}
+
+mfa_status mfa_model_bytes(mfa_ctx* ctx, int64_t model, int64_t* bytes_out) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  if (bytes_out == nullptr) return fail(MFA_ERR_INVALID, "null bytes_out");
+  auto it = ctx->models.find(model);
+  if (it == ctx->models.end()) return fail(MFA_ERR_HANDLE, "unknown model handle");
+  *bytes_out = it->second.bytes;
+  return MFA_OK;
+}
+
+mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const mfa_tf* tf,
+                      const mfa_render_params* prm, float* rgba_dev, int64_t* samples_dev,
+                      void* stream) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  auto it = ctx->models.find(model);
+  if (it == ctx->models.end()) return fail(MFA_ERR_HANDLE, "unknown model handle");
+  std::string msg;
+  mfa_status st = validate_render(cam, tf, prm, msg);
+  if (st != MFA_OK) return fail(st, msg);
+  if (rgba_dev == nullptr) return fail(MFA_ERR_INVALID, "null rgba_dev");
+  const DeviceModel& dm = it->second;
+  double diag2 = 0.0;
+  for (int k = 0; k < 3; ++k) diag2 += (dm.hi[k] - dm.lo[k]) * (dm.hi[k] - dm.lo[k]);
+  if (std::sqrt(diag2) / prm->step > double(mfa::kMaxSamplesPerRay))
+    return fail(MFA_ERR_INVALID, "step too small: more than 65536 samples per ray");
+
+  Frame fr;
+  camera_frame(cam, fr);
+
+  DeviceGuard g(ctx->device);
+  if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
+  float4* tf_dev = nullptr;
+  st = tf_device(ctx, tf, &tf_dev);
+  if (st != MFA_OK) return st;
+
+  mfa::RenderArgsDev a{};
+  a.m = dm.md;
+  a.kind = cam->kind;
+  a.width = cam->width;
+  a.height = cam->height;
+  a.ntf = tf->n;
+  for (int k = 0; k < 3; ++k) {
+    a.eye[k] = cam->eye[k];
+    a.F[k] = fr.F[k];
+    a.R[k] = fr.R[k];
+    a.V[k] = fr.V[k];
+    a.lo[k] = dm.lo[k];
+    a.hi[k] = dm.hi[k];
+  }
+  if (cam->kind == MFA_CAMERA_ORTHO) {
+    a.cam0 = cam->ortho_half_w;
+    a.cam1 = cam->ortho_half_h;
+  } else {
+    const double half = cam->fov_y_deg * (M_PI / 180.0) * 0.5;
+    a.cam0 = std::tan(half);
+    a.cam1 = double(cam->width) / double(cam->height);
+  }
+  a.step = prm->step;
+  a.tf = tf_dev;
+  a.tf_lo = float(tf->v_lo);
+  a.tf_scale = float(1.0 / (tf->v_hi - tf->v_lo));
+  a.ert = float(prm->ert_alpha);
+  a.shading = prm->shading;
+  a.shininess = prm->shininess;
+  a.ka = float(prm->ka);
+  a.kd = float(prm->kd);
+  a.ks = float(prm->ks);
+  if (prm->headlight) {
+    for (int k = 0; k < 3; ++k) a.light[k] = float(-fr.F[k]);
+  } else {
+    const double* l = prm->light_dir;
+    const double ll = std::sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]);
+    for (int k = 0; k < 3; ++k) a.light[k] = float(l[k] / ll);
+  }
+  a.out = rgba_dev;
+  a.samples = reinterpret_cast<unsigned long long*>(samples_dev);
+  const hipError_t e = mfa::launch_render(a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("render launch", e));
+  return MFA_OK;
+}
+
+mfa_status mfa_eval_points(mfa_ctx* ctx, int64_t model, int64_t n, const double* xyz_dev,
+                           float* value_dev, float* grad_dev, void* stream) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  auto it = ctx->models.find(model);
+  if (it == ctx->models.end()) return fail(MFA_ERR_HANDLE, "unknown model handle");
+  if (n < 0 || n > kMaxEvalPoints) return fail(MFA_ERR_INVALID, "point count out of range");
+  if (n == 0) return MFA_OK;
+  if (xyz_dev == nullptr || value_dev == nullptr)
+    return fail(MFA_ERR_INVALID, "null point or value buffer");
+  const DeviceModel& dm = it->second;
+  DeviceGuard g(ctx->device);
+  if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
+  mfa::EvalArgsDev a{};
+  a.m = dm.md;
+  for (int k = 0; k < 3; ++k) {
+    a.lo[k] = dm.lo[k];
+    a.hi[k] = dm.hi[k];
+  }
+  a.xyz = xyz_dev;
+  a.value = value_dev;
+  a.grad = grad_dev;
+  a.n = n;
+  const hipError_t e = mfa::launch_eval(a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("eval launch", e));
+  return MFA_OK;
+}
+
+}  // extern "C"

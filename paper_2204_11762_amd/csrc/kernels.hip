@@ -1,0 +1,547 @@
+// HIP kernels for gfx950 (CDNA4): MFA value/gradient queries and the fused
+// MFA ray caster.
+//
+// Per sample (Sect. 3.1, Algorithm 1) a lane
+//   1. forms the sample position in FP64 and normalises it to [0,1]^3,
+//   2. locates the knot span on each axis (exact FP64 comparisons: a
+//      bisection for the first sample of a ray, then a walk, since each
+//      coordinate is monotone along a ray),
+//   3. evaluates the p+1 non-zero B-spline basis functions and their first
+//      derivatives per axis (Cox--de Boor triangle, FP32, reciprocals of
+//      the knot differences read from a per-span table),
+//   4. gathers the (p+1)^3 control-point block as (p+1)^2 rows of p+1
+//      consecutive x values (one bounds-checked buffer load per row) and
+//      contracts it sum-factorised: x first (value and d/dx weights), then
+//      y, then z, giving the value and all three derivatives at once,
+//   5. looks up the RGBA transfer function, applies Phong shading from the
+//      analytic gradient, composites front to back and stops the ray once
+//      the accumulated opacity exceeds the limit.
+// One lane owns one ray; a 256-thread workgroup owns a 16x16 pixel tile,
+// each wave an 8x8 sub-tile, so that the rays of a wave gather from
+// neighbouring control points and share cache lines.
+//
+// Mixed per-axis degrees run in the kernel of the largest degree P: an axis
+// of degree q < P uses the window of P+1 control points that starts at its
+// first non-zero function, with zero weights in the last P-q positions.
+// The control-point buffer is padded with zeros, so every row load of the
+// window stays inside the allocation.
+
+#include <hip/hip_runtime.h>
+
+#include "mfa_dev.h"
+
+namespace mfa {
+namespace {
+
+constexpr uint32_t kRsrcWord3 = 0x00020000u;  // raw buffer, 32-bit data format (gfx9)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           (int)kRsrcWord3);
+}
+
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+// Row of P+1 consecutive control points along x, starting at element e >= 0.
+template <int P, int STORE>
+__device__ __forceinline__ void load_row(__amdgpu_buffer_rsrc_t rs, int e, float (&r)[P + 1]) {
+  if constexpr (STORE == 0) {
+    const uint32_t off = (uint32_t)e * 4u;
+    if constexpr (P == 1) {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+      r[0] = __uint_as_float(v[0]);
+      r[1] = __uint_as_float(v[1]);
+    } else if constexpr (P == 2) {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0);
+      r[0] = __uint_as_float(v[0]);
+      r[1] = __uint_as_float(v[1]);
+      r[2] = __uint_as_float(v[2]);
+    } else if constexpr (P == 3) {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+      r[0] = __uint_as_float(v[0]);
+      r[1] = __uint_as_float(v[1]);
+      r[2] = __uint_as_float(v[2]);
+      r[3] = __uint_as_float(v[3]);
+    } else {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+      const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 16u, 0, 0);
+      r[0] = __uint_as_float(v[0]);
+      r[1] = __uint_as_float(v[1]);
+      r[2] = __uint_as_float(v[2]);
+      r[3] = __uint_as_float(v[3]);
+      r[4] = __uint_as_float(w);
+    }
+  } else {
+    // BF16: read whole aligned dwords and realign by 16 bits for odd e.
+    const uint32_t off = (uint32_t)(e >> 1) * 4u;
+    const uint32_t sh = (uint32_t)(e & 1) * 16u;
+    if constexpr (P == 1) {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+      const uint32_t w0 = __builtin_amdgcn_alignbit(v[1], v[0], sh);
+      r[0] = bf16_lo(w0);
+      r[1] = bf16_hi(w0);
+    } else if constexpr (P == 2) {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+      const uint32_t w0 = __builtin_amdgcn_alignbit(v[1], v[0], sh);
+      const uint32_t w1 = __builtin_amdgcn_alignbit(v[1], v[1], sh);
+      r[0] = bf16_lo(w0);
+      r[1] = bf16_hi(w0);
+      r[2] = bf16_lo(w1);
+    } else if constexpr (P == 3) {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0);
+      const uint32_t w0 = __builtin_amdgcn_alignbit(v[1], v[0], sh);
+      const uint32_t w1 = __builtin_amdgcn_alignbit(v[2], v[1], sh);
+      r[0] = bf16_lo(w0);
+      r[1] = bf16_hi(w0);
+      r[2] = bf16_lo(w1);
+      r[3] = bf16_hi(w1);
+    } else {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0);
+      const uint32_t w0 = __builtin_amdgcn_alignbit(v[1], v[0], sh);
+      const uint32_t w1 = __builtin_amdgcn_alignbit(v[2], v[1], sh);
+      const uint32_t w2 = __builtin_amdgcn_alignbit(v[2], v[2], sh);
+      r[0] = bf16_lo(w0);
+      r[1] = bf16_hi(w0);
+      r[2] = bf16_lo(w1);
+      r[3] = bf16_hi(w1);
+      r[4] = bf16_lo(w2);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// knot spans (exact FP64 comparisons)
+// ---------------------------------------------------------------------------
+
+// Largest s in [p, n-1] with U[s] <= u (u in [0,1]); u = 1 gives n-1.
+__device__ __forceinline__ int span_search(const double* __restrict__ U, int n, int p, double u) {
+  if (u >= U[n]) return n - 1;
+  int lo = p, hi = n;  // U[lo] <= u < U[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (U[mid] <= u)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Same result, starting from a nearby span s.
+__device__ __forceinline__ int span_walk(const double* __restrict__ U, int n, int p, double u,
+                                         int s) {
+  while (s < n - 1 && U[s + 1] <= u) ++s;
+  while (s > p && U[s] > u) --s;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// basis functions of one axis
+// ---------------------------------------------------------------------------
+
+// Degree-Q basis N[0..Q] = N_{s-Q..s,Q}(u) and parametric derivatives
+// dN[0..Q], from d = u - U_s and the span's table row.  The triangle raises
+// the degree one step at a time; at the last step the scaled lower-degree
+// values tmp_r = N_{s-Q+1+r,Q-1} / (U_{s+r+1} - U_{s+1-Q+r}) give the
+// derivative N'_{s-Q+r,Q} = Q (tmp_{r-1} - tmp_r).
+template <int Q>
+__device__ __forceinline__ void basis_deg(const float* __restrict__ row, float d, float* N,
+                                          float* dN) {
+  constexpr int S = table_stride(Q);
+  float t[S];
+  const float4* r4 = reinterpret_cast<const float4*>(row);
+#pragma unroll
+  for (int i = 0; i < S / 4; ++i) {
+    const float4 v = r4[i];
+    t[4 * i + 0] = v.x;
+    t[4 * i + 1] = v.y;
+    t[4 * i + 2] = v.z;
+    t[4 * i + 3] = v.w;
+  }
+  float left[Q + 1], right[Q + 1];
+  left[1] = d;
+#pragma unroll
+  for (int j = 2; j <= Q; ++j) left[j] = d + t[table_dl(Q, j)];
+#pragma unroll
+  for (int j = 1; j <= Q; ++j) right[j] = t[table_dr(Q, j)] - d;
+  float T[Q];
+  N[0] = 1.0f;
+#pragma unroll
+  for (int q = 1; q <= Q; ++q) {
+    float saved = 0.0f;
+#pragma unroll
+    for (int r = 0; r < q; ++r) {
+      const float tmp = N[r] * t[table_inv(Q, q, r)];
+      N[r] = fmaf(right[r + 1], tmp, saved);
+      saved = left[q - r] * tmp;
+      if (q == Q) T[r] = tmp;
+    }
+    N[q] = saved;
+  }
+  constexpr float fq = (float)Q;
+  dN[0] = -fq * T[0];
+#pragma unroll
+  for (int r = 1; r < Q; ++r) dN[r] = fq * (T[r - 1] - T[r]);
+  dN[Q] = fq * T[Q - 1];
+}
+
+// Window of P+1 weights for an axis of runtime degree q <= P: entries
+// 0..q hold the non-zero functions, the rest are zero.
+template <int P>
+__device__ __forceinline__ void axis_basis(int q, const float* __restrict__ row, float d,
+                                           float (&N)[P + 1], float (&dN)[P + 1]) {
+  if (q == P) {
+    basis_deg<P>(row, d, N, dN);
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i <= P; ++i) {
+    N[i] = 0.0f;
+    dN[i] = 0.0f;
+  }
+  if constexpr (P >= 2) {
+    if (q == 1) basis_deg<1>(row, d, N, dN);
+  }
+  if constexpr (P >= 3) {
+    if (q == 2) basis_deg<2>(row, d, N, dN);
+  }
+  if constexpr (P >= 4) {
+    if (q == 3) basis_deg<3>(row, d, N, dN);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// value and gradient query
+// ---------------------------------------------------------------------------
+
+// Value f and world-space gradient g at parameters u (each in [0,1]).
+// span[] carries the spans between calls along one ray; first = true
+// locates them from scratch.
+template <int P, int STORE, bool GRAD>
+__device__ __forceinline__ void query(const ModelDev& m, __amdgpu_buffer_rsrc_t rs,
+                                      const double (&u)[3], int (&span)[3], bool first, float& f,
+                                      float (&g)[3]) {
+  float N[3][P + 1], dN[3][P + 1];
+  int w[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const AxisDev& A = m.ax[k];
+    const int s = first ? span_search(A.knots, A.n, A.p, u[k])
+                        : span_walk(A.knots, A.n, A.p, u[k], span[k]);
+    span[k] = s;
+    const float d = (float)(u[k] - A.knots[s]);
+    const float* row = A.tab + (size_t)(s - A.p) * (size_t)table_stride(A.p);
+    axis_basis<P>(A.p, row, d, N[k], dN[k]);
+    w[k] = s - A.p;
+  }
+  const int e0 = w[0] + m.nx * w[1] + m.nxy * w[2];
+
+  // x: value weights and d/dx weights for each of the (P+1)^2 rows
+  float a0[P + 1][P + 1], a1[P + 1][P + 1];
+#pragma unroll
+  for (int c = 0; c <= P; ++c) {
+#pragma unroll
+    for (int b = 0; b <= P; ++b) {
+      float row[P + 1];
+      load_row<P, STORE>(rs, e0 + b * m.nx + c * m.nxy, row);
+      float s0 = N[0][0] * row[0];
+      float s1 = dN[0][0] * row[0];
+#pragma unroll
+      for (int a = 1; a <= P; ++a) {
+        s0 = fmaf(N[0][a], row[a], s0);
+        if (GRAD) s1 = fmaf(dN[0][a], row[a], s1);
+      }
+      a0[c][b] = s0;
+      a1[c][b] = s1;
+    }
+  }
+  // y
+  float b0[P + 1], bx[P + 1], by[P + 1];
+#pragma unroll
+  for (int c = 0; c <= P; ++c) {
+    float s0 = N[1][0] * a0[c][0];
+    float sx = N[1][0] * a1[c][0];
+    float sy = dN[1][0] * a0[c][0];
+#pragma unroll
+    for (int b = 1; b <= P; ++b) {
+      s0 = fmaf(N[1][b], a0[c][b], s0);
+      if (GRAD) {
+        sx = fmaf(N[1][b], a1[c][b], sx);
+        sy = fmaf(dN[1][b], a0[c][b], sy);
+      }
+    }
+    b0[c] = s0;
+    bx[c] = sx;
+    by[c] = sy;
+  }
+  // z
+  float v = N[2][0] * b0[0];
+  float gx = N[2][0] * bx[0];
+  float gy = N[2][0] * by[0];
+  float gz = dN[2][0] * b0[0];
+#pragma unroll
+  for (int c = 1; c <= P; ++c) {
+    v = fmaf(N[2][c], b0[c], v);
+    if (GRAD) {
+      gx = fmaf(N[2][c], bx[c], gx);
+      gy = fmaf(N[2][c], by[c], gy);
+      gz = fmaf(dN[2][c], b0[c], gz);
+    }
+  }
+  f = v;
+  if (GRAD) {
+    g[0] = gx * m.ax[0].gscale;
+    g[1] = gy * m.ax[1].gscale;
+    g[2] = gz * m.ax[2].gscale;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// rays
+// ---------------------------------------------------------------------------
+
+struct Ray {
+  double o[3];
+  double d[3];
+  double t0;
+  int nr;  // samples on the ray (0 = miss)
+};
+
+// Ray through the centre of pixel (r, c) and its samples inside the box.
+// Plain FP64 operations in the stated order (no contraction), so that the
+// entry parameter and the sample count are the IEEE results of the
+// defining formulas.
+__device__ __forceinline__ Ray make_ray(const RenderArgsDev& a, int r, int c) {
+#pragma clang fp contract(off)
+  Ray ray;
+  const double W = (double)a.width;
+  const double H = (double)a.height;
+  const double ca = 2.0 * ((double)c + 0.5) / W - 1.0;
+  const double cb = 1.0 - 2.0 * ((double)r + 0.5) / H;
+  if (a.kind == 0) {
+    const double sa = ca * a.cam0;
+    const double sb = cb * a.cam1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ray.o[k] = a.eye[k] + sa * a.R[k] + sb * a.V[k];
+      ray.d[k] = a.F[k];
+    }
+  } else {
+    const double sa = ca * a.cam0 * a.cam1;
+    const double sb = cb * a.cam0;
+    double dv[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dv[k] = a.F[k] + sa * a.R[k] + sb * a.V[k];
+    const double len = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ray.o[k] = a.eye[k];
+      ray.d[k] = dv[k] / len;
+    }
+  }
+  double t0 = 0.0, t1 = __builtin_inf();
+  bool miss = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double dk = ray.d[k], ok = ray.o[k];
+    if (dk != 0.0) {
+      const double ta = (a.lo[k] - ok) / dk;
+      const double tb = (a.hi[k] - ok) / dk;
+      t0 = fmax(t0, fmin(ta, tb));
+      t1 = fmin(t1, fmax(ta, tb));
+    } else if (ok < a.lo[k] || ok > a.hi[k]) {
+      miss = true;
+    }
+  }
+  ray.t0 = t0;
+  ray.nr = 0;
+  if (!miss && t1 > t0) {
+    const double L = floor((t1 - t0) / a.step);
+    ray.nr = (int)fmin(L, (double)kMaxSamplesPerRay);
+  }
+  return ray;
+}
+
+// Parameters of sample s: u = clamp((o + t d - lo) / (hi - lo), 0, 1),
+// t = t0 + (s + 1/2) step, with the same unfused operations.
+__device__ __forceinline__ void sample_params(const RenderArgsDev& a, const Ray& ray, int s,
+                                              double (&u)[3]) {
+#pragma clang fp contract(off)
+  const double t = ray.t0 + ((double)s + 0.5) * a.step;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double x = ray.o[k] + t * ray.d[k];
+    const double v = (x - a.m.ax[k].lo) * a.m.ax[k].inv_ext;
+    u[k] = fmin(fmax(v, 0.0), 1.0);
+  }
+}
+
+__device__ __forceinline__ float ipowf(float x, int k) {
+  float r = 1.0f;
+  while (k) {
+    if (k & 1) r *= x;
+    x *= x;
+    k >>= 1;
+  }
+  return r;
+}
+
+template <int P, int STORE, bool SHADE>
+__global__ __launch_bounds__(256) void render_kernel(RenderArgsDev a) {
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
+  const int py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
+  const bool inside = px < a.width && py < a.height;
+  int count = 0;
+  if (inside) {
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.m.ctrl, a.m.ctrl_bytes);
+    const Ray ray = make_ray(a, py, px);
+    float cr = 0.0f, cg = 0.0f, cb = 0.0f, A = 0.0f;
+    const float vx = -(float)ray.d[0], vy = -(float)ray.d[1], vz = -(float)ray.d[2];
+    const float lx = a.light[0], ly = a.light[1], lz = a.light[2];
+    const float tf_max = (float)(a.ntf - 1);
+    int span[3] = {0, 0, 0};
+    for (int s = 0; s < ray.nr; ++s) {
+      double u[3];
+      sample_params(a, ray, s, u);
+      float f, g[3];
+      query<P, STORE, SHADE>(a.m, rs, u, span, s == 0, f, g);
+      // transfer function: linear interpolation of the RGBA table
+      float x = (f - a.tf_lo) * a.tf_scale;
+      x = fminf(fmaxf(x, 0.0f), 1.0f) * tf_max;
+      const int i = min((int)x, a.ntf - 2);
+      const float t = x - (float)i;
+      const float4 c0 = a.tf[i];
+      const float4 c1 = a.tf[i + 1];
+      float sr = fmaf(t, c1.x - c0.x, c0.x);
+      float sg = fmaf(t, c1.y - c0.y, c0.y);
+      float sb = fmaf(t, c1.z - c0.z, c0.z);
+      const float alpha = fmaf(t, c1.w - c0.w, c0.w);
+      if (SHADE) {
+        const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+        const float inv = (g2 >= 1e-12f) ? rsqrtf(g2) : 1e6f;
+        const float nx = g[0] * inv, ny = g[1] * inv, nz = g[2] * inv;
+        const float ndl = nx * lx + ny * ly + nz * lz;
+        const float diff = fabsf(ndl);
+        const float rx = 2.0f * ndl * nx - lx;
+        const float ry = 2.0f * ndl * ny - ly;
+        const float rz = 2.0f * ndl * nz - lz;
+        const float rv = rx * vx + ry * vy + rz * vz;
+        const float spec = a.ks * ipowf(fmaxf(rv, 0.0f), a.shininess);
+        const float kdiff = a.ka + a.kd * diff;
+        sr = fminf(1.0f, fmaf(kdiff, sr, spec));
+        sg = fminf(1.0f, fmaf(kdiff, sg, spec));
+        sb = fminf(1.0f, fmaf(kdiff, sb, spec));
+      }
+      // front-to-back compositing, then early termination
+      const float wgt = (1.0f - A) * alpha;
+      cr = fmaf(wgt, sr, cr);
+      cg = fmaf(wgt, sg, cg);
+      cb = fmaf(wgt, sb, cb);
+      A += wgt;
+      ++count;
+      if (A > a.ert) break;
+    }
+    float4 o;
+    o.x = cr;
+    o.y = cg;
+    o.z = cb;
+    o.w = A;
+    reinterpret_cast<float4*>(a.out)[(size_t)py * (size_t)a.width + (size_t)px] = o;
+  }
+  if (a.samples != nullptr) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) count += __shfl_xor(count, off, 64);
+    if (lane == 0 && count != 0) atomicAdd(a.samples, (unsigned long long)count);
+  }
+}
+
+template <int P, int STORE, bool GRAD>
+__global__ __launch_bounds__(256) void eval_kernel(EvalArgsDev a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.n) return;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.m.ctrl, a.m.ctrl_bytes);
+  double u[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double x = a.xyz[3 * i + k];
+    const double v = (x - a.m.ax[k].lo) * a.m.ax[k].inv_ext;
+    u[k] = fmin(fmax(v, 0.0), 1.0);
+  }
+  int span[3];
+  float f, g[3];
+  query<P, STORE, GRAD>(a.m, rs, u, span, true, f, g);
+  a.value[i] = f;
+  if (GRAD) {
+    a.grad[3 * i + 0] = g[0];
+    a.grad[3 * i + 1] = g[1];
+    a.grad[3 * i + 2] = g[2];
+  }
+}
+
+__global__ void zero_counter(unsigned long long* p) {
+  if (threadIdx.x == 0) p[0] = 0ull;
+}
+
+template <int P, int STORE>
+hipError_t launch_render_p(const RenderArgsDev& a, hipStream_t st) {
+  const dim3 grid((a.width + 15) / 16, (a.height + 15) / 16);
+  if (a.shading)
+    render_kernel<P, STORE, true><<<grid, 256, 0, st>>>(a);
+  else
+    render_kernel<P, STORE, false><<<grid, 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+template <int P, int STORE>
+hipError_t launch_eval_p(const EvalArgsDev& a, hipStream_t st) {
+  const unsigned blocks = (unsigned)((a.n + 255) / 256);
+  if (a.grad)
+    eval_kernel<P, STORE, true><<<blocks, 256, 0, st>>>(a);
+  else
+    eval_kernel<P, STORE, false><<<blocks, 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+template <int STORE>
+hipError_t dispatch_render(const RenderArgsDev& a, hipStream_t st) {
+  switch (a.m.pmax) {
+    case 1: return launch_render_p<1, STORE>(a, st);
+    case 2: return launch_render_p<2, STORE>(a, st);
+    case 3: return launch_render_p<3, STORE>(a, st);
+    case 4: return launch_render_p<4, STORE>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int STORE>
+hipError_t dispatch_eval(const EvalArgsDev& a, hipStream_t st) {
+  switch (a.m.pmax) {
+    case 1: return launch_eval_p<1, STORE>(a, st);
+    case 2: return launch_eval_p<2, STORE>(a, st);
+    case 3: return launch_eval_p<3, STORE>(a, st);
+    case 4: return launch_eval_p<4, STORE>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_render(const RenderArgsDev& a, hipStream_t st) {
+  if (a.samples != nullptr) {
+    zero_counter<<<1, 64, 0, st>>>(a.samples);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return a.m.store == 0 ? dispatch_render<0>(a, st) : dispatch_render<1>(a, st);
+}
+
+hipError_t launch_eval(const EvalArgsDev& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  return a.m.store == 0 ? dispatch_eval<0>(a, st) : dispatch_eval<1>(a, st);
+}
+
+}  // namespace mfa

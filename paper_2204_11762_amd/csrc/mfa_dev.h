@@ -1,0 +1,89 @@
+// Internal device-side records shared by the C ABI (abi.cpp) and the HIP
+// kernels (kernels.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mfa {
+
+constexpr int kMaxDegree = 4;
+// Largest number of samples one ray may take; the host rejects requests
+// whose box diagonal exceeds this many steps.
+constexpr int kMaxSamplesPerRay = 1 << 16;
+
+// Per-span FP32 table of one axis of degree p, for span s (stored at row
+// s - p).  With delta = u - U_s (rounded to FP32 once):
+//   left[1] = delta,  left[j] = delta + dl[j]   with dl[j] = U_s - U_{s+1-j}, j = 2..p
+//   right[j] = dr[j] - delta                    with dr[j] = U_{s+j} - U_s,   j = 1..p
+//   inv[q][r] = 1 / (U_{s+r+1} - U_{s+1-q+r}),  q = 1..p, r = 0..q-1
+// Layout: dl[2..p], dr[1..p], inv[1][0], inv[2][0..1], ..., inv[p][0..p-1],
+// padded to a multiple of 4 floats.
+__host__ __device__ constexpr int table_entries(int p) { return 2 * p - 1 + p * (p + 1) / 2; }
+__host__ __device__ constexpr int table_stride(int p) { return (table_entries(p) + 3) & ~3; }
+__host__ __device__ constexpr int table_dl(int /*p*/, int j) { return j - 2; }
+__host__ __device__ constexpr int table_dr(int p, int j) { return (p - 1) + (j - 1); }
+__host__ __device__ constexpr int table_inv(int p, int q, int r) {
+  return (2 * p - 1) + (q - 1) * q / 2 + r;
+}
+
+struct AxisDev {
+  const double* knots;  // n + p + 1 knots, FP64
+  const float* tab;     // (n - p) rows of table_stride(p) floats
+  int32_t n;
+  int32_t p;
+  double lo;            // box corner along this axis
+  double inv_ext;       // 1 / (hi - lo): u = (x - lo) * inv_ext
+  float gscale;         // 1 / (hi - lo) in FP32, world-gradient factor
+  int32_t reserved;
+};
+
+struct ModelDev {
+  AxisDev ax[3];
+  const void* ctrl;     // n0*n1*n2 control points, x fastest
+  uint32_t ctrl_bytes;  // size of ctrl in bytes (< 2^31)
+  int32_t store;        // 0 FP32, 1 BF16
+  int32_t nx;           // row stride (elements)
+  int32_t nxy;          // slice stride (elements)
+  int32_t pmax;         // largest degree; kernels are instantiated for it
+  int32_t reserved;
+};
+
+struct RenderArgsDev {
+  ModelDev m;
+  int32_t kind;         // 0 ortho, 1 perspective
+  int32_t width;
+  int32_t height;
+  int32_t ntf;          // transfer-function entries
+  double eye[3];
+  double F[3], R[3], V[3];
+  double cam0, cam1;    // ortho: half_w, half_h; perspective: tan(fov/2), W/H
+  double lo[3], hi[3];
+  double step;
+  const float4* tf;     // ntf RGBA entries
+  float tf_lo;          // x = (f - tf_lo) * tf_scale, clamped to [0,1]
+  float tf_scale;
+  float ert;            // early termination once A > ert
+  int32_t shading;
+  int32_t shininess;
+  float ka, kd, ks;
+  float light[3];       // unit vector towards the light
+  int32_t reserved;
+  float* out;           // width*height*4
+  unsigned long long* samples;  // nullable
+};
+
+struct EvalArgsDev {
+  ModelDev m;
+  double lo[3], hi[3];
+  const double* xyz;
+  float* value;
+  float* grad;          // nullable
+  int64_t n;
+};
+
+// Kernel launchers (kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_render(const RenderArgsDev& a, hipStream_t stream);
+hipError_t launch_eval(const EvalArgsDev& a, hipStream_t stream);
+
+}  // namespace mfa

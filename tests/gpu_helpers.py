@@ -1,0 +1,99 @@
+"""Helpers for GPU parity tests: run the HIP library through its C ABI and
+compare with the FP64 oracle."""
+
+from __future__ import annotations
+
+import copy
+from dataclasses import dataclass
+
+import numpy as np
+
+from helpers import oracle_workload
+from oracle import raycast as orc
+
+# Tolerances (normwise relative errors against FP64, image RMSE on [0,1]
+# premultiplied RGBA).
+FP32_REL = 1e-5
+FP32_RMSE = 1e-4
+BF16_REL = 4e-3
+BF16_RMSE = 2e-3
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+def gpu_render(b, ctx, model, wk, params=None):
+    torch = torch_mod()
+    cam = wk.camera
+    out = torch.full((cam.height, cam.width, 4), -1.0, dtype=torch.float32, device="cuda")
+    cnt = torch.full((1,), -7, dtype=torch.int64, device="cuda")
+    b.mfa_render(ctx, model, cam, wk.tf, params or wk.params, out, cnt)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64), int(cnt.cpu().item())
+
+
+def gpu_eval(b, ctx, model, xyz, grad=True):
+    torch = torch_mod()
+    x = torch.from_numpy(np.ascontiguousarray(xyz, dtype=np.float64)).cuda()
+    v = torch.full((len(xyz),), np.nan, dtype=torch.float32, device="cuda")
+    g = torch.full((len(xyz), 3), np.nan, dtype=torch.float32, device="cuda") if grad else None
+    b.mfa_eval_points(ctx, model, x, v, g)
+    torch.cuda.synchronize()
+    return v.cpu().numpy().astype(np.float64), (g.cpu().numpy().astype(np.float64) if grad else None)
+
+
+def normwise(approx, ref):
+    """max |a - r| / max |r| (vectors: Euclidean norm per row)."""
+    if ref.ndim == 1:
+        return float(np.abs(approx - ref).max() / max(np.abs(ref).max(), 1e-300))
+    return float(np.linalg.norm(approx - ref, axis=1).max()
+                 / max(np.linalg.norm(ref, axis=1).max(), 1e-300))
+
+
+@dataclass
+class ImageReport:
+    rmse: float
+    max_abs: float
+    n_ambiguous: int
+    n_bad: int
+    samples_gpu: int
+    samples_ref: int
+    samples_slack: int
+
+
+def oracle_on_pixels(wk, pix, o_max=None, model=None, ert=None):
+    M, cam, tf, prm = oracle_workload(wk)
+    if model is not None:
+        M = model
+    if ert is not None:
+        prm = copy.copy(prm)
+        prm.ert_alpha = ert
+    return orc.render_pixels(M, cam, tf, prm, pix, o_max=o_max)
+
+
+def compare_image(gpu_img, gpu_count, wk, pix, tau, px_tol, model=None, count_exact=True):
+    """Compare GPU pixels (flat indices ``pix``) with the oracle.  A pixel whose
+    accumulated opacity comes within ``tau`` of the termination threshold may
+    stop one or more samples earlier or later; it must then lie between the
+    oracle renders with threshold O_max - tau and O_max + tau."""
+    H, W = wk.camera.height, wk.camera.width
+    flat = gpu_img.reshape(-1, 4)[pix]
+    nom = oracle_on_pixels(wk, pix, model=model)
+    err = flat - nom.rgba
+    amb = nom.near_threshold <= tau
+    bad = np.abs(err).max(axis=1) > px_tol
+    slack = 0
+    if amb.any():
+        ip = pix[amb]
+        early = oracle_on_pixels(wk, ip, o_max=wk.params.ert_alpha - tau, model=model)
+        late = oracle_on_pixels(wk, ip, o_max=wk.params.ert_alpha + tau, model=model)
+        lo = np.minimum(early.rgba, late.rgba) - px_tol
+        hi = np.maximum(early.rgba, late.rgba) + px_tol
+        inside = ((flat[amb] >= lo) & (flat[amb] <= hi)).all(axis=1)
+        bad[np.nonzero(amb)[0]] = ~inside
+        slack = int(np.abs(late.samples - early.samples).sum())
+    rmse = float(np.sqrt((err ** 2).mean()))
+    return ImageReport(rmse, float(np.abs(err).max()), int(amb.sum()), int(bad.sum()),
+                       gpu_count, int(nom.samples.sum()), slack)

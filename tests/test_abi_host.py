@@ -1,0 +1,188 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+declared in include/mfa_dvr.h, and rejects malformed descriptors with the
+documented status codes (validation runs before any device call).  No GPU
+is needed."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2204_11762_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def b():
+    from paper_2204_11762_amd import binding
+    return binding
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mfa_dvr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mfa_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(b):
+    names = _declared()
+    assert len(names) >= 12
+    raw = C.CDLL(b.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), f"{n} declared but not exported"
+    assert set(names) == set(b.EXPORTED)
+
+
+def test_version_and_empty_error(b):
+    assert "gfx950" in b.mfa_version()
+    assert b.last_error() == ""
+
+
+def test_valid_inputs_pass(b):
+    for wk in (wl.c1(), wl.c2()):
+        b.mfa_validate_model(wk.model)
+        b.mfa_validate_model(wk.model, b.MFA_STORE_BF16)
+        b.mfa_validate_render(wk.camera, wk.tf, wk.params)
+
+
+def _bad_model(**kw):
+    spec = wl.c1().model
+    knots = [np.array(k, dtype=np.float64) for k in spec.knots]
+    ctrl = np.array(spec.ctrl)
+    deg = list(spec.degree)
+    lo, hi = list(spec.lo), list(spec.hi)
+    if "knots0" in kw:
+        knots[0] = kw["knots0"]
+    if "ctrl" in kw:
+        ctrl = kw["ctrl"]
+    if "degree" in kw:
+        deg = kw["degree"]
+    if "lo" in kw:
+        lo = kw["lo"]
+    return wl.ModelSpec(tuple(deg), tuple(knots), ctrl, tuple(lo), tuple(hi))
+
+
+def _knots_c1():
+    return wl.clamped_uniform_knots(16, 2)
+
+
+MODEL_ERRORS = {
+    "non-monotone knots": dict(knots0=np.where(np.arange(19) == 8, 0.9, _knots_c1())),
+    "unclamped start": dict(knots0=np.concatenate([[0, 0, 0.01], _knots_c1()[3:]])),
+    "unclamped end": dict(knots0=np.concatenate([_knots_c1()[:-1], [1.5]])),
+    "interior knot at 0": dict(knots0=np.concatenate([[0, 0, 0, 0], _knots_c1()[4:]])),
+    "knot multiplicity > p": dict(knots0=np.concatenate([_knots_c1()[:5], [0.4] * 3,
+                                                         _knots_c1()[8:]])),
+    "nan knot": dict(knots0=np.where(np.arange(19) == 5, np.nan, _knots_c1())),
+    "degree 0": dict(degree=[0, 2, 2]),
+    "degree 5": dict(degree=[2, 5, 2]),
+    "nan control point": dict(ctrl=np.where(np.arange(16 ** 3).reshape(16, 16, 16) == 77, np.nan,
+                                            wl.c1().model.ctrl)),
+    "control point beyond fp32": dict(ctrl=np.full((16, 16, 16), 1e39)),
+    "lo >= hi": dict(lo=[0.0, 1.0, 0.0]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MODEL_ERRORS))
+def test_model_validation_errors(b, name):
+    spec = _bad_model(**MODEL_ERRORS[name])
+    with pytest.raises(b.MFAError) as e:
+        b.mfa_validate_model(spec)
+    assert e.value.status == b.MFA_ERR_MODEL, e.value
+    assert e.value.message
+
+
+def test_wrong_knot_length_and_null_pointers(b):
+    spec = wl.c1().model
+    d, keep = b.model_desc(spec)
+    d.n_ctrl[0] = 17          # knots now one short: U_n..U_{n+p} are not all 1
+    assert b.lib.mfa_validate_model(C.byref(d)) == b.MFA_ERR_MODEL
+    d, keep = b.model_desc(spec)
+    d.ctrl = None
+    assert b.lib.mfa_validate_model(C.byref(d)) == b.MFA_ERR_MODEL
+    d, keep = b.model_desc(spec)
+    d.store = 7
+    assert b.lib.mfa_validate_model(C.byref(d)) == b.MFA_ERR_MODEL
+    assert b.lib.mfa_validate_model(None) == b.MFA_ERR_INVALID
+    assert b.lib.mfa_validate_render(None, None, None) == b.MFA_ERR_INVALID
+
+
+def test_model_too_large(b):
+    d, keep = b.model_desc(wl.c1().model)
+    d.n_ctrl[0] = d.n_ctrl[1] = d.n_ctrl[2] = 1 << 11   # 2^33 elements: rejected by size first
+    d.knots[0] = d.knots[1] = d.knots[2] = keep.f64(wl.clamped_uniform_knots(1 << 11, 2))
+    assert b.lib.mfa_validate_model(C.byref(d)) == b.MFA_ERR_INVALID
+    assert "2^31" in b.last_error()
+
+
+def _render_args():
+    wk = wl.c2()
+    return wk.camera, wk.tf, wk.params
+
+
+def _mod(obj, **kw):
+    import copy
+    o = copy.copy(obj)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+RENDER_ERRORS = {
+    "zero width": lambda c, t, p: (_mod(c, width=0), t, p),
+    "huge image": lambda c, t, p: (_mod(c, width=40000), t, p),
+    "eye == target": lambda c, t, p: (_mod(c, eye=c.target), t, p),
+    "up parallel": lambda c, t, p: (_mod(c, eye=(0.5, 3.0, 0.5), up=(0, 1, 0)), t, p),
+    "fov 0": lambda c, t, p: (_mod(c, fov_y_deg=0.0), t, p),
+    "fov 180": lambda c, t, p: (_mod(c, fov_y_deg=180.0), t, p),
+    "ortho zero extent": lambda c, t, p: (_mod(c, kind="ortho", ortho_half_w=0.0), t, p),
+    "tf one entry": lambda c, t, p: (c, _mod(t, table=t.table[:1]), p),
+    "tf too long": lambda c, t, p: (c, _mod(t, table=np.zeros((5000, 4), np.float32)), p),
+    "tf empty range": lambda c, t, p: (c, _mod(t, v_hi=t.v_lo), p),
+    "tf nan": lambda c, t, p: (c, _mod(t, table=np.full((8, 4), np.nan, np.float32)), p),
+    "step 0": lambda c, t, p: (c, t, _mod(p, step=0.0)),
+    "step negative": lambda c, t, p: (c, t, _mod(p, step=-0.1)),
+    "step nan": lambda c, t, p: (c, t, _mod(p, step=float("nan"))),
+    "shininess negative": lambda c, t, p: (c, t, _mod(p, shininess=-1)),
+    "zero light": lambda c, t, p: (c, t, _mod(p, headlight=False, light_dir=(0, 0, 0))),
+    "nan ka": lambda c, t, p: (c, t, _mod(p, ka=float("nan"))),
+}
+
+
+@pytest.mark.parametrize("name", sorted(RENDER_ERRORS))
+def test_render_validation_errors(b, name):
+    cam, tf, prm = RENDER_ERRORS[name](*_render_args())
+    with pytest.raises(b.MFAError) as e:
+        b.mfa_validate_render(cam, tf, prm)
+    assert e.value.status == b.MFA_ERR_INVALID, e.value
+
+
+def test_null_context_and_handles(b):
+    h = C.c_int64()
+    d, keep = b.model_desc(wl.c1().model)
+    assert b.lib.mfa_model_upload(None, C.byref(d), C.byref(h)) == b.MFA_ERR_HANDLE
+    assert b.lib.mfa_model_free(None, 1) == b.MFA_ERR_HANDLE
+    assert b.lib.mfa_set_memory_budget(None, 0) == b.MFA_ERR_HANDLE
+    assert b.lib.mfa_render(None, 1, None, None, None, None, None, None) == b.MFA_ERR_HANDLE
+    assert b.lib.mfa_eval_points(None, 1, 0, None, None, None, None) == b.MFA_ERR_HANDLE
+    assert b.lib.mfa_destroy(None) == b.MFA_OK
+    assert b.lib.mfa_create(0, None) == b.MFA_ERR_INVALID
+
+
+def test_product_path_does_not_use_the_oracle():
+    """The package and the benchmark's GPU leg never import the oracle; the
+    oracle is test infrastructure only."""
+    pkg = os.path.join(ROOT, "paper_2204_11762_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle", src, re.M), f
+                assert "oracle/" not in src, f
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith(".py"):
+            src = open(os.path.join(ROOT, "oracle", f)).read()
+            assert not re.search(r"^\s*(from|import)\s+paper_2204_11762_amd", src, re.M), f

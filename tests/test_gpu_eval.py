@@ -1,0 +1,116 @@
+"""GPU parity of the value and gradient queries (mfa_eval_points) against the
+FP64 oracle, through the C ABI."""
+
+import numpy as np
+import pytest
+
+from gpu_helpers import BF16_REL, FP32_REL, gpu_eval, normwise
+from helpers import oracle_model
+from oracle import bspline as ob
+from oracle import quant
+from paper_2204_11762_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _points(spec, rng, m=6000):
+    """Random points, every knot plane crossing, box faces/corners, and
+    points outside the box (clamped)."""
+    lo = np.asarray(spec.lo, dtype=np.float64)
+    hi = np.asarray(spec.hi, dtype=np.float64)
+    pts = [wl.uniform_points(rng, m, lo, hi)]
+    for ax in range(3):
+        for kv in np.unique(spec.knots[ax]):
+            q = wl.uniform_points(rng, 8, lo, hi)
+            q[:, ax] = lo[ax] + kv * (hi[ax] - lo[ax])
+            pts.append(q)
+    corners = np.array([[a, b, c] for a in (0, 1) for b in (0, 1) for c in (0, 1)], float)
+    pts.append(lo + corners * (hi - lo))
+    out = wl.uniform_points(rng, 64, lo - 0.5 * (hi - lo), hi + 0.5 * (hi - lo))
+    pts.append(out)
+    return np.concatenate(pts)
+
+
+def _check(mfa, spec, store, seed, rel_v, rel_g, ref_ctrl=None):
+    b, ctx = mfa
+    h = b.mfa_model_upload(ctx, spec, store)
+    try:
+        rng = np.random.default_rng(seed)
+        xyz = _points(spec, rng)
+        f, g = gpu_eval(b, ctx, h, xyz)
+        M = oracle_model(spec, ctrl=ref_ctrl)
+        F, G = ob.eval_world(M, xyz)
+        ev, eg = normwise(f, F), normwise(g, G)
+        print(f"\n  value rel {ev:.3e}  grad rel {eg:.3e}  (n={len(xyz)})")
+        assert np.isfinite(f).all() and np.isfinite(g).all()
+        assert ev <= rel_v
+        if rel_g is not None:
+            assert eg <= rel_g
+        # value-only launch gives the same values
+        f2, _ = gpu_eval(b, ctx, h, xyz, grad=False)
+        np.testing.assert_array_equal(f2, f)
+        return ev, eg
+    finally:
+        b.mfa_model_free(ctx, h)
+
+
+RANDOM_CASES = [
+    # (n, degree, beta knots, lo, hi)
+    ((5, 6, 7), (1, 1, 1), False, (0, 0, 0), (1, 1, 1)),
+    ((9, 7, 8), (2, 3, 1), True, (-1, 0.5, 2), (1, 1.5, 2.5)),
+    ((12, 11, 10), (3, 3, 3), True, (0, 0, 0), (1, 1, 1)),
+    ((10, 9, 13), (4, 4, 4), False, (0, 0, 0), (2, 3, 1)),
+    ((11, 8, 9), (3, 2, 4), True, (-2, -2, -2), (2, 2, 2)),
+    ((5, 4, 3), (4, 3, 2), False, (0, 0, 0), (1, 1, 1)),   # n = p+1: Bezier
+]
+
+
+@pytest.mark.parametrize("case", range(len(RANDOM_CASES)))
+@pytest.mark.parametrize("store", [0, 1])
+def test_eval_random_models(mfa, case, store):
+    n, deg, beta, lo, hi = RANDOM_CASES[case]
+    spec = wl.random_model(np.random.default_rng(100 + case), n=n, degree=deg,
+                           beta_knots=beta, lo=lo, hi=hi)
+    if store == 0:
+        _check(mfa, spec, 0, case, FP32_REL, FP32_REL)
+    else:
+        # against the canonical FP64 model: storage error within the BF16 bound
+        _check(mfa, spec, 1, case, BF16_REL, None)
+        # against the de-quantised model: arithmetic error only, FP32 bound
+        _check(mfa, spec, 1, case, FP32_REL, FP32_REL,
+               ref_ctrl=quant.dequant_bf16(spec.ctrl))
+
+
+def test_eval_c1_model(mfa):
+    _check(mfa, wl.c1().model, 0, 1, FP32_REL, FP32_REL)
+
+
+def test_eval_c2_model(mfa):
+    _check(mfa, wl.c2().model, 0, 2, FP32_REL, FP32_REL)
+
+
+@pytest.fixture(scope="module")
+def c3_model():
+    return wl.c3().model
+
+
+def test_eval_c3_model_fp32(mfa, c3_model):
+    _check(mfa, c3_model, 0, 3, FP32_REL, FP32_REL)
+
+
+def test_eval_c3_model_bf16(mfa, c3_model):
+    ev, eg = _check(mfa, c3_model, 1, 4, BF16_REL, None)
+    _check(mfa, c3_model, 1, 4, FP32_REL, FP32_REL, ref_ctrl=quant.dequant_bf16(c3_model.ctrl))
+
+
+def test_eval_zero_points_is_noop(mfa):
+    import torch
+    b, ctx = mfa
+    h = b.mfa_model_upload(ctx, wl.c1().model)
+    try:
+        x = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+        v = torch.zeros((0,), dtype=torch.float32, device="cuda")
+        b.mfa_eval_points(ctx, h, x, v, None)
+        torch.cuda.synchronize()
+    finally:
+        b.mfa_model_free(ctx, h)

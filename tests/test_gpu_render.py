@@ -1,0 +1,235 @@
+"""GPU parity of the ray caster (mfa_render) against the FP64 oracle, through
+the C ABI: full frames at small sizes with ragged tiles, the c1 frame in
+full, sampled pixels of the full-size c2 frame, and the 4096-pixel subset of
+c3 in FP32 and BF16 storage."""
+
+import copy
+
+import numpy as np
+import pytest
+
+from gpu_helpers import (BF16_REL, BF16_RMSE, FP32_REL, FP32_RMSE, compare_image, gpu_eval,
+                         gpu_render, normwise)
+from helpers import oracle_workload, oracle_model
+from oracle import bspline as ob
+from oracle import quant
+from oracle import raycast as orc
+from paper_2204_11762_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TAU32 = 2e-5      # band around the termination threshold for FP32 opacity
+PX32 = 2e-4       # per-pixel sanity bound (RMSE is the criterion)
+
+
+def _report(tag, rep):
+    print(f"\n  {tag}: rmse {rep.rmse:.3e} max {rep.max_abs:.3e} ambiguous {rep.n_ambiguous} "
+          f"bad {rep.n_bad} samples gpu {rep.samples_gpu} ref {rep.samples_ref} "
+          f"slack {rep.samples_slack}")
+
+
+def _check_counts(rep, pix_is_full):
+    if pix_is_full:
+        assert abs(rep.samples_gpu - rep.samples_ref) <= rep.samples_slack
+
+
+def test_c1_full_frame(mfa):
+    b, ctx = mfa
+    wk = wl.c1()
+    h = b.mfa_model_upload(ctx, wk.model)
+    try:
+        img, cnt = gpu_render(b, ctx, h, wk)
+        pix = np.arange(128 * 128)
+        rep = compare_image(img, cnt, wk, pix, TAU32, PX32)
+        _report("c1", rep)
+        assert rep.rmse <= FP32_RMSE and rep.n_bad == 0
+        _check_counts(rep, True)
+        # no termination: continuous, nominal 256 samples per ray
+        p2 = copy.copy(wk.params)
+        p2.ert_alpha = 1.0
+        img2, cnt2 = gpu_render(b, ctx, h, wk, p2)
+        assert cnt2 == 256 * 128 * 128
+        wk2 = copy.copy(wk)
+        wk2.params = p2
+        rep2 = compare_image(img2, cnt2, wk2, pix, TAU32, PX32)
+        _report("c1 no-ERT", rep2)
+        assert rep2.rmse <= FP32_RMSE / 10 and rep2.n_bad == 0
+    finally:
+        b.mfa_model_free(ctx, h)
+
+
+SMALL = [
+    # (seed, n, degree, beta, lo, hi, image, kind, shading, ert, headlight)
+    (1, (9, 8, 7), (3, 3, 3), False, (0, 0, 0), (1, 1, 1), (37, 29), "persp", True, 0.99, True),
+    (2, (10, 9, 11), (2, 3, 1), True, (-1, 0, 0), (1, 1, 2), (40, 33), "persp", True, 0.95, False),
+    (3, (8, 8, 8), (4, 4, 4), True, (0, 0, 0), (1, 1, 1), (23, 41), "ortho", True, 0.99, True),
+    (4, (7, 9, 6), (1, 1, 1), False, (0, 0, 0), (1, 1, 1), (31, 31), "persp", False, 0.99, True),
+    (5, (12, 10, 9), (3, 4, 2), True, (0, 0, 0), (2, 1, 1), (48, 17), "persp", True, 1.5, True),
+]
+
+
+@pytest.mark.parametrize("case", range(len(SMALL)))
+@pytest.mark.parametrize("store", [0, 1])
+def test_small_full_frames(mfa, case, store):
+    seed, n, deg, beta, lo, hi, (W, H), kind, shade, ert, head = SMALL[case]
+    rng = np.random.default_rng(seed)
+    spec = wl.random_model(rng, n=n, degree=deg, beta_knots=beta, lo=lo, hi=hi)
+    ctr = tuple((np.asarray(lo) + np.asarray(hi)) / 2)
+    ext = float(np.max(np.asarray(hi) - np.asarray(lo)))
+    if kind == "persp":
+        cam = wl.orbit_camera(W, H, 30 + 40 * seed, -20 + 15 * seed, radius=2.2 * ext, target=ctr)
+    else:
+        cam = wl.CameraSpec("ortho", (ctr[0] + 0.3, ctr[1] + 0.2, ctr[2] + 3 * ext), ctr,
+                            (0.0, 1.0, 0.0), W, H, ortho_half_w=0.6 * ext, ortho_half_h=0.7 * ext)
+    P = np.asarray(spec.ctrl)
+    tf = wl.pwl_tf(seed, P.min(), P.max(), alpha_max=0.15)
+    prm = wl.ParamSpec(step=ext / 97.0, ert_alpha=ert, shading=shade, headlight=head,
+                       light_dir=(0.3, -0.5, 0.8))
+    wk = wl.Workload("small", spec, cam, tf, prm)
+    b, ctx = mfa
+    h = b.mfa_model_upload(ctx, spec, store)
+    try:
+        img, cnt = gpu_render(b, ctx, h, wk)
+        pix = np.arange(W * H)
+        if store == 0:
+            rep = compare_image(img, cnt, wk, pix, TAU32, PX32)
+            _report(f"small{case} fp32", rep)
+            assert rep.rmse <= FP32_RMSE and rep.n_bad == 0
+            _check_counts(rep, True)
+        else:
+            # arithmetic error only: against the de-quantised model
+            Mq = oracle_model(spec, ctrl=quant.dequant_bf16(spec.ctrl))
+            rep = compare_image(img, cnt, wk, pix, TAU32, PX32, model=Mq)
+            _report(f"small{case} bf16 vs dequantised", rep)
+            assert rep.rmse <= FP32_RMSE and rep.n_bad == 0
+            # and the total error against the FP64 model
+            rep = compare_image(img, cnt, wk, pix, 3e-3, 5e-2)
+            _report(f"small{case} bf16 vs fp64", rep)
+            assert rep.rmse <= BF16_RMSE
+        # misses are exactly transparent black, and nothing is left unwritten
+        M, c, _, p = oracle_workload(wk)
+        r, cc = np.divmod(pix, W)
+        o, d = orc.camera_rays(c, r, cc)
+        t0, t1, hit = orc.slab(o, d, M.lo, M.hi)
+        nr = orc.sample_counts(t0, t1, hit, p.step)
+        flat = img.reshape(-1, 4)
+        assert (flat[nr == 0] == 0).all()
+        assert (flat >= 0).all()
+    finally:
+        b.mfa_model_free(ctx, h)
+
+
+def test_determinism_and_stream(mfa):
+    import torch
+    b, ctx = mfa
+    wk = wl.c2()
+    wk.camera.width = wk.camera.height = 200
+    h = b.mfa_model_upload(ctx, wk.model)
+    try:
+        a1, c1 = gpu_render(b, ctx, h, wk)
+        s = torch.cuda.Stream()
+        out = torch.zeros((200, 200, 4), dtype=torch.float32, device="cuda")
+        cnt = torch.zeros((1,), dtype=torch.int64, device="cuda")
+        with torch.cuda.stream(s):
+            b.mfa_render(ctx, h, wk.camera, wk.tf, wk.params, out, cnt, stream=s)
+        s.synchronize()
+        assert np.array_equal(out.cpu().numpy().astype(np.float64), a1)
+        assert int(cnt.item()) == c1
+    finally:
+        b.mfa_model_free(ctx, h)
+
+
+def test_camera_inside_volume(mfa):
+    b, ctx = mfa
+    wk = wl.c2()
+    wk.camera = wl.CameraSpec("persp", (0.45, 0.5, 0.55), (0.9, 0.6, 0.2), (0, 1, 0), 64, 48,
+                              fov_y_deg=70.0)
+    h = b.mfa_model_upload(ctx, wk.model)
+    try:
+        img, cnt = gpu_render(b, ctx, h, wk)
+        rep = compare_image(img, cnt, wk, np.arange(64 * 48), TAU32, PX32)
+        _report("inside", rep)
+        assert rep.rmse <= FP32_RMSE and rep.n_bad == 0
+        _check_counts(rep, True)
+    finally:
+        b.mfa_model_free(ctx, h)
+
+
+def test_c2_full_size_sampled_pixels(mfa):
+    b, ctx = mfa
+    wk = wl.c2()
+    h = b.mfa_model_upload(ctx, wk.model)
+    try:
+        img, cnt = gpu_render(b, ctx, h, wk)
+        # hit pixels only carry information; sample among them and misses
+        M, cam, _, p = oracle_workload(wk)
+        pix_all = np.arange(512 * 512)
+        r, c = np.divmod(pix_all, 512)
+        o, d = orc.camera_rays(cam, r, c)
+        t0, t1, hit = orc.slab(o, d, M.lo, M.hi)
+        nr = orc.sample_counts(t0, t1, hit, p.step)
+        assert (img.reshape(-1, 4)[nr == 0] == 0).all()
+        rng = np.random.default_rng(22)
+        pix = np.sort(np.concatenate([rng.choice(np.nonzero(nr > 0)[0], 3000, replace=False),
+                                      rng.choice(np.nonzero(nr == 0)[0], 200, replace=False)]))
+        rep = compare_image(img, cnt, wk, pix, TAU32, PX32)
+        _report("c2 sampled", rep)
+        assert rep.rmse <= FP32_RMSE and rep.n_bad == 0
+        # the evaluated-sample count covers the whole frame: bounded by the
+        # nominal count, and at least the count of the sampled pixels scaled
+        assert 0 < cnt <= int(nr.sum())
+    finally:
+        b.mfa_model_free(ctx, h)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return wl.c3()
+
+
+def _subset_sample_positions(wk, every=5):
+    """World positions of the oracle's samples on the subset rays (every
+    ``every``-th sample), for value/gradient parity at those positions."""
+    M, cam, _, p = oracle_workload(wk)
+    pix = wk.subset
+    r, c = np.divmod(pix, cam.width)
+    o, d = orc.camera_rays(cam, r, c)
+    t0, t1, hit = orc.slab(o, d, M.lo, M.hi)
+    nr = orc.sample_counts(t0, t1, hit, p.step)
+    pts = []
+    for i in np.nonzero(nr > 0)[0]:
+        s = np.arange(0, nr[i], every)
+        t = t0[i] + (s + 0.5) * p.step
+        pts.append(o[i] + t[:, None] * d[i])
+    return np.concatenate(pts)
+
+
+@pytest.mark.parametrize("store", [0, 1])
+def test_c3_subset(mfa, c3, store):
+    b, ctx = mfa
+    wk = c3
+    h = b.mfa_model_upload(ctx, wk.model, store)
+    try:
+        # value / gradient at the oracle's sample positions
+        xyz = _subset_sample_positions(wk)
+        f, g = gpu_eval(b, ctx, h, xyz)
+        M = oracle_model(wk.model)
+        F = np.empty(len(xyz))
+        G = np.empty((len(xyz), 3))
+        for i in range(0, len(xyz), 100000):
+            F[i:i + 100000], G[i:i + 100000] = ob.eval_world(M, xyz[i:i + 100000])
+        ev, eg = normwise(f, F), normwise(g, G)
+        print(f"\n  c3 store={store}: value rel {ev:.3e} grad rel {eg:.3e} at {len(xyz)} positions")
+        img, cnt = gpu_render(b, ctx, h, wk)
+        if store == 0:
+            assert ev <= FP32_REL and eg <= FP32_REL
+            rep = compare_image(img, cnt, wk, wk.subset, TAU32, PX32)
+            _report("c3 fp32", rep)
+            assert rep.rmse <= FP32_RMSE and rep.n_bad == 0
+        else:
+            assert ev <= BF16_REL
+            rep = compare_image(img, cnt, wk, wk.subset, 3e-3, 5e-2)
+            _report("c3 bf16 vs fp64", rep)
+            assert rep.rmse <= BF16_RMSE
+    finally:
+        b.mfa_model_free(ctx, h)
