@@ -183,6 +183,10 @@ def main():
                     help="rays of the oracle's bounded sample (0 = skip the CPU leg)")
     ap.add_argument("--cpu-workers", type=int, default=0, help="0 = host cores, at most 16")
     ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of MIB MiB (a plain copy "
+                         "kernel of known traffic, for scaling HBM counters)")
+    ap.add_argument("--legs", default="fp32,bf16", help="storages to measure")
     args = ap.parse_args()
 
     def log(msg):
@@ -209,16 +213,27 @@ def main():
 
     from paper_2204_11762_amd import binding as b
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calib > 0:
+        n = args.copy_calib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calib} MiB read + {args.copy_calib} MiB written")
+        del src, dst
     ctx = b.mfa_create(0)
     try:
         legs = {}
         for name, store in (("fp32", 0), ("bf16", 1)):
-            legs[name] = gpu_leg(b, ctx, wk, store, args.steps, args.warmup, log)
+            if name in args.legs.split(","):
+                legs[name] = gpu_leg(b, ctx, wk, store, args.steps, args.warmup, log)
     finally:
         b.mfa_destroy(ctx)
+    if args.store not in legs:
+        args.store = next(iter(legs))
 
     head = legs[args.store]
-    other = legs["fp32" if args.store == "bf16" else "bf16"]
     fps = args.steps / head["wall"]
     value = head["samples"] * fps
     kern_ms = float(head["lat"].mean())
@@ -261,7 +276,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
                      "kernel": "render_kernel<3,%s,shade>" % ("1" if args.store == "bf16" else "0"),
                      "kernel_ms": kern_ms, "flops_per_sample": flops_per_sample(p)},
-        "legs": {"fp32": summary(legs["fp32"], "fp32"), "bf16": summary(legs["bf16"], "bf16")},
+        "legs": {k: summary(v, k) for k, v in legs.items()},
     }
     if base is not None:
         line["cpu_baseline"] = {"value": base["samples"] / base["wall"], "unit": "samples/s",

@@ -274,7 +274,45 @@ struct DeviceModel {
   int64_t bytes = 0;
   mfa::ModelDev md{};
   double lo[3], hi[3];
+  int64_t nknots[3];
 };
+
+// LDS plan of the brick ray caster for one request: transfer function,
+// knots, then one brick per wave.  Workgroups are sized for four per CU;
+// requests whose tables leave too little room use the global-memory
+// fallback kernel (lds_bytes = 0).
+constexpr int kLdsPerGroup = 40 * 1024;
+constexpr int kMinBrick = 512;
+
+void plan_bricks(const DeviceModel& dm, int ntf, double step, mfa::RenderArgsDev& a) {
+  const int tf_bytes = ntf * 16;
+  int knot_doubles = 0;
+  for (int k = 0; k < 3; ++k) {
+    a.knot_off[k] = knot_doubles;
+    knot_doubles += int(dm.nknots[k]);
+  }
+  const int knot_bytes = (knot_doubles * 8 + 15) & ~15;
+  const int rest = kLdsPerGroup - tf_bytes - knot_bytes;
+  const int cap = (rest / (4 * 4)) & ~3;
+  if (cap < kMinBrick) {
+    a.lds_bytes = 0;
+    a.spr = 0;
+    a.brick_cap = 0;
+    return;
+  }
+  a.lds_knots = tf_bytes;
+  a.lds_bricks = tf_bytes + knot_bytes;
+  a.brick_cap = cap;
+  a.lds_bytes = tf_bytes + knot_bytes + 4 * cap * 4;
+  // about three knot spans along the worst axis per round
+  double cells = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double span_len = (dm.hi[k] - dm.lo[k]) / dm.md.ax[k].m;
+    cells = std::max(cells, step / span_len);
+  }
+  const int spr = cells > 0.0 ? int(3.0 / cells) : 64;
+  a.spr = std::max(4, std::min(64, spr));
+}
 
 struct TFEntry {
   std::vector<float> host;
@@ -492,6 +530,7 @@ mfa_status mfa_model_upload(mfa_ctx* ctx, const mfa_model_desc* d, int64_t* mode
   dm.bytes = int64_t(bytes);
   unsigned char* base = static_cast<unsigned char*>(mem);
   int pmax = 0;
+  int uniform = 1;
   for (int k = 0; k < 3; ++k) {
     mfa::AxisDev& A = dm.md.ax[k];
     A.knots = reinterpret_cast<const double*>(base + off_knots[k]);
@@ -500,11 +539,19 @@ mfa_status mfa_model_upload(mfa_ctx* ctx, const mfa_model_desc* d, int64_t* mode
     A.p = d->degree[k];
     A.lo = d->lo[k];
     A.inv_ext = 1.0 / (d->hi[k] - d->lo[k]);
+    A.m = double(n[k] - d->degree[k]);
     A.gscale = float(1.0 / (d->hi[k] - d->lo[k]));
+    A.inv_m = float(1.0 / A.m);
     dm.lo[k] = d->lo[k];
     dm.hi[k] = d->hi[k];
+    dm.nknots[k] = n[k] + d->degree[k] + 1;
     pmax = std::max(pmax, int(A.p));
+    // uniform knot vector: U_{p+j} = j / (n-p) exactly, j = 0..n-p
+    const int64_t m = n[k] - d->degree[k];
+    for (int64_t j = 0; j <= m && uniform; ++j)
+      if (d->knots[k][d->degree[k] + j] != double(j) / double(m)) uniform = 0;
   }
+  dm.md.uniform = uniform;
   dm.md.ctrl = base + off_ctrl;
   dm.md.ctrl_bytes = uint32_t(ctrl_bytes);
   dm.md.store = d->store;
@@ -610,6 +657,7 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const 
   }
   a.out = rgba_dev;
   a.samples = reinterpret_cast<unsigned long long*>(samples_dev);
+  plan_bricks(dm, tf->n, prm->step, a);
   const hipError_t e = mfa::launch_render(a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("render launch", e));
   return MFA_OK;

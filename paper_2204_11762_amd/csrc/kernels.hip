@@ -211,8 +211,156 @@ __device__ __forceinline__ void axis_basis(int q, const float* __restrict__ row,
   }
 }
 
+// Uniform knots (U_{p+k} = k/m on an interior span, m = n - p): in the
+// normalised coordinate t = (u - U_s) m in [0,1) the p+1 non-zero
+// functions are the cardinal B-spline pieces and their t-derivatives.
+template <int Q>
+__device__ __forceinline__ void cardinal(float t, float* N, float* dN) {
+  if constexpr (Q == 1) {
+    N[0] = 1.0f - t;
+    N[1] = t;
+    dN[0] = -1.0f;
+    dN[1] = 1.0f;
+  } else if constexpr (Q == 2) {
+    const float s = 1.0f - t;
+    N[0] = 0.5f * s * s;
+    N[1] = fmaf(t, s, 0.5f);
+    N[2] = 0.5f * t * t;
+    dN[0] = -s;
+    dN[1] = s - t;
+    dN[2] = t;
+  } else if constexpr (Q == 3) {
+    const float t2 = t * t;
+    const float s = 1.0f - t;
+    const float s2 = s * s;
+    N[0] = s2 * s * (1.0f / 6.0f);
+    N[1] = fmaf(t2, fmaf(t, 0.5f, -1.0f), 2.0f / 3.0f);
+    N[2] = fmaf(t, fmaf(t, fmaf(t, -0.5f, 0.5f), 0.5f), 1.0f / 6.0f);
+    N[3] = t2 * t * (1.0f / 6.0f);
+    dN[0] = -0.5f * s2;
+    dN[1] = t * fmaf(1.5f, t, -2.0f);
+    dN[2] = fmaf(t, fmaf(t, -1.5f, 1.0f), 0.5f);
+    dN[3] = 0.5f * t2;
+  } else {
+    // triangle with the uniform knot differences: left[j] = t + j - 1,
+    // right[j] = j - t, every order-q difference equal to q
+    float left[Q + 1], right[Q + 1], T[Q];
+#pragma unroll
+    for (int j = 1; j <= Q; ++j) {
+      left[j] = t + (float)(j - 1);
+      right[j] = (float)j - t;
+    }
+    N[0] = 1.0f;
+#pragma unroll
+    for (int q = 1; q <= Q; ++q) {
+      float saved = 0.0f;
+#pragma unroll
+      for (int r = 0; r < q; ++r) {
+        const float tmp = N[r] * (1.0f / (float)q);
+        N[r] = fmaf(right[r + 1], tmp, saved);
+        saved = left[q - r] * tmp;
+        if (q == Q) T[r] = tmp;
+      }
+      N[q] = saved;
+    }
+    constexpr float fq = (float)Q;
+    dN[0] = -fq * T[0];
+#pragma unroll
+    for (int r = 1; r < Q; ++r) dN[r] = fq * (T[r - 1] - T[r]);
+    dN[Q] = fq * T[Q - 1];
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void cardinal_window(int q, float t, float (&N)[P + 1],
+                                                float (&dN)[P + 1]) {
+  if (q == P) {
+    cardinal<P>(t, N, dN);
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i <= P; ++i) {
+    N[i] = 0.0f;
+    dN[i] = 0.0f;
+  }
+  if constexpr (P >= 2) {
+    if (q == 1) cardinal<1>(t, N, dN);
+  }
+  if constexpr (P >= 3) {
+    if (q == 2) cardinal<2>(t, N, dN);
+  }
+  if constexpr (P >= 4) {
+    if (q == 3) cardinal<3>(t, N, dN);
+  }
+}
+
 // ---------------------------------------------------------------------------
-// value and gradient query
+// sum-factorised contraction of the (P+1)^3 block
+// ---------------------------------------------------------------------------
+
+// f = sum N^x_a N^y_b N^z_c P_abc and the three derivative sums, x first:
+// each row (b,c) is contracted with N^x and dN^x, then y, then z.
+// fetch(b, c, row) supplies row[a] = P_{a,b,c} of the window.
+template <int P, bool GRAD, class Fetch>
+__device__ __forceinline__ void contract(const float (&N)[3][P + 1], const float (&dN)[3][P + 1],
+                                         Fetch fetch, float& f, float (&g)[3]) {
+  float a0[P + 1][P + 1], a1[P + 1][P + 1];
+#pragma unroll
+  for (int c = 0; c <= P; ++c) {
+#pragma unroll
+    for (int b = 0; b <= P; ++b) {
+      float row[P + 1];
+      fetch(b, c, row);
+      float s0 = N[0][0] * row[0];
+      float s1 = dN[0][0] * row[0];
+#pragma unroll
+      for (int a = 1; a <= P; ++a) {
+        s0 = fmaf(N[0][a], row[a], s0);
+        if (GRAD) s1 = fmaf(dN[0][a], row[a], s1);
+      }
+      a0[c][b] = s0;
+      a1[c][b] = s1;
+    }
+  }
+  float b0[P + 1], bx[P + 1], by[P + 1];
+#pragma unroll
+  for (int c = 0; c <= P; ++c) {
+    float s0 = N[1][0] * a0[c][0];
+    float sx = N[1][0] * a1[c][0];
+    float sy = dN[1][0] * a0[c][0];
+#pragma unroll
+    for (int b = 1; b <= P; ++b) {
+      s0 = fmaf(N[1][b], a0[c][b], s0);
+      if (GRAD) {
+        sx = fmaf(N[1][b], a1[c][b], sx);
+        sy = fmaf(dN[1][b], a0[c][b], sy);
+      }
+    }
+    b0[c] = s0;
+    bx[c] = sx;
+    by[c] = sy;
+  }
+  float v = N[2][0] * b0[0];
+  float gx = N[2][0] * bx[0];
+  float gy = N[2][0] * by[0];
+  float gz = dN[2][0] * b0[0];
+#pragma unroll
+  for (int c = 1; c <= P; ++c) {
+    v = fmaf(N[2][c], b0[c], v);
+    if (GRAD) {
+      gx = fmaf(N[2][c], bx[c], gx);
+      gy = fmaf(N[2][c], by[c], gy);
+      gz = fmaf(dN[2][c], b0[c], gz);
+    }
+  }
+  f = v;
+  g[0] = gx;
+  g[1] = gy;
+  g[2] = gz;
+}
+
+// ---------------------------------------------------------------------------
+// value and gradient query at arbitrary points (global-memory gathers)
 // ---------------------------------------------------------------------------
 
 // Value f and world-space gradient g at parameters u (each in [0,1]).
@@ -236,64 +384,15 @@ __device__ __forceinline__ void query(const ModelDev& m, __amdgpu_buffer_rsrc_t 
     w[k] = s - A.p;
   }
   const int e0 = w[0] + m.nx * w[1] + m.nxy * w[2];
-
-  // x: value weights and d/dx weights for each of the (P+1)^2 rows
-  float a0[P + 1][P + 1], a1[P + 1][P + 1];
-#pragma unroll
-  for (int c = 0; c <= P; ++c) {
-#pragma unroll
-    for (int b = 0; b <= P; ++b) {
-      float row[P + 1];
-      load_row<P, STORE>(rs, e0 + b * m.nx + c * m.nxy, row);
-      float s0 = N[0][0] * row[0];
-      float s1 = dN[0][0] * row[0];
-#pragma unroll
-      for (int a = 1; a <= P; ++a) {
-        s0 = fmaf(N[0][a], row[a], s0);
-        if (GRAD) s1 = fmaf(dN[0][a], row[a], s1);
-      }
-      a0[c][b] = s0;
-      a1[c][b] = s1;
-    }
-  }
-  // y
-  float b0[P + 1], bx[P + 1], by[P + 1];
-#pragma unroll
-  for (int c = 0; c <= P; ++c) {
-    float s0 = N[1][0] * a0[c][0];
-    float sx = N[1][0] * a1[c][0];
-    float sy = dN[1][0] * a0[c][0];
-#pragma unroll
-    for (int b = 1; b <= P; ++b) {
-      s0 = fmaf(N[1][b], a0[c][b], s0);
-      if (GRAD) {
-        sx = fmaf(N[1][b], a1[c][b], sx);
-        sy = fmaf(dN[1][b], a0[c][b], sy);
-      }
-    }
-    b0[c] = s0;
-    bx[c] = sx;
-    by[c] = sy;
-  }
-  // z
-  float v = N[2][0] * b0[0];
-  float gx = N[2][0] * bx[0];
-  float gy = N[2][0] * by[0];
-  float gz = dN[2][0] * b0[0];
-#pragma unroll
-  for (int c = 1; c <= P; ++c) {
-    v = fmaf(N[2][c], b0[c], v);
-    if (GRAD) {
-      gx = fmaf(N[2][c], bx[c], gx);
-      gy = fmaf(N[2][c], by[c], gy);
-      gz = fmaf(dN[2][c], b0[c], gz);
-    }
-  }
-  f = v;
+  const int nx = m.nx, nxy = m.nxy;
+  contract<P, GRAD>(
+      N, dN,
+      [&](int b, int c, float (&row)[P + 1]) { load_row<P, STORE>(rs, e0 + b * nx + c * nxy, row); },
+      f, g);
   if (GRAD) {
-    g[0] = gx * m.ax[0].gscale;
-    g[1] = gy * m.ax[1].gscale;
-    g[2] = gz * m.ax[2].gscale;
+    g[0] *= m.ax[0].gscale;
+    g[1] *= m.ax[1].gscale;
+    g[2] *= m.ax[2].gscale;
   }
 }
 
@@ -387,8 +486,64 @@ __device__ __forceinline__ float ipowf(float x, int k) {
   return r;
 }
 
+// Transfer function, Phong shading and one front-to-back compositing step
+// for a sample of value f and world gradient g.  Returns false once the
+// accumulated opacity exceeds the termination limit.
+template <bool SHADE, class TfFetch>
+__device__ __forceinline__ bool shade_composite(const RenderArgsDev& a, float f, const float (&g)[3],
+                                                float vx, float vy, float vz, TfFetch tf,
+                                                float& cr, float& cg, float& cb, float& A) {
+  float x = (f - a.tf_lo) * a.tf_scale;
+  x = fminf(fmaxf(x, 0.0f), 1.0f) * (float)(a.ntf - 1);
+  const int i = min((int)x, a.ntf - 2);
+  const float t = x - (float)i;
+  const float4 c0 = tf(i);
+  const float4 c1 = tf(i + 1);
+  float sr = fmaf(t, c1.x - c0.x, c0.x);
+  float sg = fmaf(t, c1.y - c0.y, c0.y);
+  float sb = fmaf(t, c1.z - c0.z, c0.z);
+  const float alpha = fmaf(t, c1.w - c0.w, c0.w);
+  if (SHADE) {
+    const float lx = a.light[0], ly = a.light[1], lz = a.light[2];
+    const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    const float inv = (g2 >= 1e-12f) ? rsqrtf(g2) : 1e6f;
+    const float nx = g[0] * inv, ny = g[1] * inv, nz = g[2] * inv;
+    const float ndl = nx * lx + ny * ly + nz * lz;
+    const float diff = fabsf(ndl);
+    const float rx = 2.0f * ndl * nx - lx;
+    const float ry = 2.0f * ndl * ny - ly;
+    const float rz = 2.0f * ndl * nz - lz;
+    const float rv = rx * vx + ry * vy + rz * vz;
+    const float spec = a.ks * ipowf(fmaxf(rv, 0.0f), a.shininess);
+    const float kdiff = a.ka + a.kd * diff;
+    sr = fminf(1.0f, fmaf(kdiff, sr, spec));
+    sg = fminf(1.0f, fmaf(kdiff, sg, spec));
+    sb = fminf(1.0f, fmaf(kdiff, sb, spec));
+  }
+  const float wgt = (1.0f - A) * alpha;
+  cr = fmaf(wgt, sr, cr);
+  cg = fmaf(wgt, sg, cg);
+  cb = fmaf(wgt, sb, cb);
+  A += wgt;
+  return !(A > a.ert);
+}
+
+__device__ __forceinline__ void count_samples(const RenderArgsDev& a, int count, int lane) {
+  if (a.samples != nullptr) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) count += __shfl_xor(count, off, 64);
+    if (lane == 0 && count != 0) atomicAdd(a.samples, (unsigned long long)count);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fallback ray caster: all data from global memory
+// ---------------------------------------------------------------------------
+
+// Used when the knots or transfer function of a request do not fit the LDS
+// budget of the brick kernel.
 template <int P, int STORE, bool SHADE>
-__global__ __launch_bounds__(256) void render_kernel(RenderArgsDev a) {
+__global__ __launch_bounds__(256) void render_global_kernel(RenderArgsDev a) {
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
@@ -401,49 +556,16 @@ __global__ __launch_bounds__(256) void render_kernel(RenderArgsDev a) {
     const Ray ray = make_ray(a, py, px);
     float cr = 0.0f, cg = 0.0f, cb = 0.0f, A = 0.0f;
     const float vx = -(float)ray.d[0], vy = -(float)ray.d[1], vz = -(float)ray.d[2];
-    const float lx = a.light[0], ly = a.light[1], lz = a.light[2];
-    const float tf_max = (float)(a.ntf - 1);
+    const float4* tfp = a.tf;
+    auto tf = [&](int i) { return tfp[i]; };
     int span[3] = {0, 0, 0};
     for (int s = 0; s < ray.nr; ++s) {
       double u[3];
       sample_params(a, ray, s, u);
       float f, g[3];
       query<P, STORE, SHADE>(a.m, rs, u, span, s == 0, f, g);
-      // transfer function: linear interpolation of the RGBA table
-      float x = (f - a.tf_lo) * a.tf_scale;
-      x = fminf(fmaxf(x, 0.0f), 1.0f) * tf_max;
-      const int i = min((int)x, a.ntf - 2);
-      const float t = x - (float)i;
-      const float4 c0 = a.tf[i];
-      const float4 c1 = a.tf[i + 1];
-      float sr = fmaf(t, c1.x - c0.x, c0.x);
-      float sg = fmaf(t, c1.y - c0.y, c0.y);
-      float sb = fmaf(t, c1.z - c0.z, c0.z);
-      const float alpha = fmaf(t, c1.w - c0.w, c0.w);
-      if (SHADE) {
-        const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
-        const float inv = (g2 >= 1e-12f) ? rsqrtf(g2) : 1e6f;
-        const float nx = g[0] * inv, ny = g[1] * inv, nz = g[2] * inv;
-        const float ndl = nx * lx + ny * ly + nz * lz;
-        const float diff = fabsf(ndl);
-        const float rx = 2.0f * ndl * nx - lx;
-        const float ry = 2.0f * ndl * ny - ly;
-        const float rz = 2.0f * ndl * nz - lz;
-        const float rv = rx * vx + ry * vy + rz * vz;
-        const float spec = a.ks * ipowf(fmaxf(rv, 0.0f), a.shininess);
-        const float kdiff = a.ka + a.kd * diff;
-        sr = fminf(1.0f, fmaf(kdiff, sr, spec));
-        sg = fminf(1.0f, fmaf(kdiff, sg, spec));
-        sb = fminf(1.0f, fmaf(kdiff, sb, spec));
-      }
-      // front-to-back compositing, then early termination
-      const float wgt = (1.0f - A) * alpha;
-      cr = fmaf(wgt, sr, cr);
-      cg = fmaf(wgt, sg, cg);
-      cb = fmaf(wgt, sb, cb);
-      A += wgt;
       ++count;
-      if (A > a.ert) break;
+      if (!shade_composite<SHADE>(a, f, g, vx, vy, vz, tf, cr, cg, cb, A)) break;
     }
     float4 o;
     o.x = cr;
@@ -452,11 +574,301 @@ __global__ __launch_bounds__(256) void render_kernel(RenderArgsDev a) {
     o.w = A;
     reinterpret_cast<float4*>(a.out)[(size_t)py * (size_t)a.width + (size_t)px] = o;
   }
-  if (a.samples != nullptr) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) count += __shfl_xor(count, off, 64);
-    if (lane == 0 && count != 0) atomicAdd(a.samples, (unsigned long long)count);
+  count_samples(a, count, lane);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-brick ray caster
+// ---------------------------------------------------------------------------
+
+struct SpanState {
+  int s;      // current span
+  double lo;  // U_s
+  double hi;  // U_{s+1}
+};
+
+// Largest s in [p, n-1] with K[s] <= u by bisection (K in LDS).
+__device__ __forceinline__ int lds_span_search(const double* K, int n, int p, double u) {
+  if (u >= K[n]) return n - 1;
+  int lo = p, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (K[mid] <= u)
+      lo = mid;
+    else
+      hi = mid;
   }
+  return lo;
+}
+
+// Move the cached span to the one of u (a few steps at most between
+// consecutive samples); knots from LDS.
+__device__ __forceinline__ void span_step(const double* K, int n, int p, double u, SpanState& st) {
+  if (u >= st.hi && st.s < n - 1) {
+    do {
+      ++st.s;
+      st.lo = st.hi;
+      st.hi = K[st.s + 1];
+    } while (u >= st.hi && st.s < n - 1);
+  } else if (u < st.lo && st.s > p) {
+    do {
+      --st.s;
+      st.hi = st.lo;
+      st.lo = K[st.s];
+    } while (u < st.lo && st.s > p);
+  }
+}
+
+// Basis window of one axis for the current span.  Uniform knots on an
+// interior span use the cardinal pieces (derivatives in t = u m units);
+// otherwise the triangle with the span's reciprocal table (derivatives in
+// u units, rescaled to t units for uniform models so that one gradient
+// factor per axis applies).
+template <int P, bool UNIFORM>
+__device__ __forceinline__ void axis_weights(const AxisDev& A, const SpanState& st, double u,
+                                             float (&N)[P + 1], float (&dN)[P + 1]) {
+  const int q = A.p;
+  if constexpr (UNIFORM) {
+    if (st.s >= 2 * q - 1 && st.s <= A.n - q) {
+      const float t = (float)((u - st.lo) * A.m);
+      cardinal_window<P>(q, t, N, dN);
+      return;
+    }
+  }
+  const float d = (float)(u - st.lo);
+  const float* row = A.tab + (size_t)(st.s - q) * (size_t)table_stride(q);
+  axis_basis<P>(q, row, d, N, dN);
+  if constexpr (UNIFORM) {
+#pragma unroll
+    for (int i = 0; i <= P; ++i) dN[i] *= A.inv_m;
+  }
+}
+
+__device__ __forceinline__ float wave_minf(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ float wave_maxf(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// a / b for 0 <= a < 2^22, b >= 1, with inv_b ~ 1/b: float estimate plus
+// one correction step.
+__device__ __forceinline__ int div_small(int a, int b, float inv_b) {
+  int q = (int)((float)a * inv_b);
+  const int r = a - q * b;
+  q += (r >= b) ? 1 : 0;
+  q -= (r < 0) ? 1 : 0;
+  return q;
+}
+
+// One 256-thread workgroup renders a 16x16 pixel tile; each wave owns an
+// 8x8 sub-tile and marches its 64 rays in rounds of `spr` samples.  Before a
+// round the wave stages, into its own LDS brick, every control point that
+// the windows of its active rays can touch during the round (the box of
+// spans between the smallest and largest parameters of the round's first
+// and last samples); the round's samples then gather from LDS.  If the box
+// exceeds the brick capacity the round gathers from global memory.  Waves
+// never wait for each other after the initial load of the transfer
+// function and knots.
+template <int P, int STORE, bool SHADE, bool UNIFORM>
+__global__ __launch_bounds__(256) void render_brick_kernel(RenderArgsDev a) {
+  extern __shared__ float4 lds4[];
+  char* lds = reinterpret_cast<char*>(lds4);
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+
+  // transfer function and knots, shared by the four waves
+  float4* tf_lds = lds4;
+  for (int i = tid; i < a.ntf; i += 256) tf_lds[i] = a.tf[i];
+  double* knots = reinterpret_cast<double*>(lds + a.lds_knots);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int nk = a.m.ax[k].n + a.m.ax[k].p + 1;
+    for (int i = tid; i < nk; i += 256) knots[a.knot_off[k] + i] = a.m.ax[k].knots[i];
+  }
+  __syncthreads();
+  float* brick = reinterpret_cast<float*>(lds + a.lds_bricks) + wave * a.brick_cap;
+  const double* K[3] = {knots + a.knot_off[0], knots + a.knot_off[1], knots + a.knot_off[2]};
+  auto tf = [&](int i) { return tf_lds[i]; };
+
+  const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
+  const int py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
+  const bool inside = px < a.width && py < a.height;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.m.ctrl, a.m.ctrl_bytes);
+
+  int nr = 0;
+  double ua[3] = {0.0, 0.0, 0.0}, ub[3] = {0.0, 0.0, 0.0};
+  float vx = 0.0f, vy = 0.0f, vz = 0.0f;
+  if (inside) {
+    const Ray ray = make_ray(a, py, px);
+    nr = ray.nr;
+    // u_k(s) = ua_k + s ub_k: the sample parameters as an affine function
+    // of the sample index
+    const double t_half = ray.t0 + 0.5 * a.step;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ua[k] = (ray.o[k] + t_half * ray.d[k] - a.m.ax[k].lo) * a.m.ax[k].inv_ext;
+      ub[k] = a.step * ray.d[k] * a.m.ax[k].inv_ext;
+    }
+    vx = -(float)ray.d[0];
+    vy = -(float)ray.d[1];
+    vz = -(float)ray.d[2];
+  }
+  auto param = [&](int s, int k) {
+    return fmin(fmax(fma((double)s, ub[k], ua[k]), 0.0), 1.0);
+  };
+
+  SpanState st[3];
+  bool alive = nr > 0;
+  if (alive) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double u = param(0, k);
+      st[k].s = lds_span_search(K[k], a.m.ax[k].n, a.m.ax[k].p, u);
+      st[k].lo = K[k][st[k].s];
+      st[k].hi = K[k][st[k].s + 1];
+    }
+  }
+  float cr = 0.0f, cg = 0.0f, cb = 0.0f, A = 0.0f;
+  int count = 0;
+  const int nx = a.m.nx, nxy = a.m.nxy;
+  const int S = a.spr;
+  float gfac[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    gfac[k] = UNIFORM ? a.m.ax[k].gscale * (float)a.m.ax[k].m : a.m.ax[k].gscale;
+
+  for (int s0 = 0;; s0 += S) {
+    if (!__any(alive)) break;
+    const int s1 = alive ? min(s0 + S, nr) : s0;
+    // parameter box of the round
+    float lo_f[3], hi_f[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float l = 2.0f, h = -1.0f;
+      if (alive) {
+        const double u0 = param(s0, k), u1 = param(s1 - 1, k);
+        l = (float)fmin(u0, u1) - 1e-6f;
+        h = (float)fmax(u0, u1) + 1e-6f;
+      }
+      lo_f[k] = wave_minf(l);
+      hi_f[k] = wave_maxf(h);
+    }
+    // windows of the spans of the box corners
+    int blo[3], bext[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const AxisDev& Ax = a.m.ax[k];
+      const double ul = fmin(fmax((double)lo_f[k], 0.0), 1.0);
+      const double uh = fmin(fmax((double)hi_f[k], 0.0), 1.0);
+      int sl, sh;
+      if constexpr (UNIFORM) {
+        // span estimate from u m, corrected by one step against the knots
+        const int m = Ax.n - Ax.p;
+        sl = Ax.p + min(max((int)(ul * Ax.m), 0), m - 1);
+        sh = Ax.p + min(max((int)(uh * Ax.m), 0), m - 1);
+        if (sl > Ax.p && K[k][sl] > ul) --sl;
+        if (sl < Ax.n - 1 && K[k][sl + 1] <= ul) ++sl;
+        if (sh > Ax.p && K[k][sh] > uh) --sh;
+        if (sh < Ax.n - 1 && K[k][sh + 1] <= uh) ++sh;
+      } else {
+        sl = lds_span_search(K[k], Ax.n, Ax.p, ul);
+        sh = lds_span_search(K[k], Ax.n, Ax.p, uh);
+      }
+      blo[k] = uniform_i(sl - Ax.p);
+      bext[k] = uniform_i(sh - sl + P + 1);
+    }
+    const int pitch_y = (bext[0] + 3) & ~3;
+    const int pitch_z = pitch_y * bext[1];
+    const int nel = pitch_z * bext[2];
+    const bool fits = nel <= a.brick_cap;
+
+    if (fits) {
+      // stage the brick, four consecutive x values per lane and step
+      const int gx = pitch_y >> 2;
+      const int gxy = gx * bext[1];
+      const int ngroups = gxy * bext[2];
+      const float inv_gx = 1.0f / (float)gx;
+      const float inv_gxy = 1.0f / (float)gxy;
+      for (int gi = lane; gi < ngroups; gi += 64) {
+        const int kz = div_small(gi, gxy, inv_gxy);
+        const int rem = gi - kz * gxy;
+        const int jy = div_small(rem, gx, inv_gx);
+        const int ix4 = rem - jy * gx;
+        const int g = (blo[0] + 4 * ix4) + nx * (blo[1] + jy) + nxy * (blo[2] + kz);
+        float v[4];
+        load_row<3, STORE>(rs, g, v);
+        float4 w;
+        w.x = v[0];
+        w.y = v[1];
+        w.z = v[2];
+        w.w = v[3];
+        *reinterpret_cast<float4*>(brick + 4 * ix4 + pitch_y * jy + pitch_z * kz) = w;
+      }
+    }
+    const int emax = nel - 1 - (P + P * pitch_y + P * pitch_z);
+
+    for (int s = s0; s < s1; ++s) {
+      float N[3][P + 1], dN[3][P + 1];
+      int w[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const AxisDev& Ax = a.m.ax[k];
+        const double u = param(s, k);
+        span_step(K[k], Ax.n, Ax.p, u, st[k]);
+        axis_weights<P, UNIFORM>(Ax, st[k], u, N[k], dN[k]);
+        w[k] = st[k].s - Ax.p;
+      }
+      float f, g[3];
+      if (fits) {
+        int e0 = (w[0] - blo[0]) + pitch_y * (w[1] - blo[1]) + pitch_z * (w[2] - blo[2]);
+        e0 = min(max(e0, 0), emax);
+        contract<P, SHADE>(
+            N, dN,
+            [&](int b, int c, float (&row)[P + 1]) {
+              const float* r = brick + e0 + b * pitch_y + c * pitch_z;
+#pragma unroll
+              for (int i = 0; i <= P; ++i) row[i] = r[i];
+            },
+            f, g);
+      } else {
+        const int e0 = w[0] + nx * w[1] + nxy * w[2];
+        contract<P, SHADE>(
+            N, dN,
+            [&](int b, int c, float (&row)[P + 1]) {
+              load_row<P, STORE>(rs, e0 + b * nx + c * nxy, row);
+            },
+            f, g);
+      }
+      if (SHADE) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g[k] *= gfac[k];
+      }
+      ++count;
+      if (!shade_composite<SHADE>(a, f, g, vx, vy, vz, tf, cr, cg, cb, A)) {
+        alive = false;
+        break;
+      }
+    }
+    if (s1 >= nr) alive = false;
+  }
+  if (inside) {
+    float4 o;
+    o.x = cr;
+    o.y = cg;
+    o.z = cb;
+    o.w = A;
+    reinterpret_cast<float4*>(a.out)[(size_t)py * (size_t)a.width + (size_t)px] = o;
+  }
+  count_samples(a, count, lane);
 }
 
 template <int P, int STORE, bool GRAD>
@@ -486,14 +898,23 @@ __global__ void zero_counter(unsigned long long* p) {
   if (threadIdx.x == 0) p[0] = 0ull;
 }
 
+template <int P, int STORE, bool SHADE>
+hipError_t launch_render_ps(const RenderArgsDev& a, hipStream_t st) {
+  const dim3 grid((a.width + 15) / 16, (a.height + 15) / 16);
+  if (a.lds_bytes > 0) {
+    if (a.m.uniform)
+      render_brick_kernel<P, STORE, SHADE, true><<<grid, 256, a.lds_bytes, st>>>(a);
+    else
+      render_brick_kernel<P, STORE, SHADE, false><<<grid, 256, a.lds_bytes, st>>>(a);
+  } else {
+    render_global_kernel<P, STORE, SHADE><<<grid, 256, 0, st>>>(a);
+  }
+  return hipGetLastError();
+}
+
 template <int P, int STORE>
 hipError_t launch_render_p(const RenderArgsDev& a, hipStream_t st) {
-  const dim3 grid((a.width + 15) / 16, (a.height + 15) / 16);
-  if (a.shading)
-    render_kernel<P, STORE, true><<<grid, 256, 0, st>>>(a);
-  else
-    render_kernel<P, STORE, false><<<grid, 256, 0, st>>>(a);
-  return hipGetLastError();
+  return a.shading ? launch_render_ps<P, STORE, true>(a, st) : launch_render_ps<P, STORE, false>(a, st);
 }
 
 template <int P, int STORE>

@@ -34,8 +34,9 @@ struct AxisDev {
   int32_t p;
   double lo;            // box corner along this axis
   double inv_ext;       // 1 / (hi - lo): u = (x - lo) * inv_ext
+  double m;             // number of knot spans n - p (as FP64)
   float gscale;         // 1 / (hi - lo) in FP32, world-gradient factor
-  int32_t reserved;
+  float inv_m;          // 1 / (n - p) in FP32
 };
 
 struct ModelDev {
@@ -46,7 +47,7 @@ struct ModelDev {
   int32_t nx;           // row stride (elements)
   int32_t nxy;          // slice stride (elements)
   int32_t pmax;         // largest degree; kernels are instantiated for it
-  int32_t reserved;
+  int32_t uniform;      // 1: every axis has knots U_{p+k} = k/(n-p) exactly
 };
 
 struct RenderArgsDev {
@@ -71,6 +72,13 @@ struct RenderArgsDev {
   int32_t reserved;
   float* out;           // width*height*4
   unsigned long long* samples;  // nullable
+  // LDS-brick ray marcher (render_brick_kernel); unused by the fallback
+  int32_t spr;          // samples per round: each wave stages one brick per round
+  int32_t brick_cap;    // floats of LDS per wave for its brick (multiple of 4)
+  int32_t lds_knots;    // byte offset of the knot vectors in dynamic LDS
+  int32_t lds_bricks;   // byte offset of the bricks in dynamic LDS
+  int32_t knot_off[3];  // offset (in doubles) of each axis' knots in LDS
+  int32_t lds_bytes;    // dynamic LDS size of one workgroup
 };
 
 struct EvalArgsDev {

@@ -233,3 +233,35 @@ def test_c3_subset(mfa, c3, store):
             assert rep.rmse <= BF16_RMSE
     finally:
         b.mfa_model_free(ctx, h)
+
+
+@pytest.mark.parametrize("variant", ["large_tf", "coarse_step"])
+@pytest.mark.parametrize("store", [0, 1])
+def test_fallback_paths(mfa, variant, store):
+    """A 2048-entry table leaves no LDS room for bricks (global-memory
+    kernel); a step of several knot spans makes every round's brick exceed
+    its capacity (rounds gather from global memory)."""
+    rng = np.random.default_rng(31)
+    if variant == "large_tf":
+        spec = wl.random_model(rng, n=(14, 12, 13), degree=(3, 3, 3))
+        P = np.asarray(spec.ctrl)
+        tf = wl.pwl_tf(7, P.min(), P.max(), n=2048, alpha_max=0.1)
+        step = 1 / 90
+    else:
+        spec = wl.random_model(rng, n=(160, 150, 170), degree=(2, 3, 2), smooth=True)
+        P = np.asarray(spec.ctrl)
+        tf = wl.pwl_tf(8, P.min(), P.max(), alpha_max=0.1)
+        step = 1 / 12
+    cam = wl.orbit_camera(45, 38, 40.0, 25.0)
+    wk = wl.Workload(variant, spec, cam, tf, wl.ParamSpec(step=step))
+    b, ctx = mfa
+    h = b.mfa_model_upload(ctx, spec, store)
+    try:
+        img, cnt = gpu_render(b, ctx, h, wk)
+        model = None if store == 0 else oracle_model(spec, ctrl=quant.dequant_bf16(spec.ctrl))
+        rep = compare_image(img, cnt, wk, np.arange(45 * 38), TAU32, PX32, model=model)
+        _report(f"{variant} store={store}", rep)
+        assert rep.rmse <= FP32_RMSE and rep.n_bad == 0
+        _check_counts(rep, True)
+    finally:
+        b.mfa_model_free(ctx, h)
