@@ -355,6 +355,10 @@ struct mfa_ctx {
   std::unordered_map<int64_t, DeviceModel> models;
   std::unordered_map<uint64_t, std::vector<TFEntry>> tfs;
   size_t n_tf = 0;
+  // tile-queue scratch of the persistent render kernel: cost and order
+  // arrays of `scratch_tiles` entries each, then the queue counter
+  void* scratch = nullptr;
+  int64_t scratch_tiles = 0;
 
   void free_tfs() {
     for (auto& kv : tfs)
@@ -401,6 +405,29 @@ mfa_status tf_device(mfa_ctx* ctx, const mfa_tf* tf, float4** out) {
   *out = ent.dev;
   ctx->tfs[h].push_back(std::move(ent));
   ctx->n_tf += 1;
+  return MFA_OK;
+}
+
+// Grow the tile-queue scratch to `tiles` entries.  An older, smaller buffer
+// may still be read by enqueued kernels, so the device is synchronised
+// before it is released.
+mfa_status ensure_scratch(mfa_ctx* ctx, int64_t tiles) {
+  if (ctx->scratch != nullptr && ctx->scratch_tiles >= tiles) return MFA_OK;
+  if (ctx->scratch != nullptr) {
+    const hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("hipDeviceSynchronize", e));
+    (void)hipFree(ctx->scratch);
+    ctx->scratch = nullptr;
+    ctx->scratch_tiles = 0;
+  }
+  const size_t bytes = size_t(tiles) * 8 + 256;
+  const hipError_t e = hipMalloc(&ctx->scratch, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->scratch = nullptr;
+    return fail(MFA_ERR_NOMEM, hip_msg("hipMalloc (tile queue)", e));
+  }
+  ctx->scratch_tiles = tiles;
   return MFA_OK;
 }
 
@@ -455,6 +482,8 @@ mfa_status mfa_destroy(mfa_ctx* ctx) {
     for (auto& kv : ctx->models) (void)hipFree(kv.second.mem);
     ctx->models.clear();
     ctx->free_tfs();
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    ctx->scratch = nullptr;
   }
   delete ctx;
   return st;
@@ -622,23 +651,28 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const 
   a.width = cam->width;
   a.height = cam->height;
   a.ntf = tf->n;
+  mfa::CamParams& c = a.cam;
+  c.kind = cam->kind;
+  c.width = cam->width;
+  c.height = cam->height;
   for (int k = 0; k < 3; ++k) {
-    a.eye[k] = cam->eye[k];
-    a.F[k] = fr.F[k];
-    a.R[k] = fr.R[k];
-    a.V[k] = fr.V[k];
-    a.lo[k] = dm.lo[k];
-    a.hi[k] = dm.hi[k];
+    c.eye[k] = cam->eye[k];
+    c.F[k] = fr.F[k];
+    c.R[k] = fr.R[k];
+    c.V[k] = fr.V[k];
+    c.lo[k] = dm.lo[k];
+    c.hi[k] = dm.hi[k];
+    c.inv_ext[k] = dm.md.ax[k].inv_ext;
   }
   if (cam->kind == MFA_CAMERA_ORTHO) {
-    a.cam0 = cam->ortho_half_w;
-    a.cam1 = cam->ortho_half_h;
+    c.cam0 = cam->ortho_half_w;
+    c.cam1 = cam->ortho_half_h;
   } else {
     const double half = cam->fov_y_deg * (M_PI / 180.0) * 0.5;
-    a.cam0 = std::tan(half);
-    a.cam1 = double(cam->width) / double(cam->height);
+    c.cam0 = std::tan(half);
+    c.cam1 = double(cam->width) / double(cam->height);
   }
-  a.step = prm->step;
+  c.step = prm->step;
   a.tf = tf_dev;
   a.tf_lo = float(tf->v_lo);
   a.tf_scale = float(1.0 / (tf->v_hi - tf->v_lo));
@@ -658,6 +692,16 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const 
   a.out = rgba_dev;
   a.samples = reinterpret_cast<unsigned long long*>(samples_dev);
   plan_bricks(dm, tf->n, prm->step, a);
+  if (a.lds_bytes > 0) {
+    const int64_t tiles = int64_t((cam->width + 7) / 8) * int64_t((cam->height + 7) / 8);
+    st = ensure_scratch(ctx, tiles);
+    if (st != MFA_OK) return st;
+    int32_t* base = static_cast<int32_t*>(ctx->scratch);
+    a.ntiles = int32_t(tiles);
+    a.tile_cost = base;
+    a.tile_order = base + ctx->scratch_tiles;
+    a.tile_counter = reinterpret_cast<unsigned*>(base + 2 * ctx->scratch_tiles);
+  }
   const hipError_t e = mfa::launch_render(a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("render launch", e));
   return MFA_OK;

@@ -411,7 +411,7 @@ struct Ray {
 // Plain FP64 operations in the stated order (no contraction), so that the
 // entry parameter and the sample count are the IEEE results of the
 // defining formulas.
-__device__ __forceinline__ Ray make_ray(const RenderArgsDev& a, int r, int c) {
+__device__ __forceinline__ Ray make_ray(const CamParams& a, int r, int c) {
 #pragma clang fp contract(off)
   Ray ray;
   const double W = (double)a.width;
@@ -464,14 +464,14 @@ __device__ __forceinline__ Ray make_ray(const RenderArgsDev& a, int r, int c) {
 
 // Parameters of sample s: u = clamp((o + t d - lo) / (hi - lo), 0, 1),
 // t = t0 + (s + 1/2) step, with the same unfused operations.
-__device__ __forceinline__ void sample_params(const RenderArgsDev& a, const Ray& ray, int s,
+__device__ __forceinline__ void sample_params(const CamParams& a, const Ray& ray, int s,
                                               double (&u)[3]) {
 #pragma clang fp contract(off)
   const double t = ray.t0 + ((double)s + 0.5) * a.step;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const double x = ray.o[k] + t * ray.d[k];
-    const double v = (x - a.m.ax[k].lo) * a.m.ax[k].inv_ext;
+    const double v = (x - a.lo[k]) * a.inv_ext[k];
     u[k] = fmin(fmax(v, 0.0), 1.0);
   }
 }
@@ -553,7 +553,7 @@ __global__ __launch_bounds__(256) void render_global_kernel(RenderArgsDev a) {
   int count = 0;
   if (inside) {
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.m.ctrl, a.m.ctrl_bytes);
-    const Ray ray = make_ray(a, py, px);
+    const Ray ray = make_ray(a.cam, py, px);
     float cr = 0.0f, cg = 0.0f, cb = 0.0f, A = 0.0f;
     const float vx = -(float)ray.d[0], vy = -(float)ray.d[1], vz = -(float)ray.d[2];
     const float4* tfp = a.tf;
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(256) void render_global_kernel(RenderArgsDev a) {
     int span[3] = {0, 0, 0};
     for (int s = 0; s < ray.nr; ++s) {
       double u[3];
-      sample_params(a, ray, s, u);
+      sample_params(a.cam, ray, s, u);
       float f, g[3];
       query<P, STORE, SHADE>(a.m, rs, u, span, s == 0, f, g);
       ++count;
@@ -668,17 +668,20 @@ __device__ __forceinline__ int div_small(int a, int b, float inv_b) {
   return q;
 }
 
-// One 256-thread workgroup renders a 16x16 pixel tile; each wave owns an
-// 8x8 sub-tile and marches its 64 rays in rounds of `spr` samples.  Before a
-// round the wave stages, into its own LDS brick, every control point that
-// the windows of its active rays can touch during the round (the box of
-// spans between the smallest and largest parameters of the round's first
-// and last samples); the round's samples then gather from LDS.  If the box
-// exceeds the brick capacity the round gathers from global memory.  Waves
-// never wait for each other after the initial load of the transfer
-// function and knots.
+// Ray caster over 8x8 pixel tiles, one tile per wave.  Workgroup b renders
+// entries 4b..4b+3 of a tile list sorted by decreasing estimated work, and
+// the hardware starts workgroups in index order, so the longest rays start
+// first.  A wave marches its 64 rays in rounds of `spr` samples.  Before a
+// round it stages, into its own LDS brick, every control point that the
+// windows of its active rays can touch during the round (the box of spans
+// between the smallest and largest parameters of the round's first and last
+// samples); the round's samples then gather from LDS.  If the box exceeds
+// the brick capacity the round gathers from global memory.  The four waves
+// of a workgroup share the transfer function and knots in LDS and never
+// wait for each other after loading them.  Which wave renders which tile
+// does not change any pixel: the arithmetic of a ray depends only on the ray.
 template <int P, int STORE, bool SHADE, bool UNIFORM>
-__global__ __launch_bounds__(256) void render_brick_kernel(RenderArgsDev a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void render_brick_kernel(RenderArgsDev a) {
   extern __shared__ float4 lds4[];
   char* lds = reinterpret_cast<char*>(lds4);
   const int tid = threadIdx.x;
@@ -699,24 +702,35 @@ __global__ __launch_bounds__(256) void render_brick_kernel(RenderArgsDev a) {
   const double* K[3] = {knots + a.knot_off[0], knots + a.knot_off[1], knots + a.knot_off[2]};
   auto tf = [&](int i) { return tf_lds[i]; };
 
-  const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
-  const int py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
-  const bool inside = px < a.width && py < a.height;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.m.ctrl, a.m.ctrl_bytes);
+  const int ntx = (a.width + 7) >> 3;
+  const int nx = a.m.nx, nxy = a.m.nxy;
+  const int S = a.spr;
+  float gfac[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    gfac[k] = UNIFORM ? a.m.ax[k].gscale * (float)a.m.ax[k].m : a.m.ax[k].gscale;
+  int count = 0;
 
+  const int ti = blockIdx.x * 4 + wave;
+  const int tile = ti < a.ntiles ? uniform_i(a.tile_order[ti]) : 0;
+  const int px = (tile % ntx) * 8 + (lane & 7);
+  const int py = (tile / ntx) * 8 + (lane >> 3);
+  const bool inside = ti < a.ntiles && px < a.width && py < a.height;
+
+  // u_k(s) = ua_k + s ub_k: the sample parameters as an affine function of
+  // the sample index
   int nr = 0;
   double ua[3] = {0.0, 0.0, 0.0}, ub[3] = {0.0, 0.0, 0.0};
   float vx = 0.0f, vy = 0.0f, vz = 0.0f;
   if (inside) {
-    const Ray ray = make_ray(a, py, px);
+    const Ray ray = make_ray(a.cam, py, px);
     nr = ray.nr;
-    // u_k(s) = ua_k + s ub_k: the sample parameters as an affine function
-    // of the sample index
-    const double t_half = ray.t0 + 0.5 * a.step;
+    const double t_half = ray.t0 + 0.5 * a.cam.step;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      ua[k] = (ray.o[k] + t_half * ray.d[k] - a.m.ax[k].lo) * a.m.ax[k].inv_ext;
-      ub[k] = a.step * ray.d[k] * a.m.ax[k].inv_ext;
+      ua[k] = (ray.o[k] + t_half * ray.d[k] - a.cam.lo[k]) * a.cam.inv_ext[k];
+      ub[k] = a.cam.step * ray.d[k] * a.cam.inv_ext[k];
     }
     vx = -(float)ray.d[0];
     vy = -(float)ray.d[1];
@@ -738,13 +752,6 @@ __global__ __launch_bounds__(256) void render_brick_kernel(RenderArgsDev a) {
     }
   }
   float cr = 0.0f, cg = 0.0f, cb = 0.0f, A = 0.0f;
-  int count = 0;
-  const int nx = a.m.nx, nxy = a.m.nxy;
-  const int S = a.spr;
-  float gfac[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-    gfac[k] = UNIFORM ? a.m.ax[k].gscale * (float)a.m.ax[k].m : a.m.ax[k].gscale;
 
   for (int s0 = 0;; s0 += S) {
     if (!__any(alive)) break;
@@ -871,6 +878,53 @@ __global__ __launch_bounds__(256) void render_brick_kernel(RenderArgsDev a) {
   count_samples(a, count, lane);
 }
 
+// Work estimate of every 8x8 tile for the queue order: the largest sample
+// count among the tile's corner and centre rays.
+__global__ __launch_bounds__(256) void plan_cost_kernel(RenderArgsDev a) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.ntiles) return;
+  const int ntx = (a.width + 7) >> 3;
+  const int x0 = (t % ntx) * 8, y0 = (t / ntx) * 8;
+  const int x1 = min(x0 + 7, a.width - 1), y1 = min(y0 + 7, a.height - 1);
+  int c = make_ray(a.cam, y0, x0).nr;
+  c = max(c, make_ray(a.cam, y0, x1).nr);
+  c = max(c, make_ray(a.cam, y1, x0).nr);
+  c = max(c, make_ray(a.cam, y1, x1).nr);
+  c = max(c, make_ray(a.cam, (y0 + y1) >> 1, (x0 + x1) >> 1).nr);
+  a.tile_cost[t] = c;
+}
+
+// Tile queue in decreasing order of estimated work (256 buckets; order
+// within a bucket is arbitrary), and a zeroed queue counter.
+__global__ __launch_bounds__(1024) void plan_order_kernel(const int* cost, int n, int* order,
+                                                          unsigned* counter) {
+  __shared__ unsigned hist[256];
+  __shared__ int cmax;
+  const int tid = threadIdx.x;
+  if (tid < 256) hist[tid] = 0u;
+  if (tid == 0) cmax = 0;
+  __syncthreads();
+  int m = 0;
+  for (int i = tid; i < n; i += 1024) m = max(m, cost[i]);
+  atomicMax(&cmax, m);
+  __syncthreads();
+  const long long denom = (long long)cmax + 1;
+  auto bucket = [&](int c) { return 255 - (int)(((long long)c * 256) / denom); };
+  for (int i = tid; i < n; i += 1024) atomicAdd(&hist[bucket(cost[i])], 1u);
+  __syncthreads();
+  if (tid == 0) {
+    unsigned run = 0;
+    for (int b = 0; b < 256; ++b) {
+      const unsigned h = hist[b];
+      hist[b] = run;
+      run += h;
+    }
+    *counter = 0u;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += 1024) order[atomicAdd(&hist[bucket(cost[i])], 1u)] = i;
+}
+
 template <int P, int STORE, bool GRAD>
 __global__ __launch_bounds__(256) void eval_kernel(EvalArgsDev a) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -898,17 +952,22 @@ __global__ void zero_counter(unsigned long long* p) {
   if (threadIdx.x == 0) p[0] = 0ull;
 }
 
+template <int P, int STORE, bool SHADE, bool UNIFORM>
+hipError_t launch_brick(const RenderArgsDev& a, hipStream_t st) {
+  plan_cost_kernel<<<(a.ntiles + 255) / 256, 256, 0, st>>>(a);
+  plan_order_kernel<<<1, 1024, 0, st>>>(a.tile_cost, a.ntiles, a.tile_order, a.tile_counter);
+  render_brick_kernel<P, STORE, SHADE, UNIFORM><<<(a.ntiles + 3) / 4, 256, a.lds_bytes, st>>>(a);
+  return hipGetLastError();
+}
+
 template <int P, int STORE, bool SHADE>
 hipError_t launch_render_ps(const RenderArgsDev& a, hipStream_t st) {
-  const dim3 grid((a.width + 15) / 16, (a.height + 15) / 16);
   if (a.lds_bytes > 0) {
-    if (a.m.uniform)
-      render_brick_kernel<P, STORE, SHADE, true><<<grid, 256, a.lds_bytes, st>>>(a);
-    else
-      render_brick_kernel<P, STORE, SHADE, false><<<grid, 256, a.lds_bytes, st>>>(a);
-  } else {
-    render_global_kernel<P, STORE, SHADE><<<grid, 256, 0, st>>>(a);
+    return a.m.uniform ? launch_brick<P, STORE, SHADE, true>(a, st)
+                       : launch_brick<P, STORE, SHADE, false>(a, st);
   }
+  const dim3 grid((a.width + 15) / 16, (a.height + 15) / 16);
+  render_global_kernel<P, STORE, SHADE><<<grid, 256, 0, st>>>(a);
   return hipGetLastError();
 }
 

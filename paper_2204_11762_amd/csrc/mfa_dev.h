@@ -50,17 +50,27 @@ struct ModelDev {
   int32_t uniform;      // 1: every axis has knots U_{p+k} = k/(n-p) exactly
 };
 
-struct RenderArgsDev {
-  ModelDev m;
-  int32_t kind;         // 0 ortho, 1 perspective
-  int32_t width;
-  int32_t height;
-  int32_t ntf;          // transfer-function entries
+// Camera, box and step: everything the ray setup of a pixel reads.
+struct CamParams {
   double eye[3];
   double F[3], R[3], V[3];
   double cam0, cam1;    // ortho: half_w, half_h; perspective: tan(fov/2), W/H
-  double lo[3], hi[3];
+  double lo[3], hi[3];  // box
+  double inv_ext[3];    // 1 / (hi - lo)
   double step;
+  int32_t kind;         // 0 ortho, 1 perspective
+  int32_t width;
+  int32_t height;
+  int32_t reserved;
+};
+
+struct RenderArgsDev {
+  ModelDev m;
+  CamParams cam;
+  int32_t width;
+  int32_t height;
+  int32_t ntf;          // transfer-function entries
+  int32_t kind;
   const float4* tf;     // ntf RGBA entries
   float tf_lo;          // x = (f - tf_lo) * tf_scale, clamped to [0,1]
   float tf_scale;
@@ -79,6 +89,10 @@ struct RenderArgsDev {
   int32_t lds_bricks;   // byte offset of the bricks in dynamic LDS
   int32_t knot_off[3];  // offset (in doubles) of each axis' knots in LDS
   int32_t lds_bytes;    // dynamic LDS size of one workgroup
+  int32_t ntiles;       // 8x8 pixel tiles of the image
+  int32_t* tile_cost;   // ntiles work estimates (scratch)
+  int32_t* tile_order;  // ntiles tile indices, longest first (scratch)
+  unsigned* tile_counter;  // queue head (scratch, zeroed before the render kernel)
 };
 
 struct EvalArgsDev {
