@@ -310,7 +310,7 @@ void plan_bricks(const DeviceModel& dm, int ntf, double step, mfa::RenderArgsDev
     const double span_len = (dm.hi[k] - dm.lo[k]) / dm.md.ax[k].m;
     cells = std::max(cells, step / span_len);
   }
-  const int spr = cells > 0.0 ? int(3.0 / cells) : 64;
+  const int spr = cells > 0.0 ? int(3.0 * mfa::kLanesPerRay / cells) : 64;
   a.spr = std::max(4, std::min(64, spr));
 }
 
@@ -693,7 +693,10 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const 
   a.samples = reinterpret_cast<unsigned long long*>(samples_dev);
   plan_bricks(dm, tf->n, prm->step, a);
   if (a.lds_bytes > 0) {
-    const int64_t tiles = int64_t((cam->width + 7) / 8) * int64_t((cam->height + 7) / 8);
+    const int64_t tiles = int64_t((cam->width + mfa::kTileW - 1) / mfa::kTileW) *
+                          int64_t((cam->height + mfa::kTileH - 1) / mfa::kTileH);
+    a.tile_w = mfa::kTileW;
+    a.tile_h = mfa::kTileH;
     st = ensure_scratch(ctx, tiles);
     if (st != MFA_OK) return st;
     int32_t* base = static_cast<int32_t*>(ctx->scratch);

@@ -486,6 +486,53 @@ __device__ __forceinline__ float ipowf(float x, int k) {
   return r;
 }
 
+// Transfer function and Phong shading of a sample of value f and world
+// gradient g: shaded colour (sr, sg, sb) and opacity alpha.
+template <bool SHADE, class TfFetch>
+__device__ __forceinline__ void shade_sample(const RenderArgsDev& a, float f, const float (&g)[3],
+                                             float vx, float vy, float vz, TfFetch tf, float& sr,
+                                             float& sg, float& sb, float& alpha) {
+  float x = (f - a.tf_lo) * a.tf_scale;
+  x = fminf(fmaxf(x, 0.0f), 1.0f) * (float)(a.ntf - 1);
+  const int i = min((int)x, a.ntf - 2);
+  const float t = x - (float)i;
+  const float4 c0 = tf(i);
+  const float4 c1 = tf(i + 1);
+  sr = fmaf(t, c1.x - c0.x, c0.x);
+  sg = fmaf(t, c1.y - c0.y, c0.y);
+  sb = fmaf(t, c1.z - c0.z, c0.z);
+  alpha = fmaf(t, c1.w - c0.w, c0.w);
+  if (SHADE) {
+    const float lx = a.light[0], ly = a.light[1], lz = a.light[2];
+    const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    const float inv = (g2 >= 1e-12f) ? rsqrtf(g2) : 1e6f;
+    const float nx = g[0] * inv, ny = g[1] * inv, nz = g[2] * inv;
+    const float ndl = nx * lx + ny * ly + nz * lz;
+    const float diff = fabsf(ndl);
+    const float rx = 2.0f * ndl * nx - lx;
+    const float ry = 2.0f * ndl * ny - ly;
+    const float rz = 2.0f * ndl * nz - lz;
+    const float rv = rx * vx + ry * vy + rz * vz;
+    const float spec = a.ks * ipowf(fmaxf(rv, 0.0f), a.shininess);
+    const float kdiff = a.ka + a.kd * diff;
+    sr = fminf(1.0f, fmaf(kdiff, sr, spec));
+    sg = fminf(1.0f, fmaf(kdiff, sg, spec));
+    sb = fminf(1.0f, fmaf(kdiff, sb, spec));
+  }
+}
+
+// One front-to-back compositing step; false once the accumulated opacity
+// exceeds the termination limit.
+__device__ __forceinline__ bool composite_one(float ert, float sr, float sg, float sb, float alpha,
+                                              float& cr, float& cg, float& cb, float& A) {
+  const float wgt = (1.0f - A) * alpha;
+  cr = fmaf(wgt, sr, cr);
+  cg = fmaf(wgt, sg, cg);
+  cb = fmaf(wgt, sb, cb);
+  A += wgt;
+  return !(A > ert);
+}
+
 // Transfer function, Phong shading and one front-to-back compositing step
 // for a sample of value f and world gradient g.  Returns false once the
 // accumulated opacity exceeds the termination limit.
@@ -658,6 +705,21 @@ __device__ __forceinline__ float wave_maxf(float v) {
 
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Value of lane (group base + q) of each aligned group of L lanes (L = 1, 2
+// or 4, so a group never leaves its quad of lanes), by a DPP quad
+// permutation.
+template <int L, int Q>
+__device__ __forceinline__ float group_bcast(float v) {
+  if constexpr (L == 1) {
+    return v;
+  } else {
+    constexpr int b0 = (0 & ~(L - 1)) + Q, b1 = (1 & ~(L - 1)) + Q;
+    constexpr int b2 = (2 & ~(L - 1)) + Q, b3 = (3 & ~(L - 1)) + Q;
+    constexpr int ctrl = b0 | (b1 << 2) | (b2 << 4) | (b3 << 6);
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
+  }
+}
+
 // a / b for 0 <= a < 2^22, b >= 1, with inv_b ~ 1/b: float estimate plus
 // one correction step.
 __device__ __forceinline__ int div_small(int a, int b, float inv_b) {
@@ -668,10 +730,14 @@ __device__ __forceinline__ int div_small(int a, int b, float inv_b) {
   return q;
 }
 
-// Ray caster over 8x8 pixel tiles, one tile per wave.  Workgroup b renders
+// Ray caster over pixel tiles, one tile per wave.  Workgroup b renders
 // entries 4b..4b+3 of a tile list sorted by decreasing estimated work, and
 // the hardware starts workgroups in index order, so the longest rays start
-// first.  A wave marches its 64 rays in rounds of `spr` samples.  Before a
+// first.  LPR lanes share a ray (a tile has 64/LPR rays): lane e of a ray
+// evaluates samples e, e+LPR, e+2 LPR, ..., the group exchanges the shaded
+// samples through DPP and composites them in ray order, so a ray's serial
+// chain is LPR times shorter while the composited result is the same as
+// with one lane per ray.  A wave marches its rays in rounds of `spr` samples.  Before a
 // round it stages, into its own LDS brick, every control point that the
 // windows of its active rays can touch during the round (the box of spans
 // between the smallest and largest parameters of the round's first and last
@@ -680,8 +746,11 @@ __device__ __forceinline__ int div_small(int a, int b, float inv_b) {
 // of a workgroup share the transfer function and knots in LDS and never
 // wait for each other after loading them.  Which wave renders which tile
 // does not change any pixel: the arithmetic of a ray depends only on the ray.
-template <int P, int STORE, bool SHADE, bool UNIFORM>
+template <int P, int STORE, bool SHADE, bool UNIFORM, int LPR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void render_brick_kernel(RenderArgsDev a) {
+  static_assert(LPR == 1 || LPR == 2 || LPR == 4, "lanes per ray");
+  constexpr int TW = LPR == 4 ? 4 : 8;        // tile width in pixels
+  constexpr int TH = 64 / LPR / TW;           // tile height
   extern __shared__ float4 lds4[];
   char* lds = reinterpret_cast<char*>(lds4);
   const int tid = threadIdx.x;
@@ -703,9 +772,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
   auto tf = [&](int i) { return tf_lds[i]; };
 
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.m.ctrl, a.m.ctrl_bytes);
-  const int ntx = (a.width + 7) >> 3;
+  const int ntx = (a.width + TW - 1) / TW;
   const int nx = a.m.nx, nxy = a.m.nxy;
   const int S = a.spr;
+  const int ray_lane = lane / LPR;   // ray of this lane within the tile
+  const int e = lane % LPR;          // this lane's sample phase
   float gfac[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
@@ -714,8 +785,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
 
   const int ti = blockIdx.x * 4 + wave;
   const int tile = ti < a.ntiles ? uniform_i(a.tile_order[ti]) : 0;
-  const int px = (tile % ntx) * 8 + (lane & 7);
-  const int py = (tile / ntx) * 8 + (lane >> 3);
+  const int px = (tile % ntx) * TW + ray_lane % TW;
+  const int py = (tile / ntx) * TH + ray_lane / TW;
   const bool inside = ti < a.ntiles && px < a.width && py < a.height;
 
   // u_k(s) = ua_k + s ub_k: the sample parameters as an affine function of
@@ -745,7 +816,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
   if (alive) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const double u = param(0, k);
+      const double u = param(min(e, nr - 1), k);
       st[k].s = lds_span_search(K[k], a.m.ax[k].n, a.m.ax[k].p, u);
       st[k].lo = K[k][st[k].s];
       st[k].hi = K[k][st[k].s + 1];
@@ -823,51 +894,72 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
     }
     const int emax = nel - 1 - (P + P * pitch_y + P * pitch_z);
 
-    for (int s = s0; s < s1; ++s) {
-      float N[3][P + 1], dN[3][P + 1];
-      int w[3];
+    for (int j = s0; j < s1; j += LPR) {
+      // this lane's sample of the group's LPR consecutive samples
+      const int s = j + e;
+      float sr = 0.0f, sg = 0.0f, sb = 0.0f, alpha = 0.0f;
+      if (s < s1) {
+        float N[3][P + 1], dN[3][P + 1];
+        int w[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const AxisDev& Ax = a.m.ax[k];
-        const double u = param(s, k);
-        span_step(K[k], Ax.n, Ax.p, u, st[k]);
-        axis_weights<P, UNIFORM>(Ax, st[k], u, N[k], dN[k]);
-        w[k] = st[k].s - Ax.p;
-      }
-      float f, g[3];
-      if (fits) {
-        int e0 = (w[0] - blo[0]) + pitch_y * (w[1] - blo[1]) + pitch_z * (w[2] - blo[2]);
-        e0 = min(max(e0, 0), emax);
-        contract<P, SHADE>(
-            N, dN,
-            [&](int b, int c, float (&row)[P + 1]) {
-              const float* r = brick + e0 + b * pitch_y + c * pitch_z;
+        for (int k = 0; k < 3; ++k) {
+          const AxisDev& Ax = a.m.ax[k];
+          const double u = param(s, k);
+          span_step(K[k], Ax.n, Ax.p, u, st[k]);
+          axis_weights<P, UNIFORM>(Ax, st[k], u, N[k], dN[k]);
+          w[k] = st[k].s - Ax.p;
+        }
+        float f, g[3];
+        if (fits) {
+          int e0 = (w[0] - blo[0]) + pitch_y * (w[1] - blo[1]) + pitch_z * (w[2] - blo[2]);
+          e0 = min(max(e0, 0), emax);
+          contract<P, SHADE>(
+              N, dN,
+              [&](int b, int c, float (&row)[P + 1]) {
+                const float* r = brick + e0 + b * pitch_y + c * pitch_z;
 #pragma unroll
-              for (int i = 0; i <= P; ++i) row[i] = r[i];
-            },
-            f, g);
-      } else {
-        const int e0 = w[0] + nx * w[1] + nxy * w[2];
-        contract<P, SHADE>(
-            N, dN,
-            [&](int b, int c, float (&row)[P + 1]) {
-              load_row<P, STORE>(rs, e0 + b * nx + c * nxy, row);
-            },
-            f, g);
-      }
-      if (SHADE) {
+                for (int i = 0; i <= P; ++i) row[i] = r[i];
+              },
+              f, g);
+        } else {
+          const int e0 = w[0] + nx * w[1] + nxy * w[2];
+          contract<P, SHADE>(
+              N, dN,
+              [&](int b, int c, float (&row)[P + 1]) {
+                load_row<P, STORE>(rs, e0 + b * nx + c * nxy, row);
+              },
+              f, g);
+        }
+        if (SHADE) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) g[k] *= gfac[k];
+          for (int k = 0; k < 3; ++k) g[k] *= gfac[k];
+        }
+        shade_sample<SHADE>(a, f, g, vx, vy, vz, tf, sr, sg, sb, alpha);
       }
-      ++count;
-      if (!shade_composite<SHADE>(a, f, g, vx, vy, vz, tf, cr, cg, cb, A)) {
+      // composite the group's samples j, j+1, ..., j+LPR-1 in order
+      bool go = true;
+#define MFA_COMPOSITE_PHASE(Q)                                                                   \
+  if constexpr ((Q) < LPR) {                                                                     \
+    const float qr = group_bcast<LPR, (Q)>(sr), qg = group_bcast<LPR, (Q)>(sg);                 \
+    const float qb = group_bcast<LPR, (Q)>(sb), qa = group_bcast<LPR, (Q)>(alpha);              \
+    if (go && j + (Q) < s1) {                                                                    \
+      count += (e == 0) ? 1 : 0;                                                                 \
+      go = composite_one(a.ert, qr, qg, qb, qa, cr, cg, cb, A);                                  \
+    }                                                                                            \
+  }
+      MFA_COMPOSITE_PHASE(0)
+      MFA_COMPOSITE_PHASE(1)
+      MFA_COMPOSITE_PHASE(2)
+      MFA_COMPOSITE_PHASE(3)
+#undef MFA_COMPOSITE_PHASE
+      if (!go) {
         alive = false;
         break;
       }
     }
     if (s1 >= nr) alive = false;
   }
-  if (inside) {
+  if (inside && e == 0) {
     float4 o;
     o.x = cr;
     o.y = cg;
@@ -878,14 +970,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
   count_samples(a, count, lane);
 }
 
-// Work estimate of every 8x8 tile for the queue order: the largest sample
-// count among the tile's corner and centre rays.
+// Work estimate of every tile (tile_w x tile_h pixels) for the queue order:
+// the largest sample count among the tile's corner and centre rays.
 __global__ __launch_bounds__(256) void plan_cost_kernel(RenderArgsDev a) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= a.ntiles) return;
-  const int ntx = (a.width + 7) >> 3;
-  const int x0 = (t % ntx) * 8, y0 = (t / ntx) * 8;
-  const int x1 = min(x0 + 7, a.width - 1), y1 = min(y0 + 7, a.height - 1);
+  const int ntx = (a.width + a.tile_w - 1) / a.tile_w;
+  const int x0 = (t % ntx) * a.tile_w, y0 = (t / ntx) * a.tile_h;
+  const int x1 = min(x0 + a.tile_w - 1, a.width - 1), y1 = min(y0 + a.tile_h - 1, a.height - 1);
   int c = make_ray(a.cam, y0, x0).nr;
   c = max(c, make_ray(a.cam, y0, x1).nr);
   c = max(c, make_ray(a.cam, y1, x0).nr);
@@ -956,7 +1048,8 @@ template <int P, int STORE, bool SHADE, bool UNIFORM>
 hipError_t launch_brick(const RenderArgsDev& a, hipStream_t st) {
   plan_cost_kernel<<<(a.ntiles + 255) / 256, 256, 0, st>>>(a);
   plan_order_kernel<<<1, 1024, 0, st>>>(a.tile_cost, a.ntiles, a.tile_order, a.tile_counter);
-  render_brick_kernel<P, STORE, SHADE, UNIFORM><<<(a.ntiles + 3) / 4, 256, a.lds_bytes, st>>>(a);
+  render_brick_kernel<P, STORE, SHADE, UNIFORM, kLanesPerRay>
+      <<<(a.ntiles + 3) / 4, 256, a.lds_bytes, st>>>(a);
   return hipGetLastError();
 }
 

@@ -11,6 +11,11 @@ constexpr int kMaxDegree = 4;
 // Largest number of samples one ray may take; the host rejects requests
 // whose box diagonal exceeds this many steps.
 constexpr int kMaxSamplesPerRay = 1 << 16;
+// Lanes that share one ray in the brick ray caster (1, 2 or 4); tiles are
+// 8x8, 8x4 or 4x4 pixels accordingly.
+constexpr int kLanesPerRay = 4;
+constexpr int kTileW = kLanesPerRay == 4 ? 4 : 8;
+constexpr int kTileH = 64 / kLanesPerRay / kTileW;
 
 // Per-span FP32 table of one axis of degree p, for span s (stored at row
 // s - p).  With delta = u - U_s (rounded to FP32 once):
@@ -89,7 +94,9 @@ struct RenderArgsDev {
   int32_t lds_bricks;   // byte offset of the bricks in dynamic LDS
   int32_t knot_off[3];  // offset (in doubles) of each axis' knots in LDS
   int32_t lds_bytes;    // dynamic LDS size of one workgroup
-  int32_t ntiles;       // 8x8 pixel tiles of the image
+  int32_t ntiles;       // tiles of the image
+  int32_t tile_w;       // tile size in pixels (kTileW x kTileH)
+  int32_t tile_h;
   int32_t* tile_cost;   // ntiles work estimates (scratch)
   int32_t* tile_order;  // ntiles tile indices, longest first (scratch)
   unsigned* tile_counter;  // queue head (scratch, zeroed before the render kernel)
