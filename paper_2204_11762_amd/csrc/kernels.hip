@@ -737,16 +737,27 @@ __device__ __forceinline__ int div_small(int a, int b, float inv_b) {
 // evaluates samples e, e+LPR, e+2 LPR, ..., the group exchanges the shaded
 // samples through DPP and composites them in ray order, so a ray's serial
 // chain is LPR times shorter while the composited result is the same as
-// with one lane per ray.  A wave marches its rays in rounds of `spr` samples.  Before a
-// round it stages, into its own LDS brick, every control point that the
-// windows of its active rays can touch during the round (the box of spans
-// between the smallest and largest parameters of the round's first and last
-// samples); the round's samples then gather from LDS.  If the box exceeds
-// the brick capacity the round gathers from global memory.  The four waves
-// of a workgroup share the transfer function and knots in LDS and never
-// wait for each other after loading them.  Which wave renders which tile
-// does not change any pixel: the arithmetic of a ray depends only on the ray.
-template <int P, int STORE, bool SHADE, bool UNIFORM, int LPR>
+// with one lane per ray.
+//
+// A wave marches its rays in rounds of `spr` samples.  Before a round it
+// stages, into its own LDS brick, every control point that the windows of
+// its active rays can touch during the round (the box of spans between the
+// smallest and largest parameters of the round's first and last samples);
+// the round's samples then gather from LDS.  If the box exceeds the brick
+// capacity the round gathers from global memory.  The four waves of a
+// workgroup share the transfer function and knots in LDS and never wait for
+// each other after loading them.  Which wave renders which tile does not
+// change any pixel: the arithmetic of a ray depends only on the ray.
+//
+// Span location.  FAST (uniform knots on every axis, every degree >= 2):
+// at the start of a round each lane locates the exact span of its first
+// sample in FP64 and the local coordinate t = (u - U_s)(n - p) in it; the
+// samples of the round then advance t in FP32 (t + i * dt) and take the
+// cell floor(t).  A sample within FP32 rounding of a knot may use the
+// neighbouring polynomial piece, which for degree >= 2 gives the same value
+// and gradient up to rounding.  GENERAL: every sample's span is located
+// exactly in FP64 against the knots (cached bounds, stepping along the ray).
+template <int P, int STORE, bool SHADE, bool FAST, int LPR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void render_brick_kernel(RenderArgsDev a) {
   static_assert(LPR == 1 || LPR == 2 || LPR == 4, "lanes per ray");
   constexpr int TW = LPR == 4 ? 4 : 8;        // tile width in pixels
@@ -780,7 +791,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
   float gfac[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
-    gfac[k] = UNIFORM ? a.m.ax[k].gscale * (float)a.m.ax[k].m : a.m.ax[k].gscale;
+    gfac[k] = FAST ? a.m.ax[k].gscale * (float)a.m.ax[k].m : a.m.ax[k].gscale;
   int count = 0;
 
   const int ti = blockIdx.x * 4 + wave;
@@ -811,15 +822,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
     return fmin(fmax(fma((double)s, ub[k], ua[k]), 0.0), 1.0);
   };
 
-  SpanState st[3];
   bool alive = nr > 0;
-  if (alive) {
+  // GENERAL: exact span state per axis
+  SpanState st[3];
+  // FAST: per-lane increment of the local coordinate between the lane's
+  // consecutive samples (LPR samples apart)
+  float dt[3];
+  if constexpr (FAST) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double u = param(min(e, nr - 1), k);
-      st[k].s = lds_span_search(K[k], a.m.ax[k].n, a.m.ax[k].p, u);
-      st[k].lo = K[k][st[k].s];
-      st[k].hi = K[k][st[k].s + 1];
+    for (int k = 0; k < 3; ++k) dt[k] = (float)(ub[k] * a.m.ax[k].m * (double)LPR);
+  } else {
+    if (alive) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double u = param(min(e, nr - 1), k);
+        st[k].s = lds_span_search(K[k], a.m.ax[k].n, a.m.ax[k].p, u);
+        st[k].lo = K[k][st[k].s];
+        st[k].hi = K[k][st[k].s + 1];
+      }
     }
   }
   float cr = 0.0f, cg = 0.0f, cb = 0.0f, A = 0.0f;
@@ -848,7 +868,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
       const double ul = fmin(fmax((double)lo_f[k], 0.0), 1.0);
       const double uh = fmin(fmax((double)hi_f[k], 0.0), 1.0);
       int sl, sh;
-      if constexpr (UNIFORM) {
+      if constexpr (FAST) {
         // span estimate from u m, corrected by one step against the knots
         const int m = Ax.n - Ax.p;
         sl = Ax.p + min(max((int)(ul * Ax.m), 0), m - 1);
@@ -894,23 +914,96 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
     }
     const int emax = nel - 1 - (P + P * pitch_y + P * pitch_z);
 
-    for (int j = s0; j < s1; j += LPR) {
-      // this lane's sample of the group's LPR consecutive samples
-      const int s = j + e;
-      float sr = 0.0f, sg = 0.0f, sb = 0.0f, alpha = 0.0f;
-      if (s < s1) {
-        float N[3][P + 1], dN[3][P + 1];
-        int w[3];
+    // FAST: exact cell and local coordinate of this lane's first sample of
+    // the round
+    int ca[3] = {0, 0, 0};
+    float ta[3] = {0.0f, 0.0f, 0.0f};
+    if constexpr (FAST) {
+      if (s0 + e < s1) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           const AxisDev& Ax = a.m.ax[k];
+          const int m = Ax.n - Ax.p;
+          const double u = param(s0 + e, k);
+          int c = min(max((int)(u * Ax.m), 0), m - 1);
+          if (c > 0 && u < K[k][Ax.p + c])
+            --c;
+          else if (c < m - 1 && u >= K[k][Ax.p + c + 1])
+            ++c;
+          ca[k] = c;
+          ta[k] = (float)((u - K[k][Ax.p + c]) * Ax.m);
+        }
+      }
+    }
+
+    // one lane's sample: basis weights and window start of each axis
+    auto weights = [&](int s, int i, float (&N)[3][P + 1], float (&dN)[3][P + 1], int (&w)[3]) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const AxisDev& Ax = a.m.ax[k];
+        if constexpr (FAST) {
+          const int m = Ax.n - Ax.p;
+          const float t = fmaf((float)i, dt[k], ta[k]);
+          const float fl = floorf(t);
+          const int c = min(max(ca[k] + (int)fl, 0), m - 1);
+          const float tl = t - (float)(c - ca[k]);
+          w[k] = c;
+          if (c >= Ax.p - 1 && c <= m - Ax.p) {
+            cardinal_window<P>(Ax.p, tl, N[k], dN[k]);
+          } else {
+            // boundary span: triangle with the span's reciprocal table
+            const float* row = Ax.tab + (size_t)c * (size_t)table_stride(Ax.p);
+            axis_basis<P>(Ax.p, row, tl * Ax.inv_m, N[k], dN[k]);
+#pragma unroll
+            for (int q = 0; q <= P; ++q) dN[k][q] *= Ax.inv_m;
+          }
+        } else {
           const double u = param(s, k);
           span_step(K[k], Ax.n, Ax.p, u, st[k]);
-          axis_weights<P, UNIFORM>(Ax, st[k], u, N[k], dN[k]);
+          const float d = (float)(u - st[k].lo);
+          const float* row = Ax.tab + (size_t)(st[k].s - Ax.p) * (size_t)table_stride(Ax.p);
+          axis_basis<P>(Ax.p, row, d, N[k], dN[k]);
           w[k] = st[k].s - Ax.p;
         }
-        float f, g[3];
-        if (fits) {
+      }
+    };
+
+    // shade this lane's sample, then composite the group's samples
+    // j, j+1, ..., j+LPR-1 in order; false once the ray terminates
+    auto finish = [&](int j, float f, const float (&g)[3], bool valid) {
+      float sr = 0.0f, sg = 0.0f, sb = 0.0f, alpha = 0.0f;
+      if (valid) {
+        float gw[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gw[k] = g[k] * gfac[k];
+        shade_sample<SHADE>(a, f, gw, vx, vy, vz, tf, sr, sg, sb, alpha);
+      }
+      bool go = true;
+#define MFA_COMPOSITE_PHASE(Q)                                                      \
+  if constexpr ((Q) < LPR) {                                                        \
+    const float qr = group_bcast<LPR, (Q)>(sr), qg = group_bcast<LPR, (Q)>(sg);    \
+    const float qb = group_bcast<LPR, (Q)>(sb), qa = group_bcast<LPR, (Q)>(alpha); \
+    if (go && j + (Q) < s1) {                                                       \
+      count += (e == 0) ? 1 : 0;                                                    \
+      go = composite_one(a.ert, qr, qg, qb, qa, cr, cg, cb, A);                     \
+    }                                                                               \
+  }
+      MFA_COMPOSITE_PHASE(0)
+      MFA_COMPOSITE_PHASE(1)
+      MFA_COMPOSITE_PHASE(2)
+      MFA_COMPOSITE_PHASE(3)
+#undef MFA_COMPOSITE_PHASE
+      return go;
+    };
+
+    if (fits) {
+      for (int j = s0, i = 0; j < s1; j += LPR, ++i) {
+        const int s = j + e;
+        float f = 0.0f, g[3] = {0.0f, 0.0f, 0.0f};
+        if (s < s1) {
+          float N[3][P + 1], dN[3][P + 1];
+          int w[3];
+          weights(s, i, N, dN, w);
           int e0 = (w[0] - blo[0]) + pitch_y * (w[1] - blo[1]) + pitch_z * (w[2] - blo[2]);
           e0 = min(max(e0, 0), emax);
           contract<P, SHADE>(
@@ -918,10 +1011,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
               [&](int b, int c, float (&row)[P + 1]) {
                 const float* r = brick + e0 + b * pitch_y + c * pitch_z;
 #pragma unroll
-                for (int i = 0; i <= P; ++i) row[i] = r[i];
+                for (int q = 0; q <= P; ++q) row[q] = r[q];
               },
               f, g);
-        } else {
+        }
+        if (!finish(j, f, g, s < s1)) {
+          alive = false;
+          break;
+        }
+      }
+    } else {
+      for (int j = s0, i = 0; j < s1; j += LPR, ++i) {
+        const int s = j + e;
+        float f = 0.0f, g[3] = {0.0f, 0.0f, 0.0f};
+        if (s < s1) {
+          float N[3][P + 1], dN[3][P + 1];
+          int w[3];
+          weights(s, i, N, dN, w);
           const int e0 = w[0] + nx * w[1] + nxy * w[2];
           contract<P, SHADE>(
               N, dN,
@@ -930,31 +1036,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
               },
               f, g);
         }
-        if (SHADE) {
-#pragma unroll
-          for (int k = 0; k < 3; ++k) g[k] *= gfac[k];
+        if (!finish(j, f, g, s < s1)) {
+          alive = false;
+          break;
         }
-        shade_sample<SHADE>(a, f, g, vx, vy, vz, tf, sr, sg, sb, alpha);
-      }
-      // composite the group's samples j, j+1, ..., j+LPR-1 in order
-      bool go = true;
-#define MFA_COMPOSITE_PHASE(Q)                                                                   \
-  if constexpr ((Q) < LPR) {                                                                     \
-    const float qr = group_bcast<LPR, (Q)>(sr), qg = group_bcast<LPR, (Q)>(sg);                 \
-    const float qb = group_bcast<LPR, (Q)>(sb), qa = group_bcast<LPR, (Q)>(alpha);              \
-    if (go && j + (Q) < s1) {                                                                    \
-      count += (e == 0) ? 1 : 0;                                                                 \
-      go = composite_one(a.ert, qr, qg, qb, qa, cr, cg, cb, A);                                  \
-    }                                                                                            \
-  }
-      MFA_COMPOSITE_PHASE(0)
-      MFA_COMPOSITE_PHASE(1)
-      MFA_COMPOSITE_PHASE(2)
-      MFA_COMPOSITE_PHASE(3)
-#undef MFA_COMPOSITE_PHASE
-      if (!go) {
-        alive = false;
-        break;
       }
     }
     if (s1 >= nr) alive = false;
@@ -1044,11 +1129,11 @@ __global__ void zero_counter(unsigned long long* p) {
   if (threadIdx.x == 0) p[0] = 0ull;
 }
 
-template <int P, int STORE, bool SHADE, bool UNIFORM>
+template <int P, int STORE, bool SHADE, bool FAST>
 hipError_t launch_brick(const RenderArgsDev& a, hipStream_t st) {
   plan_cost_kernel<<<(a.ntiles + 255) / 256, 256, 0, st>>>(a);
   plan_order_kernel<<<1, 1024, 0, st>>>(a.tile_cost, a.ntiles, a.tile_order, a.tile_counter);
-  render_brick_kernel<P, STORE, SHADE, UNIFORM, kLanesPerRay>
+  render_brick_kernel<P, STORE, SHADE, FAST, kLanesPerRay>
       <<<(a.ntiles + 3) / 4, 256, a.lds_bytes, st>>>(a);
   return hipGetLastError();
 }
@@ -1056,8 +1141,9 @@ hipError_t launch_brick(const RenderArgsDev& a, hipStream_t st) {
 template <int P, int STORE, bool SHADE>
 hipError_t launch_render_ps(const RenderArgsDev& a, hipStream_t st) {
   if (a.lds_bytes > 0) {
-    return a.m.uniform ? launch_brick<P, STORE, SHADE, true>(a, st)
-                       : launch_brick<P, STORE, SHADE, false>(a, st);
+    const bool fast = a.m.uniform && a.m.ax[0].p >= 2 && a.m.ax[1].p >= 2 && a.m.ax[2].p >= 2;
+    return fast ? launch_brick<P, STORE, SHADE, true>(a, st)
+                : launch_brick<P, STORE, SHADE, false>(a, st);
   }
   const dim3 grid((a.width + 15) / 16, (a.height + 15) / 16);
   render_global_kernel<P, STORE, SHADE><<<grid, 256, 0, st>>>(a);
