@@ -35,6 +35,28 @@ from paper_2204_11762_amd import workloads as wl  # noqa: E402
 
 METRIC = "MFA samples/s (value+grad) BF16 vs FP32 at stated err; p50/p99 frame latency"
 PEAK_FP32_VALU = 157.3e12     # MI355X FP32 vector peak (packed issue)
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2204_11762_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_256cubed_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic(store: str):
+    """HBM bytes per launch of the render kernel from the committed counter
+    summary, or None if the summary was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    leg = rec.get("legs", {}).get(store)
+    return None if leg is None else leg.get("hbm_bytes_per_launch")
 
 
 def flops_per_sample(p: int) -> int:
@@ -83,8 +105,11 @@ def cpu_baseline(wk, n_rays: int, seed: int, workers: int):
     r, cc = np.divmod(allpix, c.width)
     o, d = orc.camera_rays(cam, r, cc)
     t0, t1, hit = orc.slab(o, d, M.lo, M.hi)
-    rng = np.random.default_rng(seed)
-    pix = np.sort(rng.choice(np.nonzero(hit)[0], size=n_rays, replace=False))
+    hits = np.nonzero(hit)[0]
+    if n_rays < 0 or n_rays >= len(hits):
+        pix = hits
+    else:
+        pix = np.sort(np.random.default_rng(seed).choice(hits, size=n_rays, replace=False))
     _ORACLE_STATE["args"] = (M, cam, tf, prm)
     chunks = np.array_split(pix, max(workers * 4, 1))
     t_start = time.perf_counter()
@@ -113,7 +138,7 @@ def host_cpu_model() -> str:
 # GPU leg
 # ---------------------------------------------------------------------------
 
-def gpu_leg(b, ctx, wk, store: int, steps: int, warmup: int, log):
+def gpu_leg(b, ctx, wk, store: int, steps: int, warmup: int, log, nominal_frames=True):
     import torch
     cam = wk.camera
     h = b.mfa_model_upload(ctx, wk.model, store)
@@ -126,9 +151,11 @@ def gpu_leg(b, ctx, wk, store: int, steps: int, warmup: int, log):
         image = out.cpu().numpy()
         nominal_prm = copy.copy(wk.params)
         nominal_prm.ert_alpha = 1.0
-        b.mfa_render(ctx, h, cam, wk.tf, nominal_prm, out, cnt)
-        torch.cuda.synchronize()
-        nominal = int(cnt.item())
+        nominal = None
+        if nominal_frames:
+            b.mfa_render(ctx, h, cam, wk.tf, nominal_prm, out, cnt)
+            torch.cuda.synchronize()
+            nominal = int(cnt.item())
         for _ in range(warmup):
             b.mfa_render(ctx, h, cam, wk.tf, wk.params, out, None)
         torch.cuda.synchronize()
@@ -145,15 +172,17 @@ def gpu_leg(b, ctx, wk, store: int, steps: int, warmup: int, log):
         wall = time.perf_counter() - t0
         lat = np.array([a.elapsed_time(e) for a, e in zip(ev0, ev1)])  # ms
         # nominal (no termination) frames, a few, for the ERT-free rate
-        nsteps = max(3, steps // 10)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(nsteps):
-            b.mfa_render(ctx, h, cam, wk.tf, nominal_prm, out, None, stream=stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        nominal_ms = e0.elapsed_time(e1) / nsteps
+        nominal_ms = None
+        if nominal_frames:
+            nsteps = max(3, steps // 10)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(nsteps):
+                b.mfa_render(ctx, h, cam, wk.tf, nominal_prm, out, None, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            nominal_ms = e0.elapsed_time(e1) / nsteps
         log(f"store={'fp32' if store == 0 else 'bf16'}: {samples} samples/frame, "
             f"{wall / steps * 1e3:.3f} ms/frame wall, kernel p50 {np.median(lat):.3f} ms")
         return {"samples": samples, "nominal": nominal, "wall": wall, "lat": lat,
@@ -179,8 +208,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--store", choices=["bf16", "fp32"], default="bf16",
                     help="storage of the headline number (both are measured)")
-    ap.add_argument("--cpu-rays", type=int, default=24576,
-                    help="rays of the oracle's bounded sample (0 = skip the CPU leg)")
+    ap.add_argument("--cpu-rays", type=int, default=-1,
+                    help="rays of the oracle's bounded sample: -1 = every ray that meets "
+                         "the volume, 0 = skip the CPU leg")
+    ap.add_argument("--no-nominal", action="store_true",
+                    help="skip the frames without early termination (so that every render "
+                         "launch of a profiled run is a timed-type frame)")
     ap.add_argument("--cpu-workers", type=int, default=0, help="0 = host cores, at most 16")
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -203,9 +236,10 @@ def main():
 
     base = None
     cores = 0
-    if args.cpu_rays > 0:
+    if args.cpu_rays != 0:
         cores = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
-        log(f"CPU oracle on {args.cpu_rays} rays with {cores} processes")
+        log(f"CPU oracle on {'all hit' if args.cpu_rays < 0 else args.cpu_rays} rays "
+            f"with {cores} processes")
         base = cpu_baseline(wk, args.cpu_rays, args.seed, cores)
         log(f"CPU oracle: {base['samples']} samples in {base['wall']:.2f} s")
 
@@ -227,7 +261,8 @@ def main():
         legs = {}
         for name, store in (("fp32", 0), ("bf16", 1)):
             if name in args.legs.split(","):
-                legs[name] = gpu_leg(b, ctx, wk, store, args.steps, args.warmup, log)
+                legs[name] = gpu_leg(b, ctx, wk, store, args.steps, args.warmup, log,
+                                     nominal_frames=not args.no_nominal)
     finally:
         b.mfa_destroy(ctx)
     if args.store not in legs:
@@ -247,7 +282,8 @@ def main():
                 "p50_ms": float(np.percentile(leg["lat"], 50)),
                 "p99_ms": float(np.percentile(leg["lat"], 99)),
                 "nominal_samples_per_frame": leg["nominal"],
-                "nominal_samples_per_s": leg["nominal"] / (leg["nominal_ms"] * 1e-3),
+                "nominal_samples_per_s": (None if leg["nominal"] is None
+                                          else leg["nominal"] / (leg["nominal_ms"] * 1e-3)),
                 "model_bytes": leg["model_bytes"],
                 "error": rmse_on(leg["image"], base)}
 
@@ -273,16 +309,20 @@ def main():
         "p50_ms": float(np.percentile(head["lat"], 50)),
         "p99_ms": float(np.percentile(head["lat"], 99)),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
-                     "kernel": "render_kernel<3,%s,shade>" % ("1" if args.store == "bf16" else "0"),
-                     "kernel_ms": kern_ms, "flops_per_sample": flops_per_sample(p)},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
+                     "traffic": measured_traffic(args.store),
+                     "kernel": "render_brick_kernel<3,%s,shade,fast,4>" % (
+                         "1" if args.store == "bf16" else "0"),
+                     "kernel_ms": kern_ms, "flops_per_sample": flops_per_sample(p),
+                     "flops_per_launch": flops},
         "legs": {k: summary(v, k) for k, v in legs.items()},
     }
     if base is not None:
         line["cpu_baseline"] = {"value": base["samples"] / base["wall"], "unit": "samples/s",
                                 "cores": cores, "kind": "oracle",
-                                "sample": f"{len(base['pix'])} seeded hit rays of the same frame, "
-                                          f"{base['samples']} samples, {base['wall']:.1f} s wall",
+                                "sample": f"{len(base['pix'])} rays of the same frame that meet the "
+                                          f"volume, {base['samples']} samples, "
+                                          f"{base['wall']:.1f} s wall",
                                 "host_cpu": host_cpu_model()}
     print(json.dumps(line), flush=True)
 

@@ -355,8 +355,8 @@ struct mfa_ctx {
   std::unordered_map<int64_t, DeviceModel> models;
   std::unordered_map<uint64_t, std::vector<TFEntry>> tfs;
   size_t n_tf = 0;
-  // tile-queue scratch of the persistent render kernel: cost and order
-  // arrays of `scratch_tiles` entries each, then the queue counter
+  // scratch of the tile sort: cost and order arrays of `scratch_tiles`
+  // entries each, then 1024 bucket counters
   void* scratch = nullptr;
   int64_t scratch_tiles = 0;
 
@@ -420,7 +420,7 @@ mfa_status ensure_scratch(mfa_ctx* ctx, int64_t tiles) {
     ctx->scratch = nullptr;
     ctx->scratch_tiles = 0;
   }
-  const size_t bytes = size_t(tiles) * 8 + 256;
+  const size_t bytes = size_t(tiles) * 8 + 4096 + 256;
   const hipError_t e = hipMalloc(&ctx->scratch, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -693,8 +693,8 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const 
   a.samples = reinterpret_cast<unsigned long long*>(samples_dev);
   plan_bricks(dm, tf->n, prm->step, a);
   if (a.lds_bytes > 0) {
-    const int64_t tiles = int64_t((cam->width + mfa::kTileW - 1) / mfa::kTileW) *
-                          int64_t((cam->height + mfa::kTileH - 1) / mfa::kTileH);
+    const int64_t tiles = int64_t((cam->width + 2 * mfa::kTileW - 1) / (2 * mfa::kTileW)) *
+                          int64_t((cam->height + 2 * mfa::kTileH - 1) / (2 * mfa::kTileH));
     a.tile_w = mfa::kTileW;
     a.tile_h = mfa::kTileH;
     st = ensure_scratch(ctx, tiles);
@@ -703,7 +703,7 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const 
     a.ntiles = int32_t(tiles);
     a.tile_cost = base;
     a.tile_order = base + ctx->scratch_tiles;
-    a.tile_counter = reinterpret_cast<unsigned*>(base + 2 * ctx->scratch_tiles);
+    a.tile_hist = reinterpret_cast<unsigned*>(base + 2 * ctx->scratch_tiles);
   }
   const hipError_t e = mfa::launch_render(a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("render launch", e));

@@ -730,10 +730,11 @@ __device__ __forceinline__ int div_small(int a, int b, float inv_b) {
   return q;
 }
 
-// Ray caster over pixel tiles, one tile per wave.  Workgroup b renders
-// entries 4b..4b+3 of a tile list sorted by decreasing estimated work, and
-// the hardware starts workgroups in index order, so the longest rays start
-// first.  LPR lanes share a ray (a tile has 64/LPR rays): lane e of a ray
+// Ray caster over pixel tiles, one tile per wave.  Workgroup b renders the
+// 2x2 tiles of entry b of a list of super-tiles sorted by decreasing
+// estimated work, and the hardware starts workgroups in index order, so the
+// longest rays start first while the four waves of a workgroup work on
+// neighbouring tiles.  LPR lanes share a ray (a tile has 64/LPR rays): lane e of a ray
 // evaluates samples e, e+LPR, e+2 LPR, ..., the group exchanges the shaded
 // samples through DPP and composites them in ray order, so a ray's serial
 // chain is LPR times shorter while the composited result is the same as
@@ -794,11 +795,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
     gfac[k] = FAST ? a.m.ax[k].gscale * (float)a.m.ax[k].m : a.m.ax[k].gscale;
   int count = 0;
 
-  const int ti = blockIdx.x * 4 + wave;
-  const int tile = ti < a.ntiles ? uniform_i(a.tile_order[ti]) : 0;
-  const int px = (tile % ntx) * TW + ray_lane % TW;
-  const int py = (tile / ntx) * TH + ray_lane / TW;
-  const bool inside = ti < a.ntiles && px < a.width && py < a.height;
+  // workgroup b takes super-tile order[b] (2x2 tiles), wave w its quadrant
+  const int nsx = (ntx + 1) >> 1;
+  const int sup = uniform_i(a.tile_order[blockIdx.x]);
+  const int tx = (sup % nsx) * 2 + (wave & 1);
+  const int ty = (sup / nsx) * 2 + (wave >> 1);
+  const int px = tx * TW + ray_lane % TW;
+  const int py = ty * TH + ray_lane / TW;
+  const bool inside = px < a.width && py < a.height;
 
   // u_k(s) = ua_k + s ub_k: the sample parameters as an affine function of
   // the sample index
@@ -1055,51 +1059,92 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
   count_samples(a, count, lane);
 }
 
-// Work estimate of every tile (tile_w x tile_h pixels) for the queue order:
-// the largest sample count among the tile's corner and centre rays.
-__global__ __launch_bounds__(256) void plan_cost_kernel(RenderArgsDev a) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= a.ntiles) return;
-  const int ntx = (a.width + a.tile_w - 1) / a.tile_w;
-  const int x0 = (t % ntx) * a.tile_w, y0 = (t / ntx) * a.tile_h;
-  const int x1 = min(x0 + a.tile_w - 1, a.width - 1), y1 = min(y0 + a.tile_h - 1, a.height - 1);
-  int c = make_ray(a.cam, y0, x0).nr;
-  c = max(c, make_ray(a.cam, y0, x1).nr);
-  c = max(c, make_ray(a.cam, y1, x0).nr);
-  c = max(c, make_ray(a.cam, y1, x1).nr);
-  c = max(c, make_ray(a.cam, (y0 + y1) >> 1, (x0 + x1) >> 1).nr);
-  a.tile_cost[t] = c;
+// ---------------------------------------------------------------------------
+// tile order: counting sort of the tiles by decreasing estimated work
+// ---------------------------------------------------------------------------
+
+constexpr int kBuckets = 1024;
+
+// Bucket of a work estimate (4 samples per bucket), largest work first.
+__device__ __forceinline__ int cost_rank(int c) { return kBuckets - 1 - min(c >> 2, kBuckets - 1); }
+
+__global__ __launch_bounds__(256) void plan_zero_kernel(unsigned* hist) {
+  for (int i = threadIdx.x; i < kBuckets; i += 256) hist[i] = 0u;
 }
 
-// Tile queue in decreasing order of estimated work (256 buckets; order
-// within a bucket is arbitrary), and a zeroed queue counter.
-__global__ __launch_bounds__(1024) void plan_order_kernel(const int* cost, int n, int* order,
-                                                          unsigned* counter) {
-  __shared__ unsigned hist[256];
-  __shared__ int cmax;
+// Work estimate of every super-tile (2x2 tiles of tile_w x tile_h pixels):
+// the largest sample count among nine rays (corners, edge midpoints and
+// centre of its pixel rectangle); and the histogram of the estimates'
+// buckets.
+__global__ __launch_bounds__(256) void plan_cost_kernel(RenderArgsDev a) {
+  __shared__ unsigned h[kBuckets];
   const int tid = threadIdx.x;
-  if (tid < 256) hist[tid] = 0u;
-  if (tid == 0) cmax = 0;
+  for (int i = tid; i < kBuckets; i += 256) h[i] = 0u;
   __syncthreads();
-  int m = 0;
-  for (int i = tid; i < n; i += 1024) m = max(m, cost[i]);
-  atomicMax(&cmax, m);
-  __syncthreads();
-  const long long denom = (long long)cmax + 1;
-  auto bucket = [&](int c) { return 255 - (int)(((long long)c * 256) / denom); };
-  for (int i = tid; i < n; i += 1024) atomicAdd(&hist[bucket(cost[i])], 1u);
-  __syncthreads();
-  if (tid == 0) {
-    unsigned run = 0;
-    for (int b = 0; b < 256; ++b) {
-      const unsigned h = hist[b];
-      hist[b] = run;
-      run += h;
-    }
-    *counter = 0u;
+  const int t = blockIdx.x * 256 + tid;
+  if (t < a.ntiles) {
+    const int ntx = (a.width + a.tile_w - 1) / a.tile_w;
+    const int nsx = (ntx + 1) >> 1;
+    const int x0 = (t % nsx) * 2 * a.tile_w, y0 = (t / nsx) * 2 * a.tile_h;
+    const int x1 = min(x0 + 2 * a.tile_w - 1, a.width - 1);
+    const int y1 = min(y0 + 2 * a.tile_h - 1, a.height - 1);
+    const int xm = (x0 + x1) >> 1, ym = (y0 + y1) >> 1;
+    int c = 0;
+    c = max(c, make_ray(a.cam, y0, x0).nr);
+    c = max(c, make_ray(a.cam, y0, xm).nr);
+    c = max(c, make_ray(a.cam, y0, x1).nr);
+    c = max(c, make_ray(a.cam, ym, x0).nr);
+    c = max(c, make_ray(a.cam, ym, xm).nr);
+    c = max(c, make_ray(a.cam, ym, x1).nr);
+    c = max(c, make_ray(a.cam, y1, x0).nr);
+    c = max(c, make_ray(a.cam, y1, xm).nr);
+    c = max(c, make_ray(a.cam, y1, x1).nr);
+    a.tile_cost[t] = c;
+    atomicAdd(&h[cost_rank(c)], 1u);
   }
   __syncthreads();
-  for (int i = tid; i < n; i += 1024) order[atomicAdd(&hist[bucket(cost[i])], 1u)] = i;
+  for (int i = tid; i < kBuckets; i += 256)
+    if (h[i] != 0u) atomicAdd(&a.tile_hist[i], h[i]);
+}
+
+// Exclusive prefix sum of the bucket histogram (one workgroup).
+__global__ __launch_bounds__(1024) void plan_scan_kernel(unsigned* hist) {
+  __shared__ unsigned v[kBuckets];
+  const int tid = threadIdx.x;
+  const unsigned own = hist[tid];
+  v[tid] = own;
+  __syncthreads();
+  for (int off = 1; off < kBuckets; off <<= 1) {
+    const unsigned add = tid >= off ? v[tid - off] : 0u;
+    __syncthreads();
+    v[tid] += add;
+    __syncthreads();
+  }
+  hist[tid] = v[tid] - own;
+}
+
+// Tile list in bucket order; every workgroup reserves one range per bucket
+// it holds tiles of, so positions are unique (order within a bucket is
+// arbitrary and does not affect any pixel).
+__global__ __launch_bounds__(256) void plan_scatter_kernel(const int* cost, int n, unsigned* base,
+                                                           int* order) {
+  __shared__ unsigned cnt[kBuckets];
+  __shared__ unsigned off[kBuckets];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kBuckets; i += 256) cnt[i] = 0u;
+  __syncthreads();
+  const int t = blockIdx.x * 256 + tid;
+  int r = 0;
+  unsigned local = 0u;
+  if (t < n) {
+    r = cost_rank(cost[t]);
+    local = atomicAdd(&cnt[r], 1u);
+  }
+  __syncthreads();
+  for (int i = tid; i < kBuckets; i += 256)
+    if (cnt[i] != 0u) off[i] = atomicAdd(&base[i], cnt[i]);
+  __syncthreads();
+  if (t < n) order[off[r] + local] = t;
 }
 
 template <int P, int STORE, bool GRAD>
@@ -1131,10 +1176,12 @@ __global__ void zero_counter(unsigned long long* p) {
 
 template <int P, int STORE, bool SHADE, bool FAST>
 hipError_t launch_brick(const RenderArgsDev& a, hipStream_t st) {
-  plan_cost_kernel<<<(a.ntiles + 255) / 256, 256, 0, st>>>(a);
-  plan_order_kernel<<<1, 1024, 0, st>>>(a.tile_cost, a.ntiles, a.tile_order, a.tile_counter);
-  render_brick_kernel<P, STORE, SHADE, FAST, kLanesPerRay>
-      <<<(a.ntiles + 3) / 4, 256, a.lds_bytes, st>>>(a);
+  const unsigned blocks = (unsigned)((a.ntiles + 255) / 256);
+  plan_zero_kernel<<<1, 256, 0, st>>>(a.tile_hist);
+  plan_cost_kernel<<<blocks, 256, 0, st>>>(a);
+  plan_scan_kernel<<<1, kBuckets, 0, st>>>(a.tile_hist);
+  plan_scatter_kernel<<<blocks, 256, 0, st>>>(a.tile_cost, a.ntiles, a.tile_hist, a.tile_order);
+  render_brick_kernel<P, STORE, SHADE, FAST, kLanesPerRay><<<a.ntiles, 256, a.lds_bytes, st>>>(a);
   return hipGetLastError();
 }
 

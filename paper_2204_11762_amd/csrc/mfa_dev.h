@@ -94,12 +94,12 @@ struct RenderArgsDev {
   int32_t lds_bricks;   // byte offset of the bricks in dynamic LDS
   int32_t knot_off[3];  // offset (in doubles) of each axis' knots in LDS
   int32_t lds_bytes;    // dynamic LDS size of one workgroup
-  int32_t ntiles;       // tiles of the image
+  int32_t ntiles;       // super-tiles (2x2 tiles) of the image
   int32_t tile_w;       // tile size in pixels (kTileW x kTileH)
   int32_t tile_h;
   int32_t* tile_cost;   // ntiles work estimates (scratch)
-  int32_t* tile_order;  // ntiles tile indices, longest first (scratch)
-  unsigned* tile_counter;  // queue head (scratch, zeroed before the render kernel)
+  int32_t* tile_order;  // ntiles super-tile indices, longest first (scratch)
+  unsigned* tile_hist;  // 1024 bucket counters of the tile sort (scratch)
 };
 
 struct EvalArgsDev {
