@@ -173,6 +173,22 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* camera, con
                       const mfa_render_params* params, float* rgba_dev, int64_t* samples_dev,
                       void* stream);
 
+/* Kernel timing for measurement.  While enabled, every mfa_render call
+ * records a pair of HIP events on its stream immediately around the
+ * ray-casting kernel (after the per-frame tile planning), so that the
+ * kernel's own duration can be read back; at most 65536 launches are
+ * recorded, later ones are not.  Enabling or disabling discards what was
+ * recorded.  Errors: MFA_ERR_HANDLE. */
+mfa_status mfa_kernel_timing(mfa_ctx* ctx, int32_t enable);
+
+/* Wait for the recorded events and write the kernel durations in
+ * milliseconds, in call order, to ms_host (host memory of `cap` floats,
+ * owned by the caller; only the first `cap` are written).  *count receives
+ * the number of recorded launches.  The record is then cleared; recording
+ * stays as it was.  Errors: MFA_ERR_HANDLE, MFA_ERR_INVALID (null count,
+ * cap < 0, null ms_host with cap > 0), MFA_ERR_DEVICE. */
+mfa_status mfa_kernel_times(mfa_ctx* ctx, float* ms_host, int64_t cap, int64_t* count);
+
 /* Value and world-space gradient queries (Algorithm 1: value query and
  * gradient query, all three derivatives at once) at n world points
  * xyz_dev (n*3 FP64, point-major).  Points outside the box are clamped to

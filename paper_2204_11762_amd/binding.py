@@ -33,7 +33,8 @@ MFA_CAMERA_PERSP = 1
 
 EXPORTED = ("mfa_create", "mfa_destroy", "mfa_set_memory_budget", "mfa_model_upload",
             "mfa_model_free", "mfa_model_bytes", "mfa_render", "mfa_eval_points",
-            "mfa_validate_model", "mfa_validate_render", "mfa_last_error", "mfa_version")
+            "mfa_kernel_timing", "mfa_kernel_times", "mfa_validate_model",
+            "mfa_validate_render", "mfa_last_error", "mfa_version")
 
 
 class MFAError(RuntimeError):
@@ -86,6 +87,8 @@ def _load():
         "mfa_render": (st, [vp, i64, C.POINTER(Camera), C.POINTER(TF), C.POINTER(RenderParams),
                             vp, vp, vp]),
         "mfa_eval_points": (st, [vp, i64, i64, vp, vp, vp, vp]),
+        "mfa_kernel_timing": (st, [vp, C.c_int32]),
+        "mfa_kernel_times": (st, [vp, vp, i64, C.POINTER(i64)]),
         "mfa_validate_model": (st, [C.POINTER(ModelDesc)]),
         "mfa_validate_render": (st, [C.POINTER(Camera), C.POINTER(TF), C.POINTER(RenderParams)]),
         "mfa_last_error": (C.c_char_p, []),
@@ -264,6 +267,23 @@ def mfa_render(ctx: int, model: int, camera, tf, params, rgba, samples=None, str
     t, keep = tf_struct(tf)
     _check(lib.mfa_render(ctx, int(model), C.byref(camera_struct(camera)), C.byref(t),
                           C.byref(params_struct(params)), out, sp, _stream_ptr(stream)))
+
+
+def mfa_kernel_timing(ctx: int, enable: bool) -> None:
+    """Start (True) or stop (False) recording the ray-casting kernel's
+    duration on every later mfa_render call; either discards the record."""
+    _check(lib.mfa_kernel_timing(ctx, 1 if enable else 0))
+
+
+def mfa_kernel_times(ctx: int, cap: int = 1 << 16):
+    """Durations (ms, float32 numpy array, in call order) of the recorded
+    render kernels; waits for them and clears the record."""
+    import numpy as np
+    buf = np.zeros(max(int(cap), 0), dtype=np.float32)
+    n = C.c_int64()
+    _check(lib.mfa_kernel_times(ctx, buf.ctypes.data if cap > 0 else None, int(cap),
+                                C.byref(n)))
+    return buf[:min(n.value, int(cap))].copy()
 
 
 def mfa_eval_points(ctx: int, model: int, xyz, value, grad=None, stream=None) -> None:

@@ -36,6 +36,8 @@ constexpr int64_t kMaxPixels = int64_t(1) << 26;
 constexpr int kMaxImageSide = 1 << 15;
 constexpr int64_t kMaxEvalPoints = int64_t(1) << 38;
 constexpr size_t kMaxCachedTF = 64;
+// Render launches whose kernel duration one timing record holds.
+constexpr size_t kMaxTimedLaunches = 1 << 16;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -359,6 +361,10 @@ struct mfa_ctx {
   // entries each, then 1024 bucket counters
   void* scratch = nullptr;
   int64_t scratch_tiles = 0;
+  // kernel timing: event pairs, the first `timed` of which are recorded
+  bool timing = false;
+  std::vector<mfa::KernelEvents> events;
+  size_t timed = 0;
 
   void free_tfs() {
     for (auto& kv : tfs)
@@ -484,6 +490,11 @@ mfa_status mfa_destroy(mfa_ctx* ctx) {
     ctx->free_tfs();
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     ctx->scratch = nullptr;
+    for (auto& ev : ctx->events) {
+      (void)hipEventDestroy(ev.begin);
+      (void)hipEventDestroy(ev.end);
+    }
+    ctx->events.clear();
   }
   delete ctx;
   return st;
@@ -705,8 +716,54 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const 
     a.tile_order = base + ctx->scratch_tiles;
     a.tile_hist = reinterpret_cast<unsigned*>(base + 2 * ctx->scratch_tiles);
   }
-  const hipError_t e = mfa::launch_render(a, static_cast<hipStream_t>(stream));
+  mfa::KernelEvents ev;
+  if (ctx->timing && ctx->timed < kMaxTimedLaunches) {
+    if (ctx->timed == ctx->events.size()) {
+      mfa::KernelEvents fresh;
+      hipError_t e = hipEventCreate(&fresh.begin);
+      if (e == hipSuccess) {
+        e = hipEventCreate(&fresh.end);
+        if (e != hipSuccess) (void)hipEventDestroy(fresh.begin);
+      }
+      if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("hipEventCreate", e));
+      ctx->events.push_back(fresh);
+    }
+    ev = ctx->events[ctx->timed];
+  }
+  const hipError_t e = mfa::launch_render(a, static_cast<hipStream_t>(stream), ev);
   if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("render launch", e));
+  if (ev.begin != nullptr) ctx->timed += 1;
+  return MFA_OK;
+}
+
+mfa_status mfa_kernel_timing(mfa_ctx* ctx, int32_t enable) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  ctx->timing = enable != 0;
+  ctx->timed = 0;
+  return MFA_OK;
+}
+
+mfa_status mfa_kernel_times(mfa_ctx* ctx, float* ms_host, int64_t cap, int64_t* count) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  if (count == nullptr || cap < 0 || (cap > 0 && ms_host == nullptr))
+    return fail(MFA_ERR_INVALID, "null count, negative cap or null ms_host");
+  DeviceGuard g(ctx->device);
+  if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
+  const size_t n = ctx->timed;
+  for (size_t i = 0; i < n; ++i) {
+    hipError_t e = hipEventSynchronize(ctx->events[i].end);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ctx->events[i].begin, ctx->events[i].end);
+    if (e != hipSuccess) {
+      ctx->timed = 0;
+      return fail(MFA_ERR_DEVICE, hip_msg("kernel timing events", e));
+    }
+    if (int64_t(i) < cap) ms_host[i] = ms;
+  }
+  *count = int64_t(n);
+  ctx->timed = 0;
   return MFA_OK;
 }
 

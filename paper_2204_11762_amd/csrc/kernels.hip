@@ -16,9 +16,12 @@
 //   5. looks up the RGBA transfer function, applies Phong shading from the
 //      analytic gradient, composites front to back and stops the ray once
 //      the accumulated opacity exceeds the limit.
-// One lane owns one ray; a 256-thread workgroup owns a 16x16 pixel tile,
-// each wave an 8x8 sub-tile, so that the rays of a wave gather from
-// neighbouring control points and share cache lines.
+// The main ray caster (render_brick_kernel) gives each wave a 4x4 pixel
+// tile with four lanes per ray and stages the control points of a round of
+// samples in LDS; the fallback (render_global_kernel, used when the knots
+// or transfer function do not fit in LDS) gives each lane one ray of a
+// 16x16 tile and gathers from global memory.  In both, neighbouring rays
+// run in one wave, so their gathers share cache lines.
 //
 // Mixed per-axis degrees run in the kernel of the largest degree P: an axis
 // of degree q < P uses the window of P+1 control points that starts at its
@@ -1174,32 +1177,45 @@ __global__ void zero_counter(unsigned long long* p) {
   if (threadIdx.x == 0) p[0] = 0ull;
 }
 
+// Events recorded around the ray-casting kernel alone (not the planning).
+hipError_t mark(hipEvent_t ev, hipStream_t st) {
+  return ev == nullptr ? hipSuccess : hipEventRecord(ev, st);
+}
+
 template <int P, int STORE, bool SHADE, bool FAST>
-hipError_t launch_brick(const RenderArgsDev& a, hipStream_t st) {
+hipError_t launch_brick(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
   const unsigned blocks = (unsigned)((a.ntiles + 255) / 256);
   plan_zero_kernel<<<1, 256, 0, st>>>(a.tile_hist);
   plan_cost_kernel<<<blocks, 256, 0, st>>>(a);
   plan_scan_kernel<<<1, kBuckets, 0, st>>>(a.tile_hist);
   plan_scatter_kernel<<<blocks, 256, 0, st>>>(a.tile_cost, a.ntiles, a.tile_hist, a.tile_order);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = mark(ev.begin, st);
+  if (e != hipSuccess) return e;
   render_brick_kernel<P, STORE, SHADE, FAST, kLanesPerRay><<<a.ntiles, 256, a.lds_bytes, st>>>(a);
-  return hipGetLastError();
+  e = hipGetLastError();
+  return e == hipSuccess ? mark(ev.end, st) : e;
 }
 
 template <int P, int STORE, bool SHADE>
-hipError_t launch_render_ps(const RenderArgsDev& a, hipStream_t st) {
+hipError_t launch_render_ps(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
   if (a.lds_bytes > 0) {
     const bool fast = a.m.uniform && a.m.ax[0].p >= 2 && a.m.ax[1].p >= 2 && a.m.ax[2].p >= 2;
-    return fast ? launch_brick<P, STORE, SHADE, true>(a, st)
-                : launch_brick<P, STORE, SHADE, false>(a, st);
+    return fast ? launch_brick<P, STORE, SHADE, true>(a, st, ev)
+                : launch_brick<P, STORE, SHADE, false>(a, st, ev);
   }
+  hipError_t e = mark(ev.begin, st);
+  if (e != hipSuccess) return e;
   const dim3 grid((a.width + 15) / 16, (a.height + 15) / 16);
   render_global_kernel<P, STORE, SHADE><<<grid, 256, 0, st>>>(a);
-  return hipGetLastError();
+  e = hipGetLastError();
+  return e == hipSuccess ? mark(ev.end, st) : e;
 }
 
 template <int P, int STORE>
-hipError_t launch_render_p(const RenderArgsDev& a, hipStream_t st) {
-  return a.shading ? launch_render_ps<P, STORE, true>(a, st) : launch_render_ps<P, STORE, false>(a, st);
+hipError_t launch_render_p(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
+  return a.shading ? launch_render_ps<P, STORE, true>(a, st, ev)
+                   : launch_render_ps<P, STORE, false>(a, st, ev);
 }
 
 template <int P, int STORE>
@@ -1213,12 +1229,12 @@ hipError_t launch_eval_p(const EvalArgsDev& a, hipStream_t st) {
 }
 
 template <int STORE>
-hipError_t dispatch_render(const RenderArgsDev& a, hipStream_t st) {
+hipError_t dispatch_render(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
   switch (a.m.pmax) {
-    case 1: return launch_render_p<1, STORE>(a, st);
-    case 2: return launch_render_p<2, STORE>(a, st);
-    case 3: return launch_render_p<3, STORE>(a, st);
-    case 4: return launch_render_p<4, STORE>(a, st);
+    case 1: return launch_render_p<1, STORE>(a, st, ev);
+    case 2: return launch_render_p<2, STORE>(a, st, ev);
+    case 3: return launch_render_p<3, STORE>(a, st, ev);
+    case 4: return launch_render_p<4, STORE>(a, st, ev);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1236,13 +1252,13 @@ hipError_t dispatch_eval(const EvalArgsDev& a, hipStream_t st) {
 
 }  // namespace
 
-hipError_t launch_render(const RenderArgsDev& a, hipStream_t st) {
+hipError_t launch_render(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
   if (a.samples != nullptr) {
     zero_counter<<<1, 64, 0, st>>>(a.samples);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return a.m.store == 0 ? dispatch_render<0>(a, st) : dispatch_render<1>(a, st);
+  return a.m.store == 0 ? dispatch_render<0>(a, st, ev) : dispatch_render<1>(a, st, ev);
 }
 
 hipError_t launch_eval(const EvalArgsDev& a, hipStream_t st) {

@@ -111,8 +111,15 @@ struct EvalArgsDev {
   int64_t n;
 };
 
+// Optional events recorded on the render stream immediately before and after
+// the ray-casting kernel (null: not recorded).
+struct KernelEvents {
+  hipEvent_t begin = nullptr;
+  hipEvent_t end = nullptr;
+};
+
 // Kernel launchers (kernels.hip).  Return hipSuccess or the launch error.
-hipError_t launch_render(const RenderArgsDev& a, hipStream_t stream);
+hipError_t launch_render(const RenderArgsDev& a, hipStream_t stream, const KernelEvents& ev);
 hipError_t launch_eval(const EvalArgsDev& a, hipStream_t stream);
 
 }  // namespace mfa

@@ -168,6 +168,9 @@ def test_null_context_and_handles(b):
     assert b.lib.mfa_set_memory_budget(None, 0) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_render(None, 1, None, None, None, None, None, None) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_eval_points(None, 1, 0, None, None, None, None) == b.MFA_ERR_HANDLE
+    assert b.lib.mfa_kernel_timing(None, 1) == b.MFA_ERR_HANDLE
+    n = C.c_int64()
+    assert b.lib.mfa_kernel_times(None, None, 0, C.byref(n)) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_destroy(None) == b.MFA_OK
     assert b.lib.mfa_create(0, None) == b.MFA_ERR_INVALID
 

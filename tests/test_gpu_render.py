@@ -139,6 +139,38 @@ def test_determinism_and_stream(mfa):
         b.mfa_model_free(ctx, h)
 
 
+def test_kernel_timing(mfa):
+    """The optional kernel events time every render while enabled, leave the
+    image unchanged, and record nothing once disabled."""
+    import time
+
+    import torch
+    b, ctx = mfa
+    wk = wl.c2()
+    wk.camera.width = wk.camera.height = 200
+    h = b.mfa_model_upload(ctx, wk.model)
+    try:
+        ref, _ = gpu_render(b, ctx, h, wk)
+        out = torch.zeros((200, 200, 4), dtype=torch.float32, device="cuda")
+        b.mfa_kernel_timing(ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            b.mfa_render(ctx, h, wk.camera, wk.tf, wk.params, out)
+        torch.cuda.synchronize()
+        wall_ms = (time.perf_counter() - t0) * 1e3
+        ms = b.mfa_kernel_times(ctx)
+        assert ms.shape == (3,) and np.all(ms > 0) and ms.sum() <= wall_ms
+        assert np.array_equal(out.cpu().numpy().astype(np.float64), ref)
+        assert b.mfa_kernel_times(ctx).shape == (0,)      # cleared by the read
+        b.mfa_kernel_timing(ctx, False)
+        b.mfa_render(ctx, h, wk.camera, wk.tf, wk.params, out)
+        assert b.mfa_kernel_times(ctx).shape == (0,)
+    finally:
+        b.mfa_kernel_timing(ctx, False)
+        b.mfa_model_free(ctx, h)
+
+
 def test_camera_inside_volume(mfa):
     b, ctx = mfa
     wk = wl.c2()

@@ -282,3 +282,39 @@ def test_bf16_rounding_known_values_and_torch():
     ref = torch.from_numpy(y.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
     np.testing.assert_array_equal(quant.dequant_bf16(y), ref)
     np.testing.assert_array_equal(quant.dequant_f32(y), y.astype(np.float32).astype(np.float64))
+
+
+def _golden_pieces():
+    import os
+    from fractions import Fraction
+    path = os.path.join(os.path.dirname(__file__), "golden", "cardinal_pieces.txt")
+    rows = []
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        p, t, i, n, dn = line.split()
+        rows.append((int(p), float(Fraction(t)), int(i), float(Fraction(n)),
+                     float(Fraction(dn))))
+    return rows
+
+
+def test_uniform_pieces_match_hand_derived_fixture():
+    """Interior spans of uniform clamped knots carry the cardinal pieces:
+    N at u = (j + t)/m and m dN/dt equal the exact rationals of the fixture,
+    on every interior span of a long knot vector (m = 12)."""
+    rows = _golden_pieces()
+    assert len(rows) == 4 * (2 + 3 + 4)
+    for p in (1, 2, 3):
+        m = 12
+        n = m + p
+        U = wl.clamped_uniform_knots(n, p)
+        for j in range(p, m - p):          # spans whose p+1 functions are all interior
+            s = j + p
+            for (q, t, i, nv, dv) in rows:
+                if q != p:
+                    continue
+                u = (j + t) / m
+                assert ob.find_span(n, p, U, u) == s
+                N, dN = ob.basis_local(s, u, p, U)
+                assert abs(N[i] - nv) <= 1e-14, (p, j, t, i)
+                assert abs(dN[i] - m * dv) <= 1e-12, (p, j, t, i)
