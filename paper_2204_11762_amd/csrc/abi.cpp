@@ -280,7 +280,7 @@ struct DeviceModel {
 };
 
 // LDS plan of the brick ray caster for one request: transfer function,
-// knots, then one brick per wave.  Workgroups are sized for four per CU;
+// knots (general path only), then one brick per wave.  Workgroups are sized for four per CU;
 // requests whose tables leave too little room use the global-memory
 // fallback kernel (lds_bytes = 0).
 constexpr int kLdsPerGroup = 40 * 1024;
@@ -291,7 +291,8 @@ void plan_bricks(const DeviceModel& dm, int ntf, double step, mfa::RenderArgsDev
   int knot_doubles = 0;
   for (int k = 0; k < 3; ++k) {
     a.knot_off[k] = knot_doubles;
-    knot_doubles += int(dm.nknots[k]);
+    // uniform knots are implied by their index on the fast path
+    if (!a.fast) knot_doubles += int(dm.nknots[k]);
   }
   const int knot_bytes = (knot_doubles * 8 + 15) & ~15;
   const int rest = kLdsPerGroup - tf_bytes - knot_bytes;
@@ -702,6 +703,7 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const 
   }
   a.out = rgba_dev;
   a.samples = reinterpret_cast<unsigned long long*>(samples_dev);
+  a.fast = dm.md.uniform && dm.md.ax[0].p >= 2 && dm.md.ax[1].p >= 2 && dm.md.ax[2].p >= 2;
   plan_bricks(dm, tf->n, prm->step, a);
   if (a.lds_bytes > 0) {
     const int64_t tiles = int64_t((cam->width + 2 * mfa::kTileW - 1) / (2 * mfa::kTileW)) *

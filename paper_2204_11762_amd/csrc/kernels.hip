@@ -747,21 +747,28 @@ __device__ __forceinline__ int div_small(int a, int b, float inv_b) {
 // stages, into its own LDS brick, every control point that the windows of
 // its active rays can touch during the round (the box of spans between the
 // smallest and largest parameters of the round's first and last samples);
-// the round's samples then gather from LDS.  If the box exceeds the brick
-// capacity the round gathers from global memory.  The four waves of a
-// workgroup share the transfer function and knots in LDS and never wait for
-// each other after loading them.  Which wave renders which tile does not
-// change any pixel: the arithmetic of a ray depends only on the ray.
+// the round's samples then gather from LDS.  The four waves of a workgroup
+// share the transfer function (and knots) in LDS and never wait for each
+// other after loading them.  Which wave renders which tile does not change
+// any pixel; on the FAST path the round boundaries of a ray (where FP32
+// stepping restarts from FP64) depend on the other live rays of its tile,
+// which moves results only at rounding level.
 //
-// Span location.  FAST (uniform knots on every axis, every degree >= 2):
-// at the start of a round each lane locates the exact span of its first
-// sample in FP64 and the local coordinate t = (u - U_s)(n - p) in it; the
-// samples of the round then advance t in FP32 (t + i * dt) and take the
-// cell floor(t).  A sample within FP32 rounding of a knot may use the
-// neighbouring polynomial piece, which for degree >= 2 gives the same value
-// and gradient up to rounding.  GENERAL: every sample's span is located
-// exactly in FP64 against the knots (cached bounds, stepping along the ray).
-template <int P, int STORE, bool SHADE, bool FAST, int LPR>
+// Span location.  FAST (uniform knots U_{p+j} = j/m on every axis, every
+// degree >= 2): at the start of a round each lane takes, in FP64, the cell
+// c = floor(u m) of its first sample and the local coordinate t = u m - c;
+// the samples of the round then advance t in FP32 (t + i * dt) and take the
+// cell floor(t).  The knots themselves are never read.  A sample within
+// rounding of a knot may use the neighbouring polynomial piece, which for
+// degree >= 2 gives the same value and gradient up to rounding.  GENERAL:
+// every sample's span is located exactly in FP64 against the knots (kept in
+// LDS; cached bounds, stepping along the ray).
+//
+// Round length.  A round starts at `spr` samples and is halved while the
+// box of control points it touches exceeds the brick, so that nearly every
+// round gathers from LDS; a round that still does not fit at two samples
+// per lane gathers from global memory.
+template <int P, int STORE, bool SHADE, bool FAST, bool EQ, int LPR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void render_brick_kernel(RenderArgsDev a) {
   static_assert(LPR == 1 || LPR == 2 || LPR == 4, "lanes per ray");
   constexpr int TW = LPR == 4 ? 4 : 8;        // tile width in pixels
@@ -776,10 +783,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
   float4* tf_lds = lds4;
   for (int i = tid; i < a.ntf; i += 256) tf_lds[i] = a.tf[i];
   double* knots = reinterpret_cast<double*>(lds + a.lds_knots);
+  if constexpr (!FAST) {
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int nk = a.m.ax[k].n + a.m.ax[k].p + 1;
-    for (int i = tid; i < nk; i += 256) knots[a.knot_off[k] + i] = a.m.ax[k].knots[i];
+    for (int k = 0; k < 3; ++k) {
+      const int nk = a.m.ax[k].n + a.m.ax[k].p + 1;
+      for (int i = tid; i < nk; i += 256) knots[a.knot_off[k] + i] = a.m.ax[k].knots[i];
+    }
   }
   __syncthreads();
   float* brick = reinterpret_cast<float*>(lds + a.lds_bricks) + wave * a.brick_cap;
@@ -851,50 +860,54 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
   }
   float cr = 0.0f, cg = 0.0f, cb = 0.0f, A = 0.0f;
 
-  for (int s0 = 0;; s0 += S) {
+  for (int s0 = 0, sr = S;; s0 += sr) {
     if (!__any(alive)) break;
-    const int s1 = alive ? min(s0 + S, nr) : s0;
-    // parameter box of the round
-    float lo_f[3], hi_f[3];
+    // A round covers samples [s0, s0 + sr) of every live ray of the wave.
+    // It starts at the full length and is halved while the control points
+    // it touches do not fit the brick, down to two samples per lane.
+    int s1, blo[3], bext[3], pitch_y, pitch_z, nel;
+    bool fits;
+    for (sr = S;; sr >>= 1) {
+      s1 = alive ? min(s0 + sr, nr) : s0;
+      // parameter box of the round
+      float lo_f[3], hi_f[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      float l = 2.0f, h = -1.0f;
-      if (alive) {
-        const double u0 = param(s0, k), u1 = param(s1 - 1, k);
-        l = (float)fmin(u0, u1) - 1e-6f;
-        h = (float)fmax(u0, u1) + 1e-6f;
+      for (int k = 0; k < 3; ++k) {
+        float l = 2.0f, h = -1.0f;
+        if (alive) {
+          const double u0 = param(s0, k), u1 = param(s1 - 1, k);
+          l = (float)fmin(u0, u1) - 1e-6f;
+          h = (float)fmax(u0, u1) + 1e-6f;
+        }
+        lo_f[k] = wave_minf(l);
+        hi_f[k] = wave_maxf(h);
       }
-      lo_f[k] = wave_minf(l);
-      hi_f[k] = wave_maxf(h);
-    }
-    // windows of the spans of the box corners
-    int blo[3], bext[3];
+      // windows of the spans of the box corners
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const AxisDev& Ax = a.m.ax[k];
-      const double ul = fmin(fmax((double)lo_f[k], 0.0), 1.0);
-      const double uh = fmin(fmax((double)hi_f[k], 0.0), 1.0);
-      int sl, sh;
-      if constexpr (FAST) {
-        // span estimate from u m, corrected by one step against the knots
-        const int m = Ax.n - Ax.p;
-        sl = Ax.p + min(max((int)(ul * Ax.m), 0), m - 1);
-        sh = Ax.p + min(max((int)(uh * Ax.m), 0), m - 1);
-        if (sl > Ax.p && K[k][sl] > ul) --sl;
-        if (sl < Ax.n - 1 && K[k][sl + 1] <= ul) ++sl;
-        if (sh > Ax.p && K[k][sh] > uh) --sh;
-        if (sh < Ax.n - 1 && K[k][sh + 1] <= uh) ++sh;
-      } else {
-        sl = lds_span_search(K[k], Ax.n, Ax.p, ul);
-        sh = lds_span_search(K[k], Ax.n, Ax.p, uh);
+      for (int k = 0; k < 3; ++k) {
+        const AxisDev& Ax = a.m.ax[k];
+        const int q = EQ ? P : Ax.p;
+        const double ul = fmin(fmax((double)lo_f[k], 0.0), 1.0);
+        const double uh = fmin(fmax((double)hi_f[k], 0.0), 1.0);
+        int sl, sh;
+        if constexpr (FAST) {
+          // cells of u m; a sample's cell (below) is computed the same way
+          const int m = Ax.n - q;
+          sl = q + min(max((int)(ul * Ax.m), 0), m - 1);
+          sh = q + min(max((int)(uh * Ax.m), 0), m - 1);
+        } else {
+          sl = lds_span_search(K[k], Ax.n, q, ul);
+          sh = lds_span_search(K[k], Ax.n, q, uh);
+        }
+        blo[k] = uniform_i(sl - q);
+        bext[k] = uniform_i(sh - sl + P + 1);
       }
-      blo[k] = uniform_i(sl - Ax.p);
-      bext[k] = uniform_i(sh - sl + P + 1);
+      pitch_y = (bext[0] + 3) & ~3;
+      pitch_z = pitch_y * bext[1];
+      nel = pitch_z * bext[2];
+      fits = nel <= a.brick_cap;
+      if (fits || sr <= 2 * LPR) break;
     }
-    const int pitch_y = (bext[0] + 3) & ~3;
-    const int pitch_z = pitch_y * bext[1];
-    const int nel = pitch_z * bext[2];
-    const bool fits = nel <= a.brick_cap;
 
     if (fits) {
       // stage the brick, four consecutive x values per lane and step
@@ -921,8 +934,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
     }
     const int emax = nel - 1 - (P + P * pitch_y + P * pitch_z);
 
-    // FAST: exact cell and local coordinate of this lane's first sample of
-    // the round
+    // FAST: cell c = floor(u m) (clamped to the spans) and local coordinate
+    // u m - c of this lane's first sample of the round, in FP64
     int ca[3] = {0, 0, 0};
     float ta[3] = {0.0f, 0.0f, 0.0f};
     if constexpr (FAST) {
@@ -930,15 +943,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           const AxisDev& Ax = a.m.ax[k];
-          const int m = Ax.n - Ax.p;
-          const double u = param(s0 + e, k);
-          int c = min(max((int)(u * Ax.m), 0), m - 1);
-          if (c > 0 && u < K[k][Ax.p + c])
-            --c;
-          else if (c < m - 1 && u >= K[k][Ax.p + c + 1])
-            ++c;
+          const int m = Ax.n - (EQ ? P : Ax.p);
+          const double um = param(s0 + e, k) * Ax.m;
+          const int c = min(max((int)um, 0), m - 1);
           ca[k] = c;
-          ta[k] = (float)((u - K[k][Ax.p + c]) * Ax.m);
+          ta[k] = (float)(um - (double)c);
         }
       }
     }
@@ -948,29 +957,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const AxisDev& Ax = a.m.ax[k];
+        const int q = EQ ? P : Ax.p;
         if constexpr (FAST) {
-          const int m = Ax.n - Ax.p;
+          const int m = Ax.n - q;
           const float t = fmaf((float)i, dt[k], ta[k]);
           const float fl = floorf(t);
           const int c = min(max(ca[k] + (int)fl, 0), m - 1);
           const float tl = t - (float)(c - ca[k]);
           w[k] = c;
-          if (c >= Ax.p - 1 && c <= m - Ax.p) {
-            cardinal_window<P>(Ax.p, tl, N[k], dN[k]);
+          if (c >= q - 1 && c <= m - q) {
+            if constexpr (EQ)
+              cardinal<P>(tl, N[k], dN[k]);
+            else
+              cardinal_window<P>(q, tl, N[k], dN[k]);
           } else {
             // boundary span: triangle with the span's reciprocal table
-            const float* row = Ax.tab + (size_t)c * (size_t)table_stride(Ax.p);
-            axis_basis<P>(Ax.p, row, tl * Ax.inv_m, N[k], dN[k]);
+            const float* row = Ax.tab + (size_t)c * (size_t)table_stride(q);
+            axis_basis<P>(q, row, tl * Ax.inv_m, N[k], dN[k]);
 #pragma unroll
-            for (int q = 0; q <= P; ++q) dN[k][q] *= Ax.inv_m;
+            for (int r = 0; r <= P; ++r) dN[k][r] *= Ax.inv_m;
           }
         } else {
           const double u = param(s, k);
-          span_step(K[k], Ax.n, Ax.p, u, st[k]);
+          span_step(K[k], Ax.n, q, u, st[k]);
           const float d = (float)(u - st[k].lo);
-          const float* row = Ax.tab + (size_t)(st[k].s - Ax.p) * (size_t)table_stride(Ax.p);
-          axis_basis<P>(Ax.p, row, d, N[k], dN[k]);
-          w[k] = st[k].s - Ax.p;
+          const float* row = Ax.tab + (size_t)(st[k].s - q) * (size_t)table_stride(q);
+          axis_basis<P>(q, row, d, N[k], dN[k]);
+          w[k] = st[k].s - q;
         }
       }
     };
@@ -1182,7 +1195,7 @@ hipError_t mark(hipEvent_t ev, hipStream_t st) {
   return ev == nullptr ? hipSuccess : hipEventRecord(ev, st);
 }
 
-template <int P, int STORE, bool SHADE, bool FAST>
+template <int P, int STORE, bool SHADE, bool FAST, bool EQ>
 hipError_t launch_brick(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
   const unsigned blocks = (unsigned)((a.ntiles + 255) / 256);
   plan_zero_kernel<<<1, 256, 0, st>>>(a.tile_hist);
@@ -1192,7 +1205,7 @@ hipError_t launch_brick(const RenderArgsDev& a, hipStream_t st, const KernelEven
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = mark(ev.begin, st);
   if (e != hipSuccess) return e;
-  render_brick_kernel<P, STORE, SHADE, FAST, kLanesPerRay><<<a.ntiles, 256, a.lds_bytes, st>>>(a);
+  render_brick_kernel<P, STORE, SHADE, FAST, EQ, kLanesPerRay><<<a.ntiles, 256, a.lds_bytes, st>>>(a);
   e = hipGetLastError();
   return e == hipSuccess ? mark(ev.end, st) : e;
 }
@@ -1200,9 +1213,15 @@ hipError_t launch_brick(const RenderArgsDev& a, hipStream_t st, const KernelEven
 template <int P, int STORE, bool SHADE>
 hipError_t launch_render_ps(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
   if (a.lds_bytes > 0) {
-    const bool fast = a.m.uniform && a.m.ax[0].p >= 2 && a.m.ax[1].p >= 2 && a.m.ax[2].p >= 2;
-    return fast ? launch_brick<P, STORE, SHADE, true>(a, st, ev)
-                : launch_brick<P, STORE, SHADE, false>(a, st, ev);
+    // EQ: every axis has the kernel's degree P (degree known at compile time)
+    const bool eq = a.m.ax[0].p == P && a.m.ax[1].p == P && a.m.ax[2].p == P;
+    if constexpr (P >= 2) {
+      if (a.fast)
+        return eq ? launch_brick<P, STORE, SHADE, true, true>(a, st, ev)
+                  : launch_brick<P, STORE, SHADE, true, false>(a, st, ev);
+    }
+    return eq ? launch_brick<P, STORE, SHADE, false, true>(a, st, ev)
+              : launch_brick<P, STORE, SHADE, false, false>(a, st, ev);
   }
   hipError_t e = mark(ev.begin, st);
   if (e != hipSuccess) return e;

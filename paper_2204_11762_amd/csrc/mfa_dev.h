@@ -84,13 +84,13 @@ struct RenderArgsDev {
   int32_t shininess;
   float ka, kd, ks;
   float light[3];       // unit vector towards the light
-  int32_t reserved;
+  int32_t fast;         // 1: uniform knots and every degree >= 2 (local-coordinate stepping)
   float* out;           // width*height*4
   unsigned long long* samples;  // nullable
   // LDS-brick ray marcher (render_brick_kernel); unused by the fallback
   int32_t spr;          // samples per round: each wave stages one brick per round
   int32_t brick_cap;    // floats of LDS per wave for its brick (multiple of 4)
-  int32_t lds_knots;    // byte offset of the knot vectors in dynamic LDS
+  int32_t lds_knots;    // byte offset of the knot vectors in dynamic LDS (not with fast)
   int32_t lds_bricks;   // byte offset of the bricks in dynamic LDS
   int32_t knot_off[3];  // offset (in doubles) of each axis' knots in LDS
   int32_t lds_bytes;    // dynamic LDS size of one workgroup
