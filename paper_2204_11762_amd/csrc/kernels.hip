@@ -694,16 +694,24 @@ __device__ __forceinline__ void axis_weights(const AxisDev& A, const SpanState& 
   }
 }
 
-__device__ __forceinline__ float wave_minf(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
-  return v;
-}
-
-__device__ __forceinline__ float wave_maxf(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-  return v;
+// Minimum (MAX = false) or maximum over the 64 lanes of a wave, returned as
+// a wave-uniform value.  Butterflies inside each row of 16 lanes by DPP
+// (pair swap, quad-half swap, half-row mirror, row mirror), then across
+// rows and halves with the row-swapping permutes.  Every lane of the wave
+// must be active.
+template <bool MAX>
+__device__ __forceinline__ unsigned wave_reduce_u32(unsigned v) {
+  auto op = [](unsigned x, unsigned y) { return MAX ? (x > y ? x : y) : (x < y ? x : y); };
+  constexpr int id = MAX ? 0 : -1;
+  v = op(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0xB1, 0xF, 0xF, false));
+  v = op(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x4E, 0xF, 0xF, false));
+  v = op(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x141, 0xF, 0xF, false));
+  v = op(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x140, 0xF, 0xF, false));
+  const auto r16 = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  v = op(r16[0], r16[1]);
+  const auto r32 = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  v = op(r32[0], r32[1]);
+  return __builtin_amdgcn_readfirstlane(v);
 }
 
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -869,35 +877,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
     bool fits;
     for (sr = S;; sr >>= 1) {
       s1 = alive ? min(s0 + sr, nr) : s0;
-      // parameter box of the round
-      float lo_f[3], hi_f[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        float l = 2.0f, h = -1.0f;
-        if (alive) {
-          const double u0 = param(s0, k), u1 = param(s1 - 1, k);
-          l = (float)fmin(u0, u1) - 1e-6f;
-          h = (float)fmax(u0, u1) + 1e-6f;
-        }
-        lo_f[k] = wave_minf(l);
-        hi_f[k] = wave_maxf(h);
-      }
-      // windows of the spans of the box corners
+      // spans of the parameter box of the round (with a margin of 1e-6 in
+      // u), reduced over the live rays of the wave
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const AxisDev& Ax = a.m.ax[k];
         const int q = EQ ? P : Ax.p;
-        const double ul = fmin(fmax((double)lo_f[k], 0.0), 1.0);
-        const double uh = fmin(fmax((double)hi_f[k], 0.0), 1.0);
+        unsigned l = 0xFFFFFFFFu, h = 0u;
+        if (alive) {
+          const double u0 = param(s0, k), u1 = param(s1 - 1, k);
+          const double ul = fmax(fmin(u0, u1) - 1e-6, 0.0);
+          const double uh = fmin(fmax(u0, u1) + 1e-6, 1.0);
+          if constexpr (FAST) {
+            // cells of u m; a sample's cell (below) is computed the same way
+            const int m = Ax.n - q;
+            l = (unsigned)min(max((int)(ul * Ax.m), 0), m - 1);
+            h = (unsigned)min(max((int)(uh * Ax.m), 0), m - 1);
+          } else {
+            // non-negative floats order as their bit patterns
+            l = __float_as_uint((float)ul);
+            h = __float_as_uint((float)uh);
+          }
+        }
+        l = wave_reduce_u32<false>(l);
+        h = wave_reduce_u32<true>(h);
         int sl, sh;
         if constexpr (FAST) {
-          // cells of u m; a sample's cell (below) is computed the same way
-          const int m = Ax.n - q;
-          sl = q + min(max((int)(ul * Ax.m), 0), m - 1);
-          sh = q + min(max((int)(uh * Ax.m), 0), m - 1);
+          sl = q + (int)l;
+          sh = q + (int)h;
         } else {
-          sl = lds_span_search(K[k], Ax.n, q, ul);
-          sh = lds_span_search(K[k], Ax.n, q, uh);
+          sl = lds_span_search(K[k], Ax.n, q, fmin((double)__uint_as_float(l), 1.0));
+          sh = lds_span_search(K[k], Ax.n, q, fmin((double)__uint_as_float(h), 1.0));
         }
         blo[k] = uniform_i(sl - q);
         bext[k] = uniform_i(sh - sl + P + 1);
@@ -910,26 +920,57 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
     }
 
     if (fits) {
-      // stage the brick, four consecutive x values per lane and step
+      // Stage the brick: group gi = ix + gx (jy + bext1 kz) holds the four
+      // consecutive x values starting at x = 4 ix of row (jy, kz), at LDS
+      // offset 4 gi.  Lane L takes groups L, L + 64, ...; its (ix, jy, kz)
+      // and global element index advance by the mixed-radix digits of 64.
       const int gx = pitch_y >> 2;
       const int gxy = gx * bext[1];
       const int ngroups = gxy * bext[2];
-      const float inv_gx = 1.0f / (float)gx;
-      const float inv_gxy = 1.0f / (float)gxy;
-      for (int gi = lane; gi < ngroups; gi += 64) {
-        const int kz = div_small(gi, gxy, inv_gxy);
-        const int rem = gi - kz * gxy;
-        const int jy = div_small(rem, gx, inv_gx);
-        const int ix4 = rem - jy * gx;
-        const int g = (blo[0] + 4 * ix4) + nx * (blo[1] + jy) + nxy * (blo[2] + kz);
-        float v[4];
-        load_row<3, STORE>(rs, g, v);
-        float4 w;
-        w.x = v[0];
-        w.y = v[1];
-        w.z = v[2];
-        w.w = v[3];
-        *reinterpret_cast<float4*>(brick + 4 * ix4 + pitch_y * jy + pitch_z * kz) = w;
+      const float inv_gx = __builtin_amdgcn_rcpf((float)gx);
+      const int d_row = uniform_i(div_small(64, gx, inv_gx));
+      const int d_ix = 64 - d_row * gx;
+      const int d_kz = uniform_i(div_small(d_row, bext[1], __builtin_amdgcn_rcpf((float)bext[1])));
+      const int d_jy = d_row - d_kz * bext[1];
+      const int dg = 4 * d_ix + nx * d_jy + nxy * d_kz;   // step without carries
+      const int dg_c1 = nx - 4 * gx;                      // carry ix -> jy
+      const int dg_c2 = nxy - nx * bext[1];               // carry jy -> kz
+      const int kz = div_small(lane, gxy, __builtin_amdgcn_rcpf((float)gxy));
+      const int rem = lane - kz * gxy;
+      int jy = div_small(rem, gx, inv_gx);
+      int ix = rem - jy * gx;
+      int g = (blo[0] + 4 * ix) + nx * (blo[1] + jy) + nxy * (blo[2] + kz);
+      // four groups per lane in flight: loads past the last group read
+      // element 0 (and are dropped), only the LDS stores are predicated
+      for (int gi = lane; gi < ngroups; gi += 256) {
+        float v[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          load_row<3, STORE>(rs, gi + 64 * u < ngroups ? g : 0, v[u]);
+          ix += d_ix;
+          jy += d_jy;
+          g += dg;
+          if (ix >= gx) {
+            ix -= gx;
+            jy += 1;
+            g += dg_c1;
+          }
+          if (jy >= bext[1]) {
+            jy -= bext[1];
+            g += dg_c2;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (gi + 64 * u < ngroups) {
+            float4 w;
+            w.x = v[u][0];
+            w.y = v[u][1];
+            w.z = v[u][2];
+            w.w = v[u][3];
+            *reinterpret_cast<float4*>(brick + 4 * (gi + 64 * u)) = w;
+          }
+        }
       }
     }
     const int emax = nel - 1 - (P + P * pitch_y + P * pitch_z);
