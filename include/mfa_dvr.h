@@ -155,7 +155,8 @@ mfa_status mfa_set_memory_budget(mfa_ctx* ctx, int64_t bytes);
  * than 2^31 bytes of control points). */
 mfa_status mfa_model_upload(mfa_ctx* ctx, const mfa_model_desc* desc, int64_t* model_out);
 
-/* Release a model after synchronising the device.  Errors: MFA_ERR_HANDLE. */
+/* Release a model after synchronising the device.  Errors: MFA_ERR_HANDLE,
+ * MFA_ERR_INVALID (the model is used by a live batch). */
 mfa_status mfa_model_free(mfa_ctx* ctx, int64_t model);
 
 /* Device bytes held by a model.  Errors: MFA_ERR_HANDLE, MFA_ERR_INVALID. */
@@ -172,6 +173,47 @@ mfa_status mfa_model_bytes(mfa_ctx* ctx, int64_t model, int64_t* bytes_out);
 mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* camera, const mfa_tf* tf,
                       const mfa_render_params* params, float* rgba_dev, int64_t* samples_dev,
                       void* stream);
+
+/* One request of a render batch: the arguments of one mfa_render call. */
+typedef struct mfa_render_request {
+  int64_t model;
+  const mfa_camera* camera;
+  const mfa_tf* tf;
+  const mfa_render_params* params;
+  float* rgba_dev;      /* width*height*4 FP32, caller-owned device memory */
+  int64_t* samples_dev; /* nullable; one int64 of device memory */
+} mfa_render_request;
+
+/* Prepare a batch of n render requests, each the problem of Algorithm 1
+ * for its own model, camera, transfer function and parameters (different
+ * models, image sizes and views may be mixed).  Every request is checked
+ * as mfa_render checks it; the output buffers (images and counters) of a
+ * batch must not overlap.  The call copies what the requests point to
+ * (cameras, tables, parameters), uploads the per-request kernel records
+ * and planning space to device memory (counted against the memory budget)
+ * and returns synchronously; the caller's host structures may be freed at
+ * once.  The output pointers are bound to the batch.  The models stay in
+ * use until the batch is freed (mfa_model_free refuses them meanwhile).
+ * *batch_out receives a handle > 0.  Errors: MFA_ERR_INVALID (n outside
+ * [1, 65536], null pointers, overlapping outputs, or any request that
+ * mfa_render would reject; the message names the request), MFA_ERR_HANDLE,
+ * MFA_ERR_NOMEM, MFA_ERR_DEVICE. */
+mfa_status mfa_batch_create(mfa_ctx* ctx, const mfa_render_request* reqs, int32_t n,
+                            int64_t* batch_out);
+
+/* Render every request of a batch on `stream`, asynchronously: per kernel
+ * variant one work estimate and ordering pass over the tiles of all its
+ * requests, longest first, and one ray-casting launch over them.  Each
+ * image equals the image of mfa_render for the same request bit for bit.
+ * The call only enqueues kernels (no allocation, copy or fill), so it can
+ * be captured in a HIP graph and replayed.  A batch must not be rendered
+ * on two streams at once (its planning space is shared).  Errors:
+ * MFA_ERR_HANDLE, MFA_ERR_DEVICE. */
+mfa_status mfa_batch_render(mfa_ctx* ctx, int64_t batch, void* stream);
+
+/* Synchronise the device and release a batch.  Errors: MFA_ERR_HANDLE,
+ * MFA_ERR_DEVICE. */
+mfa_status mfa_batch_free(mfa_ctx* ctx, int64_t batch);
 
 /* Kernel timing for measurement.  While enabled, every mfa_render call
  * records a pair of HIP events on its stream immediately around the

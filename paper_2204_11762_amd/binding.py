@@ -33,7 +33,8 @@ MFA_CAMERA_PERSP = 1
 
 EXPORTED = ("mfa_create", "mfa_destroy", "mfa_set_memory_budget", "mfa_model_upload",
             "mfa_model_free", "mfa_model_bytes", "mfa_render", "mfa_eval_points",
-            "mfa_kernel_timing", "mfa_kernel_times", "mfa_validate_model",
+            "mfa_kernel_timing", "mfa_kernel_times", "mfa_batch_create", "mfa_batch_render",
+            "mfa_batch_free", "mfa_validate_model",
             "mfa_validate_render", "mfa_last_error", "mfa_version")
 
 
@@ -69,6 +70,12 @@ class RenderParams(C.Structure):
                 ("light_dir", C.c_double * 3)]
 
 
+class RenderRequest(C.Structure):
+    _fields_ = [("model", C.c_int64), ("camera", C.POINTER(Camera)), ("tf", C.POINTER(TF)),
+                ("params", C.POINTER(RenderParams)), ("rgba_dev", C.c_void_p),
+                ("samples_dev", C.c_void_p)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
@@ -88,6 +95,9 @@ def _load():
                             vp, vp, vp]),
         "mfa_eval_points": (st, [vp, i64, i64, vp, vp, vp, vp]),
         "mfa_kernel_timing": (st, [vp, C.c_int32]),
+        "mfa_batch_create": (st, [vp, C.POINTER(RenderRequest), C.c_int32, C.POINTER(i64)]),
+        "mfa_batch_render": (st, [vp, i64, vp]),
+        "mfa_batch_free": (st, [vp, i64]),
         "mfa_kernel_times": (st, [vp, vp, i64, C.POINTER(i64)]),
         "mfa_validate_model": (st, [C.POINTER(ModelDesc)]),
         "mfa_validate_render": (st, [C.POINTER(Camera), C.POINTER(TF), C.POINTER(RenderParams)]),
@@ -267,6 +277,40 @@ def mfa_render(ctx: int, model: int, camera, tf, params, rgba, samples=None, str
     t, keep = tf_struct(tf)
     _check(lib.mfa_render(ctx, int(model), C.byref(camera_struct(camera)), C.byref(t),
                           C.byref(params_struct(params)), out, sp, _stream_ptr(stream)))
+
+
+def mfa_batch_create(ctx: int, requests) -> int:
+    """Prepare a batch from ``requests``: a sequence of (model, camera, tf,
+    params, rgba, samples) with ``rgba`` an (H, W, 4) float32 CUDA tensor and
+    ``samples`` a one-element int64 CUDA tensor or None.  The tensors must
+    outlive the batch."""
+    import torch
+    reqs = list(requests)
+    arr = (RenderRequest * len(reqs))()
+    keep = []
+    for i, (model, cam, tf, params, rgba, samples) in enumerate(reqs):
+        c = camera_struct(cam)
+        t, k = tf_struct(tf)
+        p = params_struct(params)
+        keep += [c, t, k, p]
+        arr[i].model = int(model)
+        arr[i].camera = C.pointer(c)
+        arr[i].tf = C.pointer(t)
+        arr[i].params = C.pointer(p)
+        arr[i].rgba_dev = _dev_tensor(rgba, torch.float32, (cam.height, cam.width, 4), "rgba")
+        arr[i].samples_dev = (None if samples is None
+                              else _dev_tensor(samples, torch.int64, (1,), "samples"))
+    h = C.c_int64()
+    _check(lib.mfa_batch_create(ctx, arr, len(reqs), C.byref(h)))
+    return h.value
+
+
+def mfa_batch_render(ctx: int, batch: int, stream=None) -> None:
+    _check(lib.mfa_batch_render(ctx, int(batch), _stream_ptr(stream)))
+
+
+def mfa_batch_free(ctx: int, batch: int) -> None:
+    _check(lib.mfa_batch_free(ctx, int(batch)))
 
 
 def mfa_kernel_timing(ctx: int, enable: bool) -> None:

@@ -35,6 +35,8 @@ constexpr int kCtrlPadElems = 16;                // zero padding after the contr
 constexpr int64_t kMaxPixels = int64_t(1) << 26;
 constexpr int kMaxImageSide = 1 << 15;
 constexpr int64_t kMaxEvalPoints = int64_t(1) << 38;
+// Requests of one render batch.
+constexpr int32_t kMaxBatch = 1 << 16;
 constexpr size_t kMaxCachedTF = 64;
 // Render launches whose kernel duration one timing record holds.
 constexpr size_t kMaxTimedLaunches = 1 << 16;
@@ -277,13 +279,13 @@ struct DeviceModel {
   mfa::ModelDev md{};
   double lo[3], hi[3];
   int64_t nknots[3];
+  int64_t batch_refs = 0;  // live batches that render this model
 };
 
 // LDS plan of the brick ray caster for one request: transfer function,
 // knots (general path only), then one brick per wave.  Workgroups are sized for four per CU;
 // requests whose tables leave too little room use the global-memory
 // fallback kernel (lds_bytes = 0).
-constexpr int kLdsPerGroup = 40 * 1024;
 constexpr int kMinBrick = 512;
 
 void plan_bricks(const DeviceModel& dm, int ntf, double step, mfa::RenderArgsDev& a) {
@@ -295,7 +297,9 @@ void plan_bricks(const DeviceModel& dm, int ntf, double step, mfa::RenderArgsDev
     if (!a.fast) knot_doubles += int(dm.nknots[k]);
   }
   const int knot_bytes = (knot_doubles * 8 + 15) & ~15;
-  const int rest = kLdsPerGroup - tf_bytes - knot_bytes;
+  const int lds_budget =
+      mfa::brick_lds_per_group(mfa::brick_waves_per_simd(dm.md.pmax, a.fast != 0, a.eq != 0));
+  const int rest = lds_budget - tf_bytes - knot_bytes;
   const int cap = (rest / (4 * 4)) & ~3;
   if (cap < kMinBrick) {
     a.lds_bytes = 0;
@@ -350,12 +354,25 @@ class DeviceGuard {
 
 }  // namespace
 
+// A prepared render batch: one device allocation holding the requests'
+// kernel records, transfer-function tables and planning scratch, grouped by
+// kernel variant; requests that need the global-memory kernel are launched
+// one by one from host copies of their records.
+struct RenderBatch {
+  void* mem = nullptr;
+  int64_t bytes = 0;
+  std::vector<std::pair<mfa::BatchKey, mfa::BatchDev>> classes;
+  std::vector<mfa::RenderArgsDev> single;
+  std::vector<int64_t> models;
+};
+
 struct mfa_ctx {
   int device = 0;
   int64_t budget = 0;
   int64_t used = 0;
   int64_t next_id = 1;
   std::unordered_map<int64_t, DeviceModel> models;
+  std::unordered_map<int64_t, RenderBatch> batches;
   std::unordered_map<uint64_t, std::vector<TFEntry>> tfs;
   size_t n_tf = 0;
   // scratch of the tile sort: cost and order arrays of `scratch_tiles`
@@ -486,6 +503,8 @@ mfa_status mfa_destroy(mfa_ctx* ctx) {
     DeviceGuard g(ctx->device);
     const hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) st = fail(MFA_ERR_DEVICE, hip_msg("hipDeviceSynchronize", e));
+    for (auto& kv : ctx->batches) (void)hipFree(kv.second.mem);
+    ctx->batches.clear();
     for (auto& kv : ctx->models) (void)hipFree(kv.second.mem);
     ctx->models.clear();
     ctx->free_tfs();
@@ -612,6 +631,7 @@ mfa_status mfa_model_free(mfa_ctx* ctx, int64_t model) {
   if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
   auto it = ctx->models.find(model);
   if (it == ctx->models.end()) return fail(MFA_ERR_HANDLE, "unknown model handle");
+  if (it->second.batch_refs > 0) return fail(MFA_ERR_INVALID, "model is used by a live batch");
   DeviceGuard g(ctx->device);
   const hipError_t e = hipDeviceSynchronize();
   (void)hipFree(it->second.mem);
@@ -631,33 +651,35 @@ mfa_status mfa_model_bytes(mfa_ctx* ctx, int64_t model, int64_t* bytes_out) {
   return MFA_OK;
 }
 
-mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const mfa_tf* tf,
-                      const mfa_render_params* prm, float* rgba_dev, int64_t* samples_dev,
-                      void* stream) {
-  g_last_error.clear();
-  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
-  auto it = ctx->models.find(model);
-  if (it == ctx->models.end()) return fail(MFA_ERR_HANDLE, "unknown model handle");
+}  // extern "C"
+
+namespace {
+
+// Host checks of one render request beyond validate_render: the output
+// buffer and the number of samples per ray.
+mfa_status check_request(const DeviceModel& dm, const mfa_camera* cam, const mfa_tf* tf,
+                         const mfa_render_params* prm, const float* rgba_dev) {
   std::string msg;
-  mfa_status st = validate_render(cam, tf, prm, msg);
+  const mfa_status st = validate_render(cam, tf, prm, msg);
   if (st != MFA_OK) return fail(st, msg);
   if (rgba_dev == nullptr) return fail(MFA_ERR_INVALID, "null rgba_dev");
-  const DeviceModel& dm = it->second;
   double diag2 = 0.0;
   for (int k = 0; k < 3; ++k) diag2 += (dm.hi[k] - dm.lo[k]) * (dm.hi[k] - dm.lo[k]);
   if (std::sqrt(diag2) / prm->step > double(mfa::kMaxSamplesPerRay))
     return fail(MFA_ERR_INVALID, "step too small: more than 65536 samples per ray");
+  return MFA_OK;
+}
 
+// Kernel record of one validated request (camera frame, transfer function
+// at tf_dev, shading, LDS plan).  The tile-plan scratch pointers are left
+// for the caller; ntiles receives the request's super-tiles (0 when the
+// request uses the global-memory kernel).
+void build_render_args(const DeviceModel& dm, const mfa_camera* cam, const mfa_tf* tf,
+                       const mfa_render_params* prm, float* rgba_dev, int64_t* samples_dev,
+                       float4* tf_dev, mfa::RenderArgsDev& a) {
   Frame fr;
   camera_frame(cam, fr);
-
-  DeviceGuard g(ctx->device);
-  if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
-  float4* tf_dev = nullptr;
-  st = tf_device(ctx, tf, &tf_dev);
-  if (st != MFA_OK) return st;
-
-  mfa::RenderArgsDev a{};
+  a = mfa::RenderArgsDev{};
   a.m = dm.md;
   a.kind = cam->kind;
   a.width = cam->width;
@@ -704,16 +726,43 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const 
   a.out = rgba_dev;
   a.samples = reinterpret_cast<unsigned long long*>(samples_dev);
   a.fast = dm.md.uniform && dm.md.ax[0].p >= 2 && dm.md.ax[1].p >= 2 && dm.md.ax[2].p >= 2;
+  a.eq = dm.md.ax[0].p == dm.md.pmax && dm.md.ax[1].p == dm.md.pmax && dm.md.ax[2].p == dm.md.pmax;
   plan_bricks(dm, tf->n, prm->step, a);
-  if (a.lds_bytes > 0) {
-    const int64_t tiles = int64_t((cam->width + 2 * mfa::kTileW - 1) / (2 * mfa::kTileW)) *
-                          int64_t((cam->height + 2 * mfa::kTileH - 1) / (2 * mfa::kTileH));
-    a.tile_w = mfa::kTileW;
-    a.tile_h = mfa::kTileH;
-    st = ensure_scratch(ctx, tiles);
+  a.tile_w = mfa::kTileW;
+  a.tile_h = mfa::kTileH;
+  a.ntiles = 0;
+  if (a.lds_bytes > 0)
+    a.ntiles = int32_t(int64_t((cam->width + 2 * mfa::kTileW - 1) / (2 * mfa::kTileW)) *
+                       int64_t((cam->height + 2 * mfa::kTileH - 1) / (2 * mfa::kTileH)));
+}
+
+}  // namespace
+
+extern "C" {
+
+mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const mfa_tf* tf,
+                      const mfa_render_params* prm, float* rgba_dev, int64_t* samples_dev,
+                      void* stream) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  auto it = ctx->models.find(model);
+  if (it == ctx->models.end()) return fail(MFA_ERR_HANDLE, "unknown model handle");
+  const DeviceModel& dm = it->second;
+  mfa_status st = check_request(dm, cam, tf, prm, rgba_dev);
+  if (st != MFA_OK) return st;
+
+  DeviceGuard g(ctx->device);
+  if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
+  float4* tf_dev = nullptr;
+  st = tf_device(ctx, tf, &tf_dev);
+  if (st != MFA_OK) return st;
+
+  mfa::RenderArgsDev a;
+  build_render_args(dm, cam, tf, prm, rgba_dev, samples_dev, tf_dev, a);
+  if (a.ntiles > 0) {
+    st = ensure_scratch(ctx, a.ntiles);
     if (st != MFA_OK) return st;
     int32_t* base = static_cast<int32_t*>(ctx->scratch);
-    a.ntiles = int32_t(tiles);
     a.tile_cost = base;
     a.tile_order = base + ctx->scratch_tiles;
     a.tile_hist = reinterpret_cast<unsigned*>(base + 2 * ctx->scratch_tiles);
@@ -766,6 +815,179 @@ mfa_status mfa_kernel_times(mfa_ctx* ctx, float* ms_host, int64_t cap, int64_t* 
   }
   *count = int64_t(n);
   ctx->timed = 0;
+  return MFA_OK;
+}
+
+mfa_status mfa_batch_create(mfa_ctx* ctx, const mfa_render_request* reqs, int32_t n,
+                            int64_t* batch_out) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  if (batch_out == nullptr || reqs == nullptr) return fail(MFA_ERR_INVALID, "null argument");
+  if (n < 1 || n > kMaxBatch) return fail(MFA_ERR_INVALID, "batch size must be in [1, 65536]");
+  // validate every request; output ranges must not overlap
+  std::vector<std::pair<uintptr_t, uintptr_t>> ranges;
+  for (int32_t i = 0; i < n; ++i) {
+    const mfa_render_request& r = reqs[i];
+    auto it = ctx->models.find(r.model);
+    if (it == ctx->models.end()) return fail(MFA_ERR_HANDLE, "unknown model handle in batch");
+    const mfa_status st = check_request(it->second, r.camera, r.tf, r.params, r.rgba_dev);
+    if (st != MFA_OK) return fail(st, "request " + std::to_string(i) + ": " + g_last_error);
+    const uintptr_t o = reinterpret_cast<uintptr_t>(r.rgba_dev);
+    ranges.emplace_back(o, o + size_t(r.camera->width) * size_t(r.camera->height) * 16);
+    if (r.samples_dev != nullptr) {
+      const uintptr_t c = reinterpret_cast<uintptr_t>(r.samples_dev);
+      ranges.emplace_back(c, c + sizeof(int64_t));
+    }
+  }
+  std::sort(ranges.begin(), ranges.end());
+  for (size_t i = 1; i < ranges.size(); ++i)
+    if (ranges[i].first < ranges[i - 1].second)
+      return fail(MFA_ERR_INVALID, "output buffers of a batch overlap");
+
+  // records with placeholder transfer-function pointers, grouped by variant
+  std::vector<mfa::RenderArgsDev> args(n);
+  std::vector<size_t> tf_off(n);
+  size_t off = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const mfa_render_request& r = reqs[i];
+    build_render_args(ctx->models[r.model], r.camera, r.tf, r.params, r.rgba_dev, r.samples_dev,
+                      nullptr, args[i]);
+    tf_off[i] = off;
+    off = align256(off + size_t(r.tf->n) * 16);
+  }
+  struct Group {
+    mfa::BatchKey key;
+    std::vector<int32_t> reqs;
+    size_t off_args, off_base, off_cost, off_order, off_hist;
+    int64_t ntiles;
+  };
+  std::vector<Group> groups;
+  std::vector<int32_t> single;
+  for (int32_t i = 0; i < n; ++i) {
+    const mfa::RenderArgsDev& a = args[i];
+    if (a.ntiles == 0) {
+      single.push_back(i);
+      continue;
+    }
+    const mfa::BatchKey k{a.m.pmax, a.m.store, a.shading, a.fast, a.eq, 0};
+    Group* gp = nullptr;
+    for (auto& g : groups)
+      if (g.key.pmax == k.pmax && g.key.store == k.store && g.key.shading == k.shading &&
+          g.key.fast == k.fast && g.key.eq == k.eq)
+        gp = &g;
+    if (gp == nullptr) {
+      groups.push_back(Group{k, {}, 0, 0, 0, 0, 0, 0});
+      gp = &groups.back();
+    }
+    gp->reqs.push_back(i);
+    gp->key.lds_bytes = std::max(gp->key.lds_bytes, a.lds_bytes);
+    gp->ntiles += a.ntiles;
+  }
+  for (auto& g : groups) {
+    if (g.ntiles > int64_t(INT32_MAX)) return fail(MFA_ERR_INVALID, "batch has too many tiles");
+    g.off_args = off;
+    off = align256(off + sizeof(mfa::RenderArgsDev) * g.reqs.size());
+    g.off_base = off;
+    off = align256(off + sizeof(int32_t) * (g.reqs.size() + 1));
+    g.off_cost = off;
+    off = align256(off + sizeof(int32_t) * size_t(g.ntiles));
+    g.off_order = off;
+    off = align256(off + sizeof(int32_t) * size_t(g.ntiles));
+    g.off_hist = off;
+    off = align256(off + 4096);
+  }
+  const size_t bytes = off;
+  if (ctx->budget > 0 && ctx->used + int64_t(bytes) > ctx->budget)
+    return fail(MFA_ERR_NOMEM, "batch exceeds the context's memory budget");
+
+  DeviceGuard g(ctx->device);
+  if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
+  void* mem = nullptr;
+  hipError_t e = hipMalloc(&mem, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MFA_ERR_NOMEM, hip_msg("hipMalloc (batch)", e));
+  }
+  char* dev = static_cast<char*>(mem);
+  std::vector<unsigned char> host(bytes, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    std::memcpy(host.data() + tf_off[i], reqs[i].tf->rgba, size_t(reqs[i].tf->n) * 16);
+    args[i].tf = reinterpret_cast<const float4*>(dev + tf_off[i]);
+  }
+  RenderBatch b;
+  b.mem = mem;
+  b.bytes = int64_t(bytes);
+  for (auto& gr : groups) {
+    mfa::BatchDev bd{};
+    bd.args = reinterpret_cast<const mfa::RenderArgsDev*>(dev + gr.off_args);
+    bd.tile_base = reinterpret_cast<const int32_t*>(dev + gr.off_base);
+    bd.nreq = int32_t(gr.reqs.size());
+    bd.ntiles = int32_t(gr.ntiles);
+    bd.tile_cost = reinterpret_cast<int32_t*>(dev + gr.off_cost);
+    bd.tile_order = reinterpret_cast<int32_t*>(dev + gr.off_order);
+    bd.tile_hist = reinterpret_cast<unsigned*>(dev + gr.off_hist);
+    auto* ha = reinterpret_cast<mfa::RenderArgsDev*>(host.data() + gr.off_args);
+    auto* hb = reinterpret_cast<int32_t*>(host.data() + gr.off_base);
+    int32_t acc = 0;
+    for (size_t j = 0; j < gr.reqs.size(); ++j) {
+      ha[j] = args[gr.reqs[j]];
+      hb[j] = acc;
+      acc += ha[j].ntiles;
+    }
+    hb[gr.reqs.size()] = acc;
+    b.classes.emplace_back(gr.key, bd);
+  }
+  for (int32_t i : single) b.single.push_back(args[i]);
+  e = hipMemcpy(mem, host.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(mem);
+    return fail(MFA_ERR_DEVICE, hip_msg("hipMemcpy (batch)", e));
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    ctx->models[reqs[i].model].batch_refs += 1;
+    b.models.push_back(reqs[i].model);
+  }
+  ctx->used += b.bytes;
+  const int64_t id = ctx->next_id++;
+  ctx->batches.emplace(id, std::move(b));
+  *batch_out = id;
+  return MFA_OK;
+}
+
+mfa_status mfa_batch_render(mfa_ctx* ctx, int64_t batch, void* stream) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  auto it = ctx->batches.find(batch);
+  if (it == ctx->batches.end()) return fail(MFA_ERR_HANDLE, "unknown batch handle");
+  DeviceGuard g(ctx->device);
+  if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  for (const auto& c : it->second.classes) {
+    const hipError_t e = mfa::launch_render_batch(c.second, c.first, st);
+    if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("batch launch", e));
+  }
+  for (const auto& a : it->second.single) {
+    const hipError_t e = mfa::launch_render(a, st, mfa::KernelEvents{});
+    if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("batch launch", e));
+  }
+  return MFA_OK;
+}
+
+mfa_status mfa_batch_free(mfa_ctx* ctx, int64_t batch) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  auto it = ctx->batches.find(batch);
+  if (it == ctx->batches.end()) return fail(MFA_ERR_HANDLE, "unknown batch handle");
+  DeviceGuard g(ctx->device);
+  const hipError_t e = hipDeviceSynchronize();
+  (void)hipFree(it->second.mem);
+  ctx->used -= it->second.bytes;
+  for (int64_t m : it->second.models) {
+    auto mi = ctx->models.find(m);
+    if (mi != ctx->models.end()) mi->second.batch_refs -= 1;
+  }
+  ctx->batches.erase(it);
+  if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("hipDeviceSynchronize", e));
   return MFA_OK;
 }
 

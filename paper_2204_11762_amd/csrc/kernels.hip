@@ -777,7 +777,7 @@ __device__ __forceinline__ int div_small(int a, int b, float inv_b) {
 // round gathers from LDS; a round that still does not fit at two samples
 // per lane gathers from global memory.
 template <int P, int STORE, bool SHADE, bool FAST, bool EQ, int LPR>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void render_brick_kernel(RenderArgsDev a) {
+__device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
   static_assert(LPR == 1 || LPR == 2 || LPR == 4, "lanes per ray");
   constexpr int TW = LPR == 4 ? 4 : 8;        // tile width in pixels
   constexpr int TH = 64 / LPR / TW;           // tile height
@@ -815,9 +815,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
     gfac[k] = FAST ? a.m.ax[k].gscale * (float)a.m.ax[k].m : a.m.ax[k].gscale;
   int count = 0;
 
-  // workgroup b takes super-tile order[b] (2x2 tiles), wave w its quadrant
+  // the workgroup renders super-tile sup (2x2 tiles), wave w its quadrant
   const int nsx = (ntx + 1) >> 1;
-  const int sup = uniform_i(a.tile_order[blockIdx.x]);
   const int tx = (sup % nsx) * 2 + (wave & 1);
   const int ty = (sup / nsx) * 2 + (wave >> 1);
   const int px = tx * TW + ray_lane % TW;
@@ -1116,6 +1115,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
   count_samples(a, count, lane);
 }
 
+template <int P, int STORE, bool SHADE, bool FAST, bool EQ, int LPR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    brick_waves_per_simd(P, FAST, EQ)))) void render_brick_kernel(RenderArgsDev a) {
+  brick_render<P, STORE, SHADE, FAST, EQ, LPR>(a, uniform_i(a.tile_order[blockIdx.x]));
+}
+
+// Request of global super-tile t of a batch class: the largest r with
+// base[r] <= t (base holds the prefix sums of the requests' super-tiles).
+__device__ __forceinline__ int batch_request(const int32_t* base, int nreq, int t) {
+  int lo = 0, hi = nreq;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (base[mid] <= t)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// The same ray caster over the super-tiles of every request of a batch
+// class; workgroup b renders entry b of the class's work-sorted list.
+template <int P, int STORE, bool SHADE, bool FAST, bool EQ, int LPR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    brick_waves_per_simd(P, FAST, EQ)))) void render_batch_kernel(BatchDev b) {
+  const int t = uniform_i(b.tile_order[blockIdx.x]);
+  const int r = uniform_i(batch_request(b.tile_base, b.nreq, t));
+  brick_render<P, STORE, SHADE, FAST, EQ, LPR>(b.args[r], t - b.tile_base[r]);
+}
+
 // ---------------------------------------------------------------------------
 // tile order: counting sort of the tiles by decreasing estimated work
 // ---------------------------------------------------------------------------
@@ -1133,6 +1162,26 @@ __global__ __launch_bounds__(256) void plan_zero_kernel(unsigned* hist) {
 // the largest sample count among nine rays (corners, edge midpoints and
 // centre of its pixel rectangle); and the histogram of the estimates'
 // buckets.
+__device__ __forceinline__ int supertile_cost(const RenderArgsDev& a, int t) {
+  const int ntx = (a.width + a.tile_w - 1) / a.tile_w;
+  const int nsx = (ntx + 1) >> 1;
+  const int x0 = (t % nsx) * 2 * a.tile_w, y0 = (t / nsx) * 2 * a.tile_h;
+  const int x1 = min(x0 + 2 * a.tile_w - 1, a.width - 1);
+  const int y1 = min(y0 + 2 * a.tile_h - 1, a.height - 1);
+  const int xm = (x0 + x1) >> 1, ym = (y0 + y1) >> 1;
+  int c = 0;
+  c = max(c, make_ray(a.cam, y0, x0).nr);
+  c = max(c, make_ray(a.cam, y0, xm).nr);
+  c = max(c, make_ray(a.cam, y0, x1).nr);
+  c = max(c, make_ray(a.cam, ym, x0).nr);
+  c = max(c, make_ray(a.cam, ym, xm).nr);
+  c = max(c, make_ray(a.cam, ym, x1).nr);
+  c = max(c, make_ray(a.cam, y1, x0).nr);
+  c = max(c, make_ray(a.cam, y1, xm).nr);
+  c = max(c, make_ray(a.cam, y1, x1).nr);
+  return c;
+}
+
 __global__ __launch_bounds__(256) void plan_cost_kernel(RenderArgsDev a) {
   __shared__ unsigned h[kBuckets];
   const int tid = threadIdx.x;
@@ -1140,22 +1189,7 @@ __global__ __launch_bounds__(256) void plan_cost_kernel(RenderArgsDev a) {
   __syncthreads();
   const int t = blockIdx.x * 256 + tid;
   if (t < a.ntiles) {
-    const int ntx = (a.width + a.tile_w - 1) / a.tile_w;
-    const int nsx = (ntx + 1) >> 1;
-    const int x0 = (t % nsx) * 2 * a.tile_w, y0 = (t / nsx) * 2 * a.tile_h;
-    const int x1 = min(x0 + 2 * a.tile_w - 1, a.width - 1);
-    const int y1 = min(y0 + 2 * a.tile_h - 1, a.height - 1);
-    const int xm = (x0 + x1) >> 1, ym = (y0 + y1) >> 1;
-    int c = 0;
-    c = max(c, make_ray(a.cam, y0, x0).nr);
-    c = max(c, make_ray(a.cam, y0, xm).nr);
-    c = max(c, make_ray(a.cam, y0, x1).nr);
-    c = max(c, make_ray(a.cam, ym, x0).nr);
-    c = max(c, make_ray(a.cam, ym, xm).nr);
-    c = max(c, make_ray(a.cam, ym, x1).nr);
-    c = max(c, make_ray(a.cam, y1, x0).nr);
-    c = max(c, make_ray(a.cam, y1, xm).nr);
-    c = max(c, make_ray(a.cam, y1, x1).nr);
+    const int c = supertile_cost(a, t);
     a.tile_cost[t] = c;
     atomicAdd(&h[cost_rank(c)], 1u);
   }
@@ -1202,6 +1236,33 @@ __global__ __launch_bounds__(256) void plan_scatter_kernel(const int* cost, int 
     if (cnt[i] != 0u) off[i] = atomicAdd(&base[i], cnt[i]);
   __syncthreads();
   if (t < n) order[off[r] + local] = t;
+}
+
+// Batch class: clear the bucket counters and every request's sample
+// counter (one workgroup).
+__global__ __launch_bounds__(256) void batch_zero_kernel(BatchDev b) {
+  for (int i = threadIdx.x; i < kBuckets; i += 256) b.tile_hist[i] = 0u;
+  for (int r = threadIdx.x; r < b.nreq; r += 256)
+    if (b.args[r].samples != nullptr) *b.args[r].samples = 0ull;
+}
+
+// Batch class: work estimate of every super-tile of every request, and the
+// bucket histogram.
+__global__ __launch_bounds__(256) void batch_cost_kernel(BatchDev b) {
+  __shared__ unsigned h[kBuckets];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kBuckets; i += 256) h[i] = 0u;
+  __syncthreads();
+  const int t = blockIdx.x * 256 + tid;
+  if (t < b.ntiles) {
+    const int r = batch_request(b.tile_base, b.nreq, t);
+    const int c = supertile_cost(b.args[r], t - b.tile_base[r]);
+    b.tile_cost[t] = c;
+    atomicAdd(&h[cost_rank(c)], 1u);
+  }
+  __syncthreads();
+  for (int i = tid; i < kBuckets; i += 256)
+    if (h[i] != 0u) atomicAdd(&b.tile_hist[i], h[i]);
 }
 
 template <int P, int STORE, bool GRAD>
@@ -1255,7 +1316,7 @@ template <int P, int STORE, bool SHADE>
 hipError_t launch_render_ps(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
   if (a.lds_bytes > 0) {
     // EQ: every axis has the kernel's degree P (degree known at compile time)
-    const bool eq = a.m.ax[0].p == P && a.m.ax[1].p == P && a.m.ax[2].p == P;
+    const bool eq = a.eq != 0;
     if constexpr (P >= 2) {
       if (a.fast)
         return eq ? launch_brick<P, STORE, SHADE, true, true>(a, st, ev)
@@ -1270,6 +1331,44 @@ hipError_t launch_render_ps(const RenderArgsDev& a, hipStream_t st, const Kernel
   render_global_kernel<P, STORE, SHADE><<<grid, 256, 0, st>>>(a);
   e = hipGetLastError();
   return e == hipSuccess ? mark(ev.end, st) : e;
+}
+
+template <int P, int STORE, bool SHADE, bool FAST, bool EQ>
+hipError_t launch_batch_class(const BatchDev& b, int lds_bytes, hipStream_t st) {
+  const unsigned blocks = (unsigned)((b.ntiles + 255) / 256);
+  batch_zero_kernel<<<1, 256, 0, st>>>(b);
+  batch_cost_kernel<<<blocks, 256, 0, st>>>(b);
+  plan_scan_kernel<<<1, kBuckets, 0, st>>>(b.tile_hist);
+  plan_scatter_kernel<<<blocks, 256, 0, st>>>(b.tile_cost, b.ntiles, b.tile_hist, b.tile_order);
+  render_batch_kernel<P, STORE, SHADE, FAST, EQ, kLanesPerRay><<<b.ntiles, 256, lds_bytes, st>>>(b);
+  return hipGetLastError();
+}
+
+template <int P, int STORE, bool SHADE>
+hipError_t batch_ps(const BatchDev& b, const BatchKey& k, hipStream_t st) {
+  if constexpr (P >= 2) {
+    if (k.fast)
+      return k.eq ? launch_batch_class<P, STORE, SHADE, true, true>(b, k.lds_bytes, st)
+                  : launch_batch_class<P, STORE, SHADE, true, false>(b, k.lds_bytes, st);
+  }
+  return k.eq ? launch_batch_class<P, STORE, SHADE, false, true>(b, k.lds_bytes, st)
+              : launch_batch_class<P, STORE, SHADE, false, false>(b, k.lds_bytes, st);
+}
+
+template <int P, int STORE>
+hipError_t batch_p(const BatchDev& b, const BatchKey& k, hipStream_t st) {
+  return k.shading ? batch_ps<P, STORE, true>(b, k, st) : batch_ps<P, STORE, false>(b, k, st);
+}
+
+template <int STORE>
+hipError_t batch_store(const BatchDev& b, const BatchKey& k, hipStream_t st) {
+  switch (k.pmax) {
+    case 1: return batch_p<1, STORE>(b, k, st);
+    case 2: return batch_p<2, STORE>(b, k, st);
+    case 3: return batch_p<3, STORE>(b, k, st);
+    case 4: return batch_p<4, STORE>(b, k, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int P, int STORE>
@@ -1319,6 +1418,11 @@ hipError_t launch_render(const RenderArgsDev& a, hipStream_t st, const KernelEve
     if (e != hipSuccess) return e;
   }
   return a.m.store == 0 ? dispatch_render<0>(a, st, ev) : dispatch_render<1>(a, st, ev);
+}
+
+hipError_t launch_render_batch(const BatchDev& b, const BatchKey& k, hipStream_t st) {
+  if (b.ntiles <= 0) return hipSuccess;
+  return k.store == 0 ? batch_store<0>(b, k, st) : batch_store<1>(b, k, st);
 }
 
 hipError_t launch_eval(const EvalArgsDev& a, hipStream_t st) {

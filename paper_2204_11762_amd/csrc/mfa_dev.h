@@ -17,6 +17,17 @@ constexpr int kLanesPerRay = 4;
 constexpr int kTileW = kLanesPerRay == 4 ? 4 : 8;
 constexpr int kTileH = 64 / kLanesPerRay / kTileW;
 
+// Waves per SIMD that the brick ray caster of kernel degree P is compiled
+// for (four workgroups of four waves per CU, or three for the variants
+// whose registers would otherwise spill), and the LDS one workgroup may use
+// at that occupancy (160 KB per CU).
+__host__ __device__ constexpr int brick_waves_per_simd(int P, bool fast, bool eq) {
+  return (P >= 4 || (P == 3 && !fast && !eq)) ? 3 : 4;
+}
+__host__ __device__ constexpr int brick_lds_per_group(int waves) {
+  return waves == 3 ? 52 * 1024 : 40 * 1024;
+}
+
 // Per-span FP32 table of one axis of degree p, for span s (stored at row
 // s - p).  With delta = u - U_s (rounded to FP32 once):
 //   left[1] = delta,  left[j] = delta + dl[j]   with dl[j] = U_s - U_{s+1-j}, j = 2..p
@@ -85,6 +96,7 @@ struct RenderArgsDev {
   float ka, kd, ks;
   float light[3];       // unit vector towards the light
   int32_t fast;         // 1: uniform knots and every degree >= 2 (local-coordinate stepping)
+  int32_t eq;           // 1: every axis has degree pmax (degree fixed at compile time)
   float* out;           // width*height*4
   unsigned long long* samples;  // nullable
   // LDS-brick ray marcher (render_brick_kernel); unused by the fallback
@@ -111,6 +123,28 @@ struct EvalArgsDev {
   int64_t n;
 };
 
+// The requests of a render batch that share one kernel variant (a class):
+// their records in device memory and the class's planning scratch.
+struct BatchDev {
+  const RenderArgsDev* args;  // nreq request records
+  const int32_t* tile_base;   // nreq + 1 prefix sums of the requests' super-tiles
+  int32_t nreq;
+  int32_t ntiles;             // super-tiles of all requests of the class
+  int32_t* tile_cost;         // ntiles work estimates (scratch)
+  int32_t* tile_order;        // ntiles class-wide super-tile indices, longest first
+  unsigned* tile_hist;        // 1024 bucket counters (scratch)
+};
+
+// Kernel variant of a batch class and the dynamic LDS of its launch.
+struct BatchKey {
+  int32_t pmax;
+  int32_t store;
+  int32_t shading;
+  int32_t fast;
+  int32_t eq;
+  int32_t lds_bytes;
+};
+
 // Optional events recorded on the render stream immediately before and after
 // the ray-casting kernel (null: not recorded).
 struct KernelEvents {
@@ -120,6 +154,7 @@ struct KernelEvents {
 
 // Kernel launchers (kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_render(const RenderArgsDev& a, hipStream_t stream, const KernelEvents& ev);
+hipError_t launch_render_batch(const BatchDev& b, const BatchKey& k, hipStream_t stream);
 hipError_t launch_eval(const EvalArgsDev& a, hipStream_t stream);
 
 }  // namespace mfa

@@ -278,6 +278,93 @@ def random_model(rng: np.random.Generator, n=(9, 7, 8), degree=(3, 2, 1),
                      tuple(map(float, hi)))
 
 
+def fit_field_on_knots(knots, degree, grid_factor: int = 2) -> np.ndarray:
+    """Separable least-squares fit of the test field on the given knot
+    vectors (one per axis, any clamped knots), sampled at ``grid_factor * n``
+    equally spaced sites per axis.  Returns control points (n_z, n_y, n_x)."""
+    fits = []
+    for k in range(3):
+        U = np.asarray(knots[k], dtype=np.float64)
+        n = len(U) - degree[k] - 1
+        xs = np.linspace(0.0, 1.0, grid_factor * n)
+        g = np.exp(-40.0 * (xs - 0.5) ** 2)
+        trig = (np.sin(6.0 * xs), np.cos(5.0 * xs), np.sin(7.0 * xs))[k]
+        fits.append((_pinv_apply(U, degree[k], xs, trig), _pinv_apply(U, degree[k], xs, g)))
+    (ax, gx), (by, gy), (cz, gz) = fits
+    return (cz[:, None, None] * by[None, :, None] * ax[None, None, :]
+            + 0.3 * gz[:, None, None] * gy[None, :, None] * gx[None, None, :])
+
+
+@dataclass
+class BatchRequest:
+    model: int                         # index into the batch's model list
+    camera: CameraSpec
+    tf: TFSpec
+    params: ParamSpec
+
+
+def batch_mix_small(seed: int = 11):
+    """Small mixed batch for parity tests: four models (uniform and Beta
+    knots, degrees 1-4, mixed per axis, non-unit box, FP32 and BF16) and
+    eight requests (ragged image sizes, perspective and orthographic,
+    shading off, no early termination, one 2048-entry table).
+    Returns ([(ModelSpec, store)], [BatchRequest])."""
+    rng = np.random.default_rng(seed)
+    models = [
+        (random_model(rng, n=(9, 8, 7), degree=(3, 3, 3)), 0),
+        (random_model(rng, n=(10, 9, 11), degree=(2, 3, 1), beta_knots=True,
+                      lo=(-1.0, 0.0, 0.0), hi=(1.0, 1.0, 2.0)), 1),
+        (random_model(rng, n=(8, 8, 8), degree=(4, 4, 4), beta_knots=True), 1),
+        (random_model(rng, n=(12, 10, 9), degree=(2, 2, 2)), 0),
+    ]
+    sizes = [(37, 29), (40, 33), (23, 41), (64, 48), (31, 31), (48, 17), (56, 40), (33, 52)]
+    reqs = []
+    for i, (W, H) in enumerate(sizes):
+        mi = i % len(models)
+        spec = models[mi][0]
+        lo, hi = np.asarray(spec.lo), np.asarray(spec.hi)
+        ctr = tuple((lo + hi) / 2)
+        ext = float(np.max(hi - lo))
+        if i == 4:
+            cam = CameraSpec("ortho", (ctr[0] + 0.3, ctr[1] + 0.2, ctr[2] + 3 * ext), ctr,
+                             (0.0, 1.0, 0.0), W, H, ortho_half_w=0.6 * ext,
+                             ortho_half_h=0.7 * ext)
+        else:
+            cam = orbit_camera(W, H, float(rng.uniform(0, 360)), float(rng.uniform(-50, 50)),
+                               radius=2.2 * ext, target=ctr)
+        P = np.asarray(spec.ctrl)
+        tf = pwl_tf(seed + i, P.min(), P.max(), alpha_max=0.15, n=2048 if i == 6 else 256)
+        prm = ParamSpec(step=ext / 97.0, ert_alpha=1.5 if i == 5 else 0.99,
+                        shading=(i != 2), headlight=(i % 3 != 1), light_dir=(0.3, -0.5, 0.8))
+        reqs.append(BatchRequest(mi, cam, tf, prm))
+    return models, reqs
+
+
+def batch_config(seed: int = 21, n_requests: int = 64):
+    """The batching workload: four resident BF16 models with Beta(2,5)
+    knot spacings, degrees 2/3/4/3, control grids 32^3, 96x128x80, 128^3
+    and 200x200x100 (least-squares fits of the test field); n_requests
+    requests over them with image sizes drawn from {256^2, 512^2, 768x432,
+    1024^2}, step 1/512, random orbit cameras and per-model 8-node tables.
+    Returns ([(ModelSpec, store)], [BatchRequest])."""
+    rng = np.random.default_rng(seed)
+    shapes = [((32, 32, 32), 2), ((96, 128, 80), 3), ((128, 128, 128), 4), ((200, 200, 100), 3)]
+    models, tfs = [], []
+    for (n, p) in shapes:
+        knots = tuple(clamped_beta_knots(n[k], p, rng) for k in range(3))
+        ctrl = fit_field_on_knots(knots, (p, p, p))
+        models.append((ModelSpec((p, p, p), knots, ctrl), 1))
+        tfs.append(pwl_tf(int(rng.integers(1 << 30)), float(ctrl.min()), float(ctrl.max())))
+    sizes = [(256, 256), (512, 512), (768, 432), (1024, 1024)]
+    reqs = []
+    for _ in range(n_requests):
+        mi = int(rng.integers(len(models)))
+        W, H = sizes[int(rng.integers(len(sizes)))]
+        reqs.append(BatchRequest(mi, random_orbit_camera(rng, W, H), tfs[mi],
+                                 ParamSpec(step=1.0 / 512)))
+    return models, reqs
+
+
 def pixel_subset(width: int, height: int, size: int, seed: int) -> np.ndarray:
     return np.sort(np.random.default_rng(seed).choice(width * height, size=size,
                                                       replace=False))

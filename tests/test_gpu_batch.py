@@ -1,0 +1,157 @@
+"""Render batches through the C ABI: every request of a batch gives the
+image and sample count of the same request rendered alone (bit for bit),
+matches the FP64 oracle, and a captured HIP graph of the batch replays to
+the same result."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from gpu_helpers import FP32_RMSE, compare_image, gpu_render
+from helpers import oracle_model
+from oracle import quant
+from paper_2204_11762_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TAU32 = 2e-5
+PX32 = 2e-4
+
+
+def _setup(b, ctx, models, reqs):
+    import torch
+    handles = [b.mfa_model_upload(ctx, spec, store) for spec, store in models]
+    outs, cnts, batch_reqs = [], [], []
+    for r in reqs:
+        out = torch.full((r.camera.height, r.camera.width, 4), -1.0, dtype=torch.float32,
+                         device="cuda")
+        cnt = torch.full((1,), -7, dtype=torch.int64, device="cuda")
+        outs.append(out)
+        cnts.append(cnt)
+        batch_reqs.append((handles[r.model], r.camera, r.tf, r.params, out, cnt))
+    return handles, outs, cnts, batch_reqs
+
+
+def _workload(models, r):
+    return wl.Workload("batch", models[r.model][0], r.camera, r.tf, r.params)
+
+
+def test_batch_equals_single_renders_and_oracle(mfa):
+    import torch
+    b, ctx = mfa
+    models, reqs = wl.batch_mix_small()
+    handles, outs, cnts, breqs = _setup(b, ctx, models, reqs)
+    batch = None
+    try:
+        batch = b.mfa_batch_create(ctx, breqs)
+        b.mfa_batch_render(ctx, batch)
+        torch.cuda.synchronize()
+        for i, r in enumerate(reqs):
+            wk = _workload(models, r)
+            img, cnt = gpu_render(b, ctx, handles[r.model], wk)
+            got = outs[i].cpu().numpy().astype(np.float64)
+            assert np.array_equal(got, img), f"request {i}: batch image differs from mfa_render"
+            assert int(cnts[i].item()) == cnt
+            spec, store = models[r.model]
+            M = None if store == 0 else oracle_model(spec, ctrl=quant.dequant_bf16(spec.ctrl))
+            W, H = r.camera.width, r.camera.height
+            rep = compare_image(got, cnt, wk, np.arange(W * H), TAU32, PX32, model=M)
+            print(f"\n  request {i} ({W}x{H}, model {r.model}, store {store}): rmse {rep.rmse:.2e} "
+                  f"ambiguous {rep.n_ambiguous} samples {rep.samples_gpu}/{rep.samples_ref}")
+            assert rep.rmse <= FP32_RMSE and rep.n_bad == 0
+            assert abs(rep.samples_gpu - rep.samples_ref) <= rep.samples_slack
+        # a second render of the same batch gives the same result
+        first = [o.clone() for o in outs]
+        for o in outs:
+            o.fill_(-1.0)
+        b.mfa_batch_render(ctx, batch)
+        torch.cuda.synchronize()
+        for o, f in zip(outs, first):
+            assert torch.equal(o, f)
+    finally:
+        if batch is not None:
+            b.mfa_batch_free(ctx, batch)
+        for h in handles:
+            b.mfa_model_free(ctx, h)
+
+
+def test_batch_graph_replay(mfa):
+    """Capture mfa_batch_render in a HIP graph; replay it several times with
+    eager work and synchronisation in between; every replay equals the eager
+    result."""
+    import torch
+    b, ctx = mfa
+    models, reqs = wl.batch_mix_small(seed=12)
+    handles, outs, cnts, breqs = _setup(b, ctx, models, reqs)
+    batch = None
+    try:
+        batch = b.mfa_batch_create(ctx, breqs)
+        b.mfa_batch_render(ctx, batch)
+        torch.cuda.synchronize()
+        ref = [o.clone() for o in outs]
+        ref_cnt = [c.clone() for c in cnts]
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            b.mfa_batch_render(ctx, batch)
+        other_wk = _workload(models, reqs[0])
+        for rep in range(3):
+            for o in outs:
+                o.fill_(-1.0)
+            for c in cnts:
+                c.fill_(-7)
+            torch.cuda.synchronize()
+            g.replay()
+            # eager work between replays: a single-frame render and a reduction
+            gpu_render(b, ctx, handles[reqs[0].model], other_wk)
+            _ = torch.stack([o.sum() for o in outs]).sum().item()
+            torch.cuda.synchronize()
+            for i in range(len(outs)):
+                assert torch.equal(outs[i], ref[i]), f"replay {rep}, request {i}"
+                assert torch.equal(cnts[i], ref_cnt[i]), f"replay {rep}, request {i} count"
+        del g
+    finally:
+        if batch is not None:
+            b.mfa_batch_free(ctx, batch)
+        for h in handles:
+            b.mfa_model_free(ctx, h)
+
+
+def test_batch_errors(mfa):
+    import torch
+    b, ctx = mfa
+    models, reqs = wl.batch_mix_small(seed=13)
+    handles, outs, cnts, breqs = _setup(b, ctx, models, reqs[:3])
+    try:
+        # overlapping outputs
+        bad = list(breqs)
+        bad[1] = (bad[1][0], bad[1][1], bad[1][2], bad[1][3], bad[1][4], bad[0][5])
+        with pytest.raises(b.MFAError) as ei:
+            b.mfa_batch_create(ctx, bad)
+        assert ei.value.status == b.MFA_ERR_INVALID
+        # an invalid request is named
+        import copy
+        p = copy.copy(reqs[2].params)
+        p.step = -1.0
+        bad = list(breqs)
+        bad[2] = (bad[2][0], bad[2][1], bad[2][2], p, bad[2][4], bad[2][5])
+        with pytest.raises(b.MFAError) as ei:
+            b.mfa_batch_create(ctx, bad)
+        assert ei.value.status == b.MFA_ERR_INVALID and "request 2" in ei.value.message
+        with pytest.raises(b.MFAError) as ei:
+            b.mfa_batch_create(ctx, [])
+        assert ei.value.status == b.MFA_ERR_INVALID
+        # a model used by a live batch cannot be freed
+        batch = b.mfa_batch_create(ctx, breqs)
+        with pytest.raises(b.MFAError) as ei:
+            b.mfa_model_free(ctx, handles[reqs[0].model])
+        assert ei.value.status == b.MFA_ERR_INVALID
+        b.mfa_batch_render(ctx, batch)
+        torch.cuda.synchronize()
+        b.mfa_batch_free(ctx, batch)
+        with pytest.raises(b.MFAError) as ei:
+            b.mfa_batch_render(ctx, batch)
+        assert ei.value.status == b.MFA_ERR_HANDLE
+    finally:
+        for h in handles:
+            b.mfa_model_free(ctx, h)
