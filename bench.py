@@ -199,6 +199,86 @@ def gpu_leg(b, ctx, wk, store: int, steps: int, warmup: int, log, nominal_frames
         b.mfa_model_free(ctx, h)
 
 
+def batch_leg(b, ctx, steps: int, warmup: int, log):
+    """The batching workload (64 requests over four resident BF16 models with
+    Beta(2,5) knots, degrees 2/3/4/3, mixed image sizes): the same requests
+    rendered one by one with mfa_render, as one batch, and as a replayed HIP
+    graph of the batch."""
+    import torch
+    models, reqs = wl.batch_config()
+    p_of = [int(max(spec.degree)) for spec, _ in models]
+    handles = [b.mfa_model_upload(ctx, spec, store) for spec, store in models]
+    batch = None
+    try:
+        outs = [torch.zeros((r.camera.height, r.camera.width, 4), dtype=torch.float32,
+                            device="cuda") for r in reqs]
+        cnts = [torch.zeros((1,), dtype=torch.int64, device="cuda") for _ in reqs]
+        breqs = [(handles[r.model], r.camera, r.tf, r.params, o, c)
+                 for r, o, c in zip(reqs, outs, cnts)]
+        batch = b.mfa_batch_create(ctx, breqs)
+        b.mfa_batch_render(ctx, batch)
+        torch.cuda.synchronize()
+        per_req = [int(c.item()) for c in cnts]
+        samples = sum(per_req)
+        flops = sum(n * flops_per_sample(p_of[r.model]) for n, r in zip(per_req, reqs))
+        stream = torch.cuda.current_stream()
+
+        def timed(fn, n):
+            e0 = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+            e1 = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(n):
+                e0[i].record(stream)
+                fn()
+                e1[i].record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            return wall / n * 1e3, np.array([a.elapsed_time(z) for a, z in zip(e0, e1)])
+
+        def one_by_one():
+            for r, o, c in zip(reqs, outs, cnts):
+                b.mfa_render(ctx, handles[r.model], r.camera, r.tf, r.params, o, c, stream=stream)
+
+        def batched():
+            b.mfa_batch_render(ctx, batch, stream=stream)
+
+        for _ in range(warmup):
+            one_by_one()
+            batched()
+        seq_ms, seq_lat = timed(one_by_one, steps)
+        bat_ms, bat_lat = timed(batched, steps)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            b.mfa_batch_render(ctx, batch)
+        for _ in range(warmup):
+            g.replay()
+        gr_ms, gr_lat = timed(g.replay, steps)
+        del g
+        log(f"batch: {len(reqs)} requests, {samples} samples; one by one {seq_ms:.3f} ms, "
+            f"batch {bat_ms:.3f} ms, graph {gr_ms:.3f} ms")
+        return {"workload": "64 requests, 4 BF16 models (Beta(2,5) knots; p 2/3/4/3; 32^3, "
+                            "96x128x80, 128^3, 200x200x100), images {256^2, 512^2, 768x432, "
+                            "1024^2}, step 1/512, random orbit cameras",
+                "requests": len(reqs), "samples_per_batch": samples,
+                "flops_per_batch": flops,
+                "one_by_one": {"ms": seq_ms, "samples_per_s": samples / (seq_ms * 1e-3),
+                               "p50_ms": float(np.percentile(seq_lat, 50)),
+                               "p99_ms": float(np.percentile(seq_lat, 99))},
+                "batch": {"ms": bat_ms, "samples_per_s": samples / (bat_ms * 1e-3),
+                          "p50_ms": float(np.percentile(bat_lat, 50)),
+                          "p99_ms": float(np.percentile(bat_lat, 99))},
+                "graph": {"ms": gr_ms, "samples_per_s": samples / (gr_ms * 1e-3),
+                          "p50_ms": float(np.percentile(gr_lat, 50)),
+                          "p99_ms": float(np.percentile(gr_lat, 99)),
+                          "tflops": flops / (gr_ms * 1e-3) / 1e12}}
+    finally:
+        if batch is not None:
+            b.mfa_batch_free(ctx, batch)
+        for h in handles:
+            b.mfa_model_free(ctx, h)
+
+
 def rmse_on(image, base):
     if base is None:
         return None
@@ -227,6 +307,8 @@ def main():
                     help="first run one device-to-device copy of MIB MiB (a plain copy "
                          "kernel of known traffic, for scaling HBM counters)")
     ap.add_argument("--legs", default="fp32,bf16", help="storages to measure")
+    ap.add_argument("--batch-steps", type=int, default=20,
+                    help="timed repetitions of the batching workload (0 = skip it)")
     args = ap.parse_args()
 
     def log(msg):
@@ -271,6 +353,9 @@ def main():
             if name in args.legs.split(","):
                 legs[name] = gpu_leg(b, ctx, wk, store, args.steps, args.warmup, log,
                                      nominal_frames=not args.no_nominal)
+        batch = None
+        if args.batch_steps > 0:
+            batch = batch_leg(b, ctx, args.batch_steps, 2, log)
     finally:
         b.mfa_destroy(ctx)
     if args.store not in legs:
@@ -326,6 +411,8 @@ def main():
                      "flops_per_launch": flops},
         "legs": {k: summary(v, k) for k, v in legs.items()},
     }
+    if batch is not None:
+        line["batch"] = batch
     if base is not None:
         line["cpu_baseline"] = {"value": base["samples"] / base["wall"], "unit": "samples/s",
                                 "cores": cores, "kind": "oracle",
