@@ -41,7 +41,8 @@ typedef int32_t mfa_status;
 #define MFA_ERR_MODEL (-2)   /* malformed model descriptor */
 #define MFA_ERR_NOMEM (-3)   /* device memory or the context budget exhausted */
 #define MFA_ERR_DEVICE (-4)  /* HIP runtime error (including an earlier fault) */
-#define MFA_ERR_HANDLE (-5)  /* unknown context or model handle */
+#define MFA_ERR_HANDLE (-5)  /* unknown context, model, batch or ticket handle */
+#define MFA_ERR_TIMEOUT (-6) /* mfa_server_wait: the request has not finished yet */
 
 /* Storage precision of the control points on the device.  Basis functions
  * and all accumulation are FP32 in either case. */
@@ -214,6 +215,66 @@ mfa_status mfa_batch_render(mfa_ctx* ctx, int64_t batch, void* stream);
 /* Synchronise the device and release a batch.  Errors: MFA_ERR_HANDLE,
  * MFA_ERR_DEVICE. */
 mfa_status mfa_batch_free(mfa_ctx* ctx, int64_t batch);
+
+/* ----------------------------------------------------------------------
+ * Serving: a render server with continuous batching.
+ *
+ * A worker thread owned by the server takes submitted requests in arrival
+ * order and launches them as batches (as mfa_batch_render does) on up to
+ * `streams` concurrent slots.  Whenever a slot is free, every queued
+ * request that fits is admitted into one batch: at most `max_batch`
+ * requests, and, when max_bytes > 0, only while the device bytes of the
+ * requests in flight (their images and their share of the batch records
+ * and planning space) stay within max_bytes.  Requests that arrive while
+ * others run therefore start as soon as a slot frees up, and their work
+ * overlaps the tail of the running batches on the device.  Every image
+ * equals the image of mfa_render for the same request bit for bit.
+ *
+ * While a server exists its context must be used through the server only
+ * (upload models before creating it; free them after destroying it).
+ * mfa_server_submit and mfa_server_wait may be called from any host
+ * thread.  A request's output buffers must stay valid and untouched until
+ * its ticket has been waited for.
+ * ---------------------------------------------------------------------- */
+typedef struct mfa_server_config {
+  int32_t streams;   /* concurrent batches, 1..8 (0 = 2) */
+  int32_t max_batch; /* requests per batch, 1..65536 (0 = 256) */
+  int64_t max_bytes; /* device-byte budget of requests in flight (0 = none) */
+} mfa_server_config;
+
+typedef struct mfa_request_info {
+  int32_t status;     /* MFA_OK, or the error of a failed request */
+  int32_t batch_size; /* requests in the batch that rendered it */
+  int64_t submit_ns;  /* host steady-clock times: submission, */
+  int64_t launch_ns;  /* admission into a launched batch, */
+  int64_t done_ns;    /* completion seen by the worker */
+} mfa_request_info;
+
+typedef struct mfa_server mfa_server;
+
+/* Start a server on a context (cfg may be null for the defaults).
+ * Errors: MFA_ERR_HANDLE, MFA_ERR_INVALID (config out of range),
+ * MFA_ERR_DEVICE. */
+mfa_status mfa_server_create(mfa_ctx* ctx, const mfa_server_config* cfg, mfa_server** server_out);
+
+/* Queue one request (checked as mfa_render checks it; everything it points
+ * to is copied) and return its ticket (> 0).  Errors: MFA_ERR_HANDLE,
+ * MFA_ERR_INVALID (any request mfa_render would reject, or the server is
+ * shutting down), MFA_ERR_NOMEM (the request alone exceeds max_bytes). */
+mfa_status mfa_server_submit(mfa_server* server, const mfa_render_request* req,
+                             int64_t* ticket_out);
+
+/* Wait up to timeout_us microseconds (< 0: without limit) for a request to
+ * finish; on completion fill *info (nullable), forget the ticket and
+ * return the request's status.  Errors: MFA_ERR_TIMEOUT (not finished; the
+ * ticket stays valid), MFA_ERR_HANDLE (unknown or already waited-for
+ * ticket), MFA_ERR_DEVICE (the request failed on the device). */
+mfa_status mfa_server_wait(mfa_server* server, int64_t ticket, int64_t timeout_us,
+                           mfa_request_info* info);
+
+/* Finish every queued and running request, stop the worker and release the
+ * server.  Null is accepted and ignored. */
+mfa_status mfa_server_destroy(mfa_server* server);
 
 /* Kernel timing for measurement.  While enabled, every mfa_render call
  * records a pair of HIP events on its stream immediately around the

@@ -24,8 +24,9 @@ MFA_ERR_MODEL = -2
 MFA_ERR_NOMEM = -3
 MFA_ERR_DEVICE = -4
 MFA_ERR_HANDLE = -5
+MFA_ERR_TIMEOUT = -6
 STATUS_NAMES = {0: "MFA_OK", -1: "MFA_ERR_INVALID", -2: "MFA_ERR_MODEL", -3: "MFA_ERR_NOMEM",
-                -4: "MFA_ERR_DEVICE", -5: "MFA_ERR_HANDLE"}
+                -4: "MFA_ERR_DEVICE", -5: "MFA_ERR_HANDLE", -6: "MFA_ERR_TIMEOUT"}
 MFA_STORE_F32 = 0
 MFA_STORE_BF16 = 1
 MFA_CAMERA_ORTHO = 0
@@ -34,7 +35,8 @@ MFA_CAMERA_PERSP = 1
 EXPORTED = ("mfa_create", "mfa_destroy", "mfa_set_memory_budget", "mfa_model_upload",
             "mfa_model_free", "mfa_model_bytes", "mfa_render", "mfa_eval_points",
             "mfa_kernel_timing", "mfa_kernel_times", "mfa_batch_create", "mfa_batch_render",
-            "mfa_batch_free", "mfa_validate_model",
+            "mfa_batch_free", "mfa_server_create", "mfa_server_submit", "mfa_server_wait",
+            "mfa_server_destroy", "mfa_validate_model",
             "mfa_validate_render", "mfa_last_error", "mfa_version")
 
 
@@ -76,6 +78,15 @@ class RenderRequest(C.Structure):
                 ("samples_dev", C.c_void_p)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("streams", C.c_int32), ("max_batch", C.c_int32), ("max_bytes", C.c_int64)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("batch_size", C.c_int32), ("submit_ns", C.c_int64),
+                ("launch_ns", C.c_int64), ("done_ns", C.c_int64)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
@@ -98,6 +109,10 @@ def _load():
         "mfa_batch_create": (st, [vp, C.POINTER(RenderRequest), C.c_int32, C.POINTER(i64)]),
         "mfa_batch_render": (st, [vp, i64, vp]),
         "mfa_batch_free": (st, [vp, i64]),
+        "mfa_server_create": (st, [vp, C.POINTER(ServerConfig), C.POINTER(vp)]),
+        "mfa_server_submit": (st, [vp, C.POINTER(RenderRequest), C.POINTER(i64)]),
+        "mfa_server_wait": (st, [vp, i64, i64, C.POINTER(RequestInfo)]),
+        "mfa_server_destroy": (st, [vp]),
         "mfa_kernel_times": (st, [vp, vp, i64, C.POINTER(i64)]),
         "mfa_validate_model": (st, [C.POINTER(ModelDesc)]),
         "mfa_validate_render": (st, [C.POINTER(Camera), C.POINTER(TF), C.POINTER(RenderParams)]),
@@ -311,6 +326,52 @@ def mfa_batch_render(ctx: int, batch: int, stream=None) -> None:
 
 def mfa_batch_free(ctx: int, batch: int) -> None:
     _check(lib.mfa_batch_free(ctx, int(batch)))
+
+
+def _request_struct(model, cam, tf, params, rgba, samples, keep):
+    import torch
+    c = camera_struct(cam)
+    t, k = tf_struct(tf)
+    p = params_struct(params)
+    keep += [c, t, k, p]
+    r = RenderRequest()
+    r.model = int(model)
+    r.camera = C.pointer(c)
+    r.tf = C.pointer(t)
+    r.params = C.pointer(p)
+    r.rgba_dev = _dev_tensor(rgba, torch.float32, (cam.height, cam.width, 4), "rgba")
+    r.samples_dev = None if samples is None else _dev_tensor(samples, torch.int64, (1,), "samples")
+    return r
+
+
+def mfa_server_create(ctx: int, streams: int = 0, max_batch: int = 0, max_bytes: int = 0) -> int:
+    cfg = ServerConfig(int(streams), int(max_batch), int(max_bytes))
+    h = C.c_void_p()
+    _check(lib.mfa_server_create(ctx, C.byref(cfg), C.byref(h)))
+    return h.value
+
+
+def mfa_server_submit(server: int, model, camera, tf, params, rgba, samples=None) -> int:
+    """Queue one request; the tensors must stay alive until it is waited for."""
+    keep = []
+    r = _request_struct(model, camera, tf, params, rgba, samples, keep)
+    t = C.c_int64()
+    _check(lib.mfa_server_submit(server, C.byref(r), C.byref(t)))
+    return t.value
+
+
+def mfa_server_wait(server: int, ticket: int, timeout_us: int = -1):
+    """Wait for a request; returns its RequestInfo, or None on time-out."""
+    info = RequestInfo()
+    st = lib.mfa_server_wait(server, int(ticket), int(timeout_us), C.byref(info))
+    if st == MFA_ERR_TIMEOUT:
+        return None
+    _check(st)
+    return info
+
+
+def mfa_server_destroy(server: int) -> None:
+    _check(lib.mfa_server_destroy(server))
 
 
 def mfa_kernel_timing(ctx: int, enable: bool) -> None:

@@ -7,9 +7,14 @@
 
 #include <algorithm>
 #include <cfloat>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -736,6 +741,143 @@ void build_render_args(const DeviceModel& dm, const mfa_camera* cam, const mfa_t
                        int64_t((cam->height + 2 * mfa::kTileH - 1) / (2 * mfa::kTileH)));
 }
 
+// Enqueue a prepared batch on a stream: per kernel class the planning
+// passes and one ray-casting launch; requests on the global-memory kernel
+// one by one.
+hipError_t launch_batch(const RenderBatch& b, hipStream_t st) {
+  for (const auto& c : b.classes) {
+    const hipError_t e = mfa::launch_render_batch(c.second, c.first, st);
+    if (e != hipSuccess) return e;
+  }
+  for (const auto& a : b.single) {
+    const hipError_t e = mfa::launch_render(a, st, mfa::KernelEvents{});
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Two-phase construction of a render batch: prepare() checks the requests
+// and lays out one device block (transfer-function tables, then per kernel
+// class the request records, tile prefix sums and planning scratch);
+// materialize() writes the block's host image for a given device address
+// and the launch description.  The requests' host structures are read by
+// prepare() only.
+class BatchBuilder {
+ public:
+  mfa_status prepare(const DeviceModel* const* dms, const mfa_render_request* reqs, int32_t n) {
+    std::vector<std::pair<uintptr_t, uintptr_t>> ranges;
+    for (int32_t i = 0; i < n; ++i) {
+      const mfa_render_request& r = reqs[i];
+      const mfa_status st = check_request(*dms[i], r.camera, r.tf, r.params, r.rgba_dev);
+      if (st != MFA_OK) return fail(st, "request " + std::to_string(i) + ": " + g_last_error);
+      const uintptr_t o = reinterpret_cast<uintptr_t>(r.rgba_dev);
+      ranges.emplace_back(o, o + size_t(r.camera->width) * size_t(r.camera->height) * 16);
+      if (r.samples_dev != nullptr) {
+        const uintptr_t c = reinterpret_cast<uintptr_t>(r.samples_dev);
+        ranges.emplace_back(c, c + sizeof(int64_t));
+      }
+    }
+    std::sort(ranges.begin(), ranges.end());
+    for (size_t i = 1; i < ranges.size(); ++i)
+      if (ranges[i].first < ranges[i - 1].second)
+        return fail(MFA_ERR_INVALID, "output buffers of a batch overlap");
+    args_.resize(n);
+    tf_off_.resize(n);
+    tables_.resize(n);
+    size_t off = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      const mfa_render_request& r = reqs[i];
+      build_render_args(*dms[i], r.camera, r.tf, r.params, r.rgba_dev, r.samples_dev, nullptr,
+                        args_[i]);
+      tables_[i].assign(r.tf->rgba, r.tf->rgba + size_t(r.tf->n) * 4);
+      tf_off_[i] = off;
+      off = align256(off + size_t(r.tf->n) * 16);
+    }
+    for (int32_t i = 0; i < n; ++i) {
+      const mfa::RenderArgsDev& a = args_[i];
+      if (a.ntiles == 0) {
+        single_.push_back(i);
+        continue;
+      }
+      const mfa::BatchKey k{a.m.pmax, a.m.store, a.shading, a.fast, a.eq, 0};
+      Group* gp = nullptr;
+      for (auto& g : groups_)
+        if (g.key.pmax == k.pmax && g.key.store == k.store && g.key.shading == k.shading &&
+            g.key.fast == k.fast && g.key.eq == k.eq)
+          gp = &g;
+      if (gp == nullptr) {
+        groups_.push_back(Group{k, {}, 0, 0, 0, 0, 0, 0});
+        gp = &groups_.back();
+      }
+      gp->reqs.push_back(i);
+      gp->key.lds_bytes = std::max(gp->key.lds_bytes, a.lds_bytes);
+      gp->ntiles += a.ntiles;
+    }
+    for (auto& g : groups_) {
+      if (g.ntiles > int64_t(INT32_MAX)) return fail(MFA_ERR_INVALID, "batch has too many tiles");
+      g.off_args = off;
+      off = align256(off + sizeof(mfa::RenderArgsDev) * g.reqs.size());
+      g.off_base = off;
+      off = align256(off + sizeof(int32_t) * (g.reqs.size() + 1));
+      g.off_cost = off;
+      off = align256(off + sizeof(int32_t) * size_t(g.ntiles));
+      g.off_order = off;
+      off = align256(off + sizeof(int32_t) * size_t(g.ntiles));
+      g.off_hist = off;
+      off = align256(off + 4096);
+    }
+    bytes_ = off;
+    return MFA_OK;
+  }
+
+  size_t bytes() const { return bytes_; }
+
+  // host: bytes() zeroed bytes, copied to dev before the batch runs
+  void materialize(char* dev, unsigned char* host, RenderBatch& b) {
+    for (size_t i = 0; i < args_.size(); ++i) {
+      std::memcpy(host + tf_off_[i], tables_[i].data(), tables_[i].size() * sizeof(float));
+      args_[i].tf = reinterpret_cast<const float4*>(dev + tf_off_[i]);
+    }
+    b.classes.clear();
+    b.single.clear();
+    for (auto& gr : groups_) {
+      mfa::BatchDev bd{};
+      bd.args = reinterpret_cast<const mfa::RenderArgsDev*>(dev + gr.off_args);
+      bd.tile_base = reinterpret_cast<const int32_t*>(dev + gr.off_base);
+      bd.nreq = int32_t(gr.reqs.size());
+      bd.ntiles = int32_t(gr.ntiles);
+      bd.tile_cost = reinterpret_cast<int32_t*>(dev + gr.off_cost);
+      bd.tile_order = reinterpret_cast<int32_t*>(dev + gr.off_order);
+      bd.tile_hist = reinterpret_cast<unsigned*>(dev + gr.off_hist);
+      auto* ha = reinterpret_cast<mfa::RenderArgsDev*>(host + gr.off_args);
+      auto* hb = reinterpret_cast<int32_t*>(host + gr.off_base);
+      int32_t acc = 0;
+      for (size_t j = 0; j < gr.reqs.size(); ++j) {
+        ha[j] = args_[gr.reqs[j]];
+        hb[j] = acc;
+        acc += ha[j].ntiles;
+      }
+      hb[gr.reqs.size()] = acc;
+      b.classes.emplace_back(gr.key, bd);
+    }
+    for (int32_t i : single_) b.single.push_back(args_[i]);
+  }
+
+ private:
+  struct Group {
+    mfa::BatchKey key;
+    std::vector<int32_t> reqs;
+    size_t off_args, off_base, off_cost, off_order, off_hist;
+    int64_t ntiles;
+  };
+  std::vector<mfa::RenderArgsDev> args_;
+  std::vector<size_t> tf_off_;
+  std::vector<std::vector<float>> tables_;
+  std::vector<Group> groups_;
+  std::vector<int32_t> single_;
+  size_t bytes_ = 0;
+};
+
 }  // namespace
 
 extern "C" {
@@ -824,82 +966,18 @@ mfa_status mfa_batch_create(mfa_ctx* ctx, const mfa_render_request* reqs, int32_
   if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
   if (batch_out == nullptr || reqs == nullptr) return fail(MFA_ERR_INVALID, "null argument");
   if (n < 1 || n > kMaxBatch) return fail(MFA_ERR_INVALID, "batch size must be in [1, 65536]");
-  // validate every request; output ranges must not overlap
-  std::vector<std::pair<uintptr_t, uintptr_t>> ranges;
+  std::vector<const DeviceModel*> dms(n);
   for (int32_t i = 0; i < n; ++i) {
-    const mfa_render_request& r = reqs[i];
-    auto it = ctx->models.find(r.model);
+    auto it = ctx->models.find(reqs[i].model);
     if (it == ctx->models.end()) return fail(MFA_ERR_HANDLE, "unknown model handle in batch");
-    const mfa_status st = check_request(it->second, r.camera, r.tf, r.params, r.rgba_dev);
-    if (st != MFA_OK) return fail(st, "request " + std::to_string(i) + ": " + g_last_error);
-    const uintptr_t o = reinterpret_cast<uintptr_t>(r.rgba_dev);
-    ranges.emplace_back(o, o + size_t(r.camera->width) * size_t(r.camera->height) * 16);
-    if (r.samples_dev != nullptr) {
-      const uintptr_t c = reinterpret_cast<uintptr_t>(r.samples_dev);
-      ranges.emplace_back(c, c + sizeof(int64_t));
-    }
+    dms[i] = &it->second;
   }
-  std::sort(ranges.begin(), ranges.end());
-  for (size_t i = 1; i < ranges.size(); ++i)
-    if (ranges[i].first < ranges[i - 1].second)
-      return fail(MFA_ERR_INVALID, "output buffers of a batch overlap");
-
-  // records with placeholder transfer-function pointers, grouped by variant
-  std::vector<mfa::RenderArgsDev> args(n);
-  std::vector<size_t> tf_off(n);
-  size_t off = 0;
-  for (int32_t i = 0; i < n; ++i) {
-    const mfa_render_request& r = reqs[i];
-    build_render_args(ctx->models[r.model], r.camera, r.tf, r.params, r.rgba_dev, r.samples_dev,
-                      nullptr, args[i]);
-    tf_off[i] = off;
-    off = align256(off + size_t(r.tf->n) * 16);
-  }
-  struct Group {
-    mfa::BatchKey key;
-    std::vector<int32_t> reqs;
-    size_t off_args, off_base, off_cost, off_order, off_hist;
-    int64_t ntiles;
-  };
-  std::vector<Group> groups;
-  std::vector<int32_t> single;
-  for (int32_t i = 0; i < n; ++i) {
-    const mfa::RenderArgsDev& a = args[i];
-    if (a.ntiles == 0) {
-      single.push_back(i);
-      continue;
-    }
-    const mfa::BatchKey k{a.m.pmax, a.m.store, a.shading, a.fast, a.eq, 0};
-    Group* gp = nullptr;
-    for (auto& g : groups)
-      if (g.key.pmax == k.pmax && g.key.store == k.store && g.key.shading == k.shading &&
-          g.key.fast == k.fast && g.key.eq == k.eq)
-        gp = &g;
-    if (gp == nullptr) {
-      groups.push_back(Group{k, {}, 0, 0, 0, 0, 0, 0});
-      gp = &groups.back();
-    }
-    gp->reqs.push_back(i);
-    gp->key.lds_bytes = std::max(gp->key.lds_bytes, a.lds_bytes);
-    gp->ntiles += a.ntiles;
-  }
-  for (auto& g : groups) {
-    if (g.ntiles > int64_t(INT32_MAX)) return fail(MFA_ERR_INVALID, "batch has too many tiles");
-    g.off_args = off;
-    off = align256(off + sizeof(mfa::RenderArgsDev) * g.reqs.size());
-    g.off_base = off;
-    off = align256(off + sizeof(int32_t) * (g.reqs.size() + 1));
-    g.off_cost = off;
-    off = align256(off + sizeof(int32_t) * size_t(g.ntiles));
-    g.off_order = off;
-    off = align256(off + sizeof(int32_t) * size_t(g.ntiles));
-    g.off_hist = off;
-    off = align256(off + 4096);
-  }
-  const size_t bytes = off;
+  BatchBuilder bb;
+  mfa_status st = bb.prepare(dms.data(), reqs, n);
+  if (st != MFA_OK) return st;
+  const size_t bytes = bb.bytes();
   if (ctx->budget > 0 && ctx->used + int64_t(bytes) > ctx->budget)
     return fail(MFA_ERR_NOMEM, "batch exceeds the context's memory budget");
-
   DeviceGuard g(ctx->device);
   if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
   void* mem = nullptr;
@@ -908,36 +986,11 @@ mfa_status mfa_batch_create(mfa_ctx* ctx, const mfa_render_request* reqs, int32_
     (void)hipGetLastError();
     return fail(MFA_ERR_NOMEM, hip_msg("hipMalloc (batch)", e));
   }
-  char* dev = static_cast<char*>(mem);
   std::vector<unsigned char> host(bytes, 0);
-  for (int32_t i = 0; i < n; ++i) {
-    std::memcpy(host.data() + tf_off[i], reqs[i].tf->rgba, size_t(reqs[i].tf->n) * 16);
-    args[i].tf = reinterpret_cast<const float4*>(dev + tf_off[i]);
-  }
   RenderBatch b;
+  bb.materialize(static_cast<char*>(mem), host.data(), b);
   b.mem = mem;
   b.bytes = int64_t(bytes);
-  for (auto& gr : groups) {
-    mfa::BatchDev bd{};
-    bd.args = reinterpret_cast<const mfa::RenderArgsDev*>(dev + gr.off_args);
-    bd.tile_base = reinterpret_cast<const int32_t*>(dev + gr.off_base);
-    bd.nreq = int32_t(gr.reqs.size());
-    bd.ntiles = int32_t(gr.ntiles);
-    bd.tile_cost = reinterpret_cast<int32_t*>(dev + gr.off_cost);
-    bd.tile_order = reinterpret_cast<int32_t*>(dev + gr.off_order);
-    bd.tile_hist = reinterpret_cast<unsigned*>(dev + gr.off_hist);
-    auto* ha = reinterpret_cast<mfa::RenderArgsDev*>(host.data() + gr.off_args);
-    auto* hb = reinterpret_cast<int32_t*>(host.data() + gr.off_base);
-    int32_t acc = 0;
-    for (size_t j = 0; j < gr.reqs.size(); ++j) {
-      ha[j] = args[gr.reqs[j]];
-      hb[j] = acc;
-      acc += ha[j].ntiles;
-    }
-    hb[gr.reqs.size()] = acc;
-    b.classes.emplace_back(gr.key, bd);
-  }
-  for (int32_t i : single) b.single.push_back(args[i]);
   e = hipMemcpy(mem, host.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(mem);
@@ -961,15 +1014,8 @@ mfa_status mfa_batch_render(mfa_ctx* ctx, int64_t batch, void* stream) {
   if (it == ctx->batches.end()) return fail(MFA_ERR_HANDLE, "unknown batch handle");
   DeviceGuard g(ctx->device);
   if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
-  const hipStream_t st = static_cast<hipStream_t>(stream);
-  for (const auto& c : it->second.classes) {
-    const hipError_t e = mfa::launch_render_batch(c.second, c.first, st);
-    if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("batch launch", e));
-  }
-  for (const auto& a : it->second.single) {
-    const hipError_t e = mfa::launch_render(a, st, mfa::KernelEvents{});
-    if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("batch launch", e));
-  }
+  const hipError_t e = launch_batch(it->second, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("batch launch", e));
   return MFA_OK;
 }
 
@@ -1016,6 +1062,328 @@ mfa_status mfa_eval_points(mfa_ctx* ctx, int64_t model, int64_t n, const double*
   a.n = n;
   const hipError_t e = mfa::launch_eval(a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("eval launch", e));
+  return MFA_OK;
+}
+
+}  // extern "C"
+
+// --------------------------------------------------------------------------
+// serving: continuous batching of render requests
+// --------------------------------------------------------------------------
+
+namespace {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// A submitted request with private copies of everything it points to.
+struct Pending {
+  int64_t ticket = 0;
+  int64_t model = 0;
+  DeviceModel dm;              // copy of the model record (device pointers)
+  mfa_camera cam{};
+  mfa_render_params prm{};
+  std::vector<float> table;
+  mfa_tf tf{};
+  float* rgba = nullptr;
+  int64_t* samples = nullptr;
+  int64_t footprint = 0;       // output bytes plus an estimate of its share of a batch block
+  int64_t submit_ns = 0;
+};
+
+struct TicketState {
+  mfa_request_info info{};
+  bool finished = false;
+};
+
+// One launch slot: a stream, its completion event, a reusable device block
+// and pinned staging for the block's host image.  A slot is reused only
+// after its event has completed.
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  unsigned char* staging = nullptr;
+  size_t staging_bytes = 0;
+  bool busy = false;
+  int64_t bytes = 0;            // footprint of the requests in flight
+  std::vector<Pending> reqs;
+};
+
+}  // namespace
+
+struct mfa_server {
+  mfa_ctx* ctx = nullptr;
+  mfa_server_config cfg{};
+  std::mutex mu;
+  std::condition_variable work_cv;   // submitters -> worker
+  std::condition_variable done_cv;   // worker -> waiters
+  std::deque<Pending> queue;
+  std::unordered_map<int64_t, TicketState> tickets;
+  std::vector<Slot> slots;
+  int64_t next_ticket = 1;
+  int64_t in_flight_bytes = 0;
+  bool stop = false;
+  std::thread worker;
+  std::string worker_error;
+};
+
+namespace {
+
+// Grow a slot's device block and pinned staging to `bytes`; the slot is idle.
+hipError_t slot_reserve(Slot& sl, size_t bytes) {
+  if (sl.arena_bytes < bytes) {
+    if (sl.arena != nullptr) (void)hipFree(sl.arena);
+    sl.arena = nullptr;
+    sl.arena_bytes = 0;
+    const size_t want = std::max(bytes, size_t(1) << 20) * 3 / 2;
+    const hipError_t e = hipMalloc(&sl.arena, want);
+    if (e != hipSuccess) return e;
+    sl.arena_bytes = want;
+  }
+  if (sl.staging_bytes < bytes) {
+    if (sl.staging != nullptr) (void)hipHostFree(sl.staging);
+    sl.staging = nullptr;
+    sl.staging_bytes = 0;
+    const size_t want = std::max(bytes, size_t(1) << 20) * 3 / 2;
+    const hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&sl.staging), want, 0);
+    if (e != hipSuccess) return e;
+    sl.staging_bytes = want;
+  }
+  return hipSuccess;
+}
+
+// Finish the requests of a slot (status st), under the server lock.
+void slot_retire(mfa_server* sv, Slot& sl, mfa_status st) {
+  const int64_t t = now_ns();
+  for (auto& r : sl.reqs) {
+    auto it = sv->tickets.find(r.ticket);
+    if (it != sv->tickets.end()) {
+      it->second.info.status = st;
+      it->second.info.done_ns = t;
+      it->second.finished = true;
+    }
+    auto mi = sv->ctx->models.find(r.model);
+    if (mi != sv->ctx->models.end()) mi->second.batch_refs -= 1;
+  }
+  sv->in_flight_bytes -= sl.bytes;
+  sl.reqs.clear();
+  sl.bytes = 0;
+  sl.busy = false;
+}
+
+// Build the batch of a slot's requests into its block and enqueue it.
+// Called without the server lock (the slot's requests are owned by the
+// worker until it retires them).
+mfa_status slot_launch(Slot& sl) {
+  const int32_t n = int32_t(sl.reqs.size());
+  std::vector<const DeviceModel*> dms(n);
+  std::vector<mfa_render_request> rq(n);
+  for (int32_t i = 0; i < n; ++i) {
+    Pending& p = sl.reqs[i];
+    p.tf.rgba = p.table.data();
+    dms[i] = &p.dm;
+    rq[i] = mfa_render_request{p.model, &p.cam, &p.tf, &p.prm, p.rgba, p.samples};
+  }
+  BatchBuilder bb;
+  mfa_status st = bb.prepare(dms.data(), rq.data(), n);
+  if (st != MFA_OK) return st;
+  const size_t bytes = bb.bytes();
+  hipError_t e = slot_reserve(sl, bytes);
+  if (e != hipSuccess) return fail(MFA_ERR_NOMEM, hip_msg("server block", e));
+  std::memset(sl.staging, 0, bytes);
+  RenderBatch b;
+  bb.materialize(static_cast<char*>(sl.arena), sl.staging, b);
+  e = hipMemcpyAsync(sl.arena, sl.staging, bytes, hipMemcpyHostToDevice, sl.stream);
+  if (e == hipSuccess) e = launch_batch(b, sl.stream);
+  if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
+  if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("server launch", e));
+  return MFA_OK;
+}
+
+void server_loop(mfa_server* sv) {
+  DeviceGuard g(sv->ctx->device);
+  std::unique_lock<std::mutex> lk(sv->mu);
+  for (;;) {
+    bool progress = false;
+    // retire finished slots
+    for (auto& sl : sv->slots) {
+      if (!sl.busy) continue;
+      const hipError_t q = hipEventQuery(sl.done);
+      if (q == hipErrorNotReady) continue;
+      slot_retire(sv, sl, q == hipSuccess ? MFA_OK : MFA_ERR_DEVICE);
+      progress = true;
+    }
+    if (progress) sv->done_cv.notify_all();
+    // admit queued requests into a free slot
+    Slot* free_slot = nullptr;
+    for (auto& sl : sv->slots)
+      if (!sl.busy) {
+        free_slot = &sl;
+        break;
+      }
+    if (free_slot != nullptr && !sv->queue.empty()) {
+      const int64_t budget = sv->cfg.max_bytes;
+      while (!sv->queue.empty() && int32_t(free_slot->reqs.size()) < sv->cfg.max_batch) {
+        Pending& p = sv->queue.front();
+        if (budget > 0 && sv->in_flight_bytes + free_slot->bytes + p.footprint > budget &&
+            !(free_slot->reqs.empty() && sv->in_flight_bytes == 0))
+          break;
+        free_slot->bytes += p.footprint;
+        free_slot->reqs.push_back(std::move(p));
+        sv->queue.pop_front();
+      }
+      if (!free_slot->reqs.empty()) {
+        free_slot->busy = true;
+        sv->in_flight_bytes += free_slot->bytes;
+        const int64_t t = now_ns();
+        const int32_t nb = int32_t(free_slot->reqs.size());
+        for (auto& r : free_slot->reqs) {
+          TicketState& ts = sv->tickets[r.ticket];
+          ts.info.launch_ns = t;
+          ts.info.batch_size = nb;
+        }
+        lk.unlock();
+        const mfa_status st = slot_launch(*free_slot);
+        lk.lock();
+        if (st != MFA_OK) {
+          (void)hipStreamSynchronize(free_slot->stream);
+          slot_retire(sv, *free_slot, st);
+          sv->done_cv.notify_all();
+        }
+        progress = true;
+      }
+    }
+    bool any_busy = false;
+    for (auto& sl : sv->slots) any_busy = any_busy || sl.busy;
+    if (sv->stop && sv->queue.empty() && !any_busy) break;
+    if (!progress) {
+      // poll the device while work is in flight, else sleep until a submit
+      if (any_busy)
+        sv->work_cv.wait_for(lk, std::chrono::microseconds(20));
+      else
+        sv->work_cv.wait_for(lk, std::chrono::milliseconds(5));
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+mfa_status mfa_server_create(mfa_ctx* ctx, const mfa_server_config* cfg, mfa_server** out) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  if (out == nullptr) return fail(MFA_ERR_INVALID, "null server_out");
+  mfa_server_config c{2, 256, 0};
+  if (cfg != nullptr) c = *cfg;
+  if (c.streams == 0) c.streams = 2;
+  if (c.max_batch == 0) c.max_batch = 256;
+  if (c.streams < 1 || c.streams > 8 || c.max_batch < 1 || c.max_batch > kMaxBatch ||
+      c.max_bytes < 0)
+    return fail(MFA_ERR_INVALID, "server config: streams in [1, 8], max_batch in [1, 65536], "
+                                 "max_bytes >= 0");
+  DeviceGuard g(ctx->device);
+  if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
+  auto* sv = new mfa_server;
+  sv->ctx = ctx;
+  sv->cfg = c;
+  sv->slots.resize(c.streams);
+  for (auto& sl : sv->slots) {
+    hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      for (auto& t : sv->slots) {
+        if (t.done) (void)hipEventDestroy(t.done);
+        if (t.stream) (void)hipStreamDestroy(t.stream);
+      }
+      delete sv;
+      return fail(MFA_ERR_DEVICE, hip_msg("server streams", e));
+    }
+  }
+  sv->worker = std::thread(server_loop, sv);
+  *out = sv;
+  return MFA_OK;
+}
+
+mfa_status mfa_server_submit(mfa_server* sv, const mfa_render_request* req, int64_t* ticket_out) {
+  g_last_error.clear();
+  if (sv == nullptr) return fail(MFA_ERR_HANDLE, "null server");
+  if (req == nullptr || ticket_out == nullptr) return fail(MFA_ERR_INVALID, "null argument");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  if (sv->stop) return fail(MFA_ERR_INVALID, "server is shutting down");
+  auto it = sv->ctx->models.find(req->model);
+  if (it == sv->ctx->models.end()) return fail(MFA_ERR_HANDLE, "unknown model handle");
+  const mfa_status st = check_request(it->second, req->camera, req->tf, req->params,
+                                      req->rgba_dev);
+  if (st != MFA_OK) return st;
+  Pending p;
+  p.model = req->model;
+  p.dm = it->second;
+  p.cam = *req->camera;
+  p.prm = *req->params;
+  p.table.assign(req->tf->rgba, req->tf->rgba + size_t(req->tf->n) * 4);
+  p.tf = *req->tf;
+  p.rgba = req->rgba_dev;
+  p.samples = req->samples_dev;
+  const int64_t pixels = int64_t(p.cam.width) * p.cam.height;
+  p.footprint = pixels * 16 + (pixels / 64 + 1) * 8 + int64_t(p.tf.n) * 16 + 1024;
+  if (sv->cfg.max_bytes > 0 && p.footprint > sv->cfg.max_bytes)
+    return fail(MFA_ERR_NOMEM, "request exceeds the server's byte budget");
+  p.ticket = sv->next_ticket++;
+  p.submit_ns = now_ns();
+  TicketState& ts = sv->tickets[p.ticket];
+  ts.info.status = MFA_OK;
+  ts.info.submit_ns = p.submit_ns;
+  it->second.batch_refs += 1;
+  *ticket_out = p.ticket;
+  sv->queue.push_back(std::move(p));
+  lk.unlock();
+  sv->work_cv.notify_one();
+  return MFA_OK;
+}
+
+mfa_status mfa_server_wait(mfa_server* sv, int64_t ticket, int64_t timeout_us,
+                           mfa_request_info* info) {
+  g_last_error.clear();
+  if (sv == nullptr) return fail(MFA_ERR_HANDLE, "null server");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->tickets.find(ticket);
+  if (it == sv->tickets.end()) return fail(MFA_ERR_HANDLE, "unknown ticket");
+  auto ready = [&] { return sv->tickets[ticket].finished; };
+  if (timeout_us < 0)
+    sv->done_cv.wait(lk, ready);
+  else if (!sv->done_cv.wait_for(lk, std::chrono::microseconds(timeout_us), ready))
+    return fail(MFA_ERR_TIMEOUT, "request not finished");
+  const TicketState ts = sv->tickets[ticket];
+  sv->tickets.erase(ticket);
+  if (info != nullptr) *info = ts.info;
+  if (ts.info.status != MFA_OK) return fail(ts.info.status, "request failed on the device");
+  return MFA_OK;
+}
+
+mfa_status mfa_server_destroy(mfa_server* sv) {
+  g_last_error.clear();
+  if (sv == nullptr) return MFA_OK;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->work_cv.notify_all();
+  if (sv->worker.joinable()) sv->worker.join();
+  DeviceGuard g(sv->ctx->device);
+  for (auto& sl : sv->slots) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.arena) (void)hipFree(sl.arena);
+    if (sl.staging) (void)hipHostFree(sl.staging);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  }
+  delete sv;
   return MFA_OK;
 }
 

@@ -173,6 +173,11 @@ def test_null_context_and_handles(b):
     assert b.lib.mfa_batch_create(None, None, 1, C.byref(bh)) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_batch_render(None, 1, None) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_batch_free(None, 1) == b.MFA_ERR_HANDLE
+    sh = C.c_void_p()
+    assert b.lib.mfa_server_create(None, None, C.byref(sh)) == b.MFA_ERR_HANDLE
+    assert b.lib.mfa_server_submit(None, None, C.byref(bh)) == b.MFA_ERR_HANDLE
+    assert b.lib.mfa_server_wait(None, 1, 0, None) == b.MFA_ERR_HANDLE
+    assert b.lib.mfa_server_destroy(None) == b.MFA_OK
     n = C.c_int64()
     assert b.lib.mfa_kernel_times(None, None, 0, C.byref(n)) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_destroy(None) == b.MFA_OK
