@@ -279,6 +279,64 @@ def batch_leg(b, ctx, steps: int, warmup: int, log):
             b.mfa_model_free(ctx, h)
 
 
+def serve_leg(b, ctx, log, rate: float, duration: float):
+    """The serving workload: requests submitted to the library's render
+    server at their Poisson arrival times; throughput over the whole run and
+    per-request latency (submission to completion)."""
+    import torch
+    models, reqs, arrivals = wl.serve_config(rate=rate, duration_s=duration)
+    p_of = [int(max(spec.degree)) for spec, _ in models]
+    handles = [b.mfa_model_upload(ctx, spec, store) for spec, store in models]
+    try:
+        outs = [torch.empty((r.camera.height, r.camera.width, 4), dtype=torch.float32,
+                            device="cuda") for r in reqs]
+        cnt = torch.zeros((len(reqs),), dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        server = b.mfa_server_create(ctx, streams=2, max_batch=64)
+        infos = []
+        try:
+            # a few requests first, so that the slots' buffers are sized
+            warm = [b.mfa_server_submit(server, handles[r.model], r.camera, r.tf, r.params,
+                                        outs[i], cnt[i:i + 1]) for i, r in enumerate(reqs[:8])]
+            for t in warm:
+                b.mfa_server_wait(server, t, -1)
+            tickets = []
+            t0 = time.perf_counter()
+            for i, r in enumerate(reqs):
+                delay = t0 + arrivals[i] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                tickets.append(b.mfa_server_submit(server, handles[r.model], r.camera, r.tf,
+                                                   r.params, outs[i], cnt[i:i + 1]))
+            infos = [b.mfa_server_wait(server, t, -1) for t in tickets]
+        finally:
+            b.mfa_server_destroy(server)
+        per_req = cnt.cpu().numpy()
+        samples = int(per_req.sum())
+        flops = int(sum(int(n) * flops_per_sample(p_of[r.model]) for n, r in zip(per_req, reqs)))
+        sub = np.array([inf.submit_ns for inf in infos], dtype=np.float64)
+        done = np.array([inf.done_ns for inf in infos], dtype=np.float64)
+        span = (done.max() - sub.min()) * 1e-9
+        lat = (done - sub) * 1e-6
+        bsz = np.array([inf.batch_size for inf in infos])
+        log(f"serve: {len(reqs)} requests in {span:.2f} s, {samples} samples, "
+            f"p50 {np.percentile(lat, 50):.2f} ms, p99 {np.percentile(lat, 99):.2f} ms, "
+            f"mean batch {bsz.mean():.1f}")
+        return {"workload": f"Poisson {rate:g} req/s for {duration:g} s over 16 resident models "
+                            "(p 2-4, 32^3-256^3, FP32/BF16, uniform/Beta(2,5) knots); images "
+                            "128^2-1920x1080, 128-1024 samples per unit length, per-request table",
+                "requests": len(reqs), "offered_req_per_s": rate,
+                "frames_per_s": len(reqs) / span, "samples_per_s": samples / span,
+                "tflops": flops / span / 1e12, "samples": samples,
+                "latency_p50_ms": float(np.percentile(lat, 50)),
+                "latency_p99_ms": float(np.percentile(lat, 99)),
+                "latency_max_ms": float(lat.max()), "mean_batch": float(bsz.mean()),
+                "server": {"streams": 2, "max_batch": 64}}
+    finally:
+        for h in handles:
+            b.mfa_model_free(ctx, h)
+
+
 def rmse_on(image, base):
     if base is None:
         return None
@@ -309,6 +367,9 @@ def main():
     ap.add_argument("--legs", default="fp32,bf16", help="storages to measure")
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="timed repetitions of the batching workload (0 = skip it)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="duration of the served request stream (0 = skip it)")
+    ap.add_argument("--serve-rate", type=float, default=400.0, help="requests per second")
     args = ap.parse_args()
 
     def log(msg):
@@ -356,6 +417,11 @@ def main():
         batch = None
         if args.batch_steps > 0:
             batch = batch_leg(b, ctx, args.batch_steps, 2, log)
+        serve = saturated = None
+        if args.serve_seconds > 0:
+            serve = serve_leg(b, ctx, log, args.serve_rate, args.serve_seconds)
+            # the same request mix offered 20 times faster: the server's capacity
+            saturated = serve_leg(b, ctx, log, 20 * args.serve_rate, args.serve_seconds / 8)
     finally:
         b.mfa_destroy(ctx)
     if args.store not in legs:
@@ -413,6 +479,9 @@ def main():
     }
     if batch is not None:
         line["batch"] = batch
+    if serve is not None:
+        line["serve"] = serve
+        line["serve_saturated"] = saturated
     if base is not None:
         line["cpu_baseline"] = {"value": base["samples"] / base["wall"], "unit": "samples/s",
                                 "cores": cores, "kind": "oracle",

@@ -365,6 +365,42 @@ def batch_config(seed: int = 21, n_requests: int = 64):
     return models, reqs
 
 
+def serve_config(seed: int = 41, rate: float = 400.0, duration_s: float = 2.0):
+    """The serving workload: a Poisson request stream (mean ``rate`` per
+    second for ``duration_s``) over 16 resident models (degree 2-4 on every
+    axis; 32^3 to 256^3 control points; FP32 or BF16; uniform or Beta(2,5)
+    knots; least-squares fits of the test field).  Each request draws its
+    model, an orbit camera, an image size from {128^2, 256^2, 512^2,
+    1024x768, 1280x720, 1920x1080}, N in {128, 256, 512, 1024} samples per
+    unit length (step 1/N) and its own 8-node table.
+    Returns ([(ModelSpec, store)], [BatchRequest], arrival times in s)."""
+    rng = np.random.default_rng(seed)
+    grids = [32, 64, 128, 256]
+    models = []
+    for i in range(16):
+        p = 2 + i % 3
+        n = grids[(i // 3) % 4] if i < 12 else grids[i % 4]
+        beta = bool(i % 2)
+        if beta:
+            knots = tuple(clamped_beta_knots(n, p, rng) for _ in range(3))
+        else:
+            knots = tuple(clamped_uniform_knots(n, p) for _ in range(3))
+        ctrl = fit_field_on_knots(knots, (p, p, p))
+        models.append((ModelSpec((p, p, p), knots, ctrl), int(i % 4 >= 2)))
+    sizes = [(128, 128), (256, 256), (512, 512), (1024, 768), (1280, 720), (1920, 1080)]
+    n_req = int(round(rate * duration_s))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    reqs = []
+    for i in range(n_req):
+        mi = int(rng.integers(len(models)))
+        W, H = sizes[int(rng.integers(len(sizes)))]
+        N = int(rng.choice([128, 256, 512, 1024]))
+        P = models[mi][0].ctrl
+        tf = pwl_tf(int(rng.integers(1 << 30)), float(P.min()), float(P.max()))
+        reqs.append(BatchRequest(mi, random_orbit_camera(rng, W, H), tf, ParamSpec(step=1.0 / N)))
+    return models, reqs, arrivals
+
+
 def pixel_subset(width: int, height: int, size: int, seed: int) -> np.ndarray:
     return np.sort(np.random.default_rng(seed).choice(width * height, size=size,
                                                       replace=False))
