@@ -381,7 +381,7 @@ struct mfa_ctx {
   std::unordered_map<uint64_t, std::vector<TFEntry>> tfs;
   size_t n_tf = 0;
   // scratch of the tile sort: cost and order arrays of `scratch_tiles`
-  // entries each, then 1024 bucket counters
+  // entries each (launch slots), then kPlanHistWords bucket counters
   void* scratch = nullptr;
   int64_t scratch_tiles = 0;
   // kernel timing: event pairs, the first `timed` of which are recorded
@@ -449,7 +449,7 @@ mfa_status ensure_scratch(mfa_ctx* ctx, int64_t tiles) {
     ctx->scratch = nullptr;
     ctx->scratch_tiles = 0;
   }
-  const size_t bytes = size_t(tiles) * 8 + 4096 + 256;
+  const size_t bytes = size_t(tiles) * 8 + size_t(mfa::kPlanHistWords) * 4 + 256;
   const hipError_t e = hipMalloc(&ctx->scratch, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -736,9 +736,26 @@ void build_render_args(const DeviceModel& dm, const mfa_camera* cam, const mfa_t
   a.tile_w = mfa::kTileW;
   a.tile_h = mfa::kTileH;
   a.ntiles = 0;
-  if (a.lds_bytes > 0)
-    a.ntiles = int32_t(int64_t((cam->width + 2 * mfa::kTileW - 1) / (2 * mfa::kTileW)) *
-                       int64_t((cam->height + 2 * mfa::kTileH - 1) / (2 * mfa::kTileH)));
+  a.nslots = 0;
+  if (a.lds_bytes > 0) {
+    const int nsx = (cam->width + 2 * mfa::kTileW - 1) / (2 * mfa::kTileW);
+    const int nsy = (cam->height + 2 * mfa::kTileH - 1) / (2 * mfa::kTileH);
+    a.nsx = nsx;
+    a.ntiles = int32_t(int64_t(nsx) * nsy);
+    const int R = std::max(1, std::min(mfa::kMaxRegion, int(std::sqrt(a.ntiles / 64.0))));
+    a.region = R;
+    // super-tiles per XCD group (regions dealt as in the device's xcd_group)
+    int64_t group[mfa::kXcdGroups] = {};
+    for (int by = 0; by * R < nsy; ++by)
+      for (int bx = 0; bx * R < nsx; ++bx) {
+        const int w = std::min(R, nsx - bx * R);
+        const int h = std::min(R, nsy - by * R);
+        group[(bx + 3 * by) & (mfa::kXcdGroups - 1)] += int64_t(w) * h;
+      }
+    int64_t largest = 0;
+    for (int64_t g : group) largest = std::max(largest, g);
+    a.nslots = int32_t(largest * mfa::kXcdGroups);
+  }
 }
 
 // Enqueue a prepared batch on a stream: per kernel class the planning
@@ -902,7 +919,7 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const 
   mfa::RenderArgsDev a;
   build_render_args(dm, cam, tf, prm, rgba_dev, samples_dev, tf_dev, a);
   if (a.ntiles > 0) {
-    st = ensure_scratch(ctx, a.ntiles);
+    st = ensure_scratch(ctx, a.nslots);
     if (st != MFA_OK) return st;
     int32_t* base = static_cast<int32_t*>(ctx->scratch);
     a.tile_cost = base;

@@ -1118,7 +1118,9 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
 template <int P, int STORE, bool SHADE, bool FAST, bool EQ, int LPR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     brick_waves_per_simd(P, FAST, EQ)))) void render_brick_kernel(RenderArgsDev a) {
-  brick_render<P, STORE, SHADE, FAST, EQ, LPR>(a, uniform_i(a.tile_order[blockIdx.x]));
+  const int sup = uniform_i(a.tile_order[blockIdx.x]);
+  if (sup < 0) return;   // empty launch slot of a smaller XCD group
+  brick_render<P, STORE, SHADE, FAST, EQ, LPR>(a, sup);
 }
 
 // Request of global super-tile t of a batch class: the largest r with
@@ -1149,19 +1151,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
 // tile order: counting sort of the tiles by decreasing estimated work
 // ---------------------------------------------------------------------------
 
-constexpr int kBuckets = 1024;
+constexpr int kBuckets = 512;
 
-// Bucket of a work estimate (4 samples per bucket), largest work first.
-__device__ __forceinline__ int cost_rank(int c) { return kBuckets - 1 - min(c >> 2, kBuckets - 1); }
+// Bucket of a work estimate (8 samples per bucket), largest work first.
+__device__ __forceinline__ int cost_rank(int c) { return kBuckets - 1 - min(c >> 3, kBuckets - 1); }
 
-__global__ __launch_bounds__(256) void plan_zero_kernel(unsigned* hist) {
-  for (int i = threadIdx.x; i < kBuckets; i += 256) hist[i] = 0u;
+// XCD group of super-tile t of a frame nsx super-tiles wide: square regions
+// of region x region super-tiles are dealt to the groups in a skewed
+// pattern, so that each group's regions are spread over the image.
+__device__ __forceinline__ int xcd_group(int t, int nsx, int region) {
+  const int sx = t % nsx, sy = t / nsx;
+  return ((sx / region) + 3 * (sy / region)) & (kXcdGroups - 1);
+}
+
+// Clear G x kBuckets counters and mark every launch slot empty.
+__global__ __launch_bounds__(256) void plan_zero_kernel(unsigned* hist, int nhist, int* order,
+                                                        int nslots) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < nhist) hist[i] = 0u;
+  if (i < nslots) order[i] = -1;
 }
 
 // Work estimate of every super-tile (2x2 tiles of tile_w x tile_h pixels):
 // the largest sample count among nine rays (corners, edge midpoints and
-// centre of its pixel rectangle); and the histogram of the estimates'
-// buckets.
+// centre of its pixel rectangle).
 __device__ __forceinline__ int supertile_cost(const RenderArgsDev& a, int t) {
   const int ntx = (a.width + a.tile_w - 1) / a.tile_w;
   const int nsx = (ntx + 1) >> 1;
@@ -1182,27 +1195,30 @@ __device__ __forceinline__ int supertile_cost(const RenderArgsDev& a, int t) {
   return c;
 }
 
+// Single frame: work estimates and the per-group bucket histogram.
 __global__ __launch_bounds__(256) void plan_cost_kernel(RenderArgsDev a) {
-  __shared__ unsigned h[kBuckets];
+  __shared__ unsigned h[kXcdGroups * kBuckets];
   const int tid = threadIdx.x;
-  for (int i = tid; i < kBuckets; i += 256) h[i] = 0u;
+  for (int i = tid; i < kXcdGroups * kBuckets; i += 256) h[i] = 0u;
   __syncthreads();
   const int t = blockIdx.x * 256 + tid;
   if (t < a.ntiles) {
     const int c = supertile_cost(a, t);
     a.tile_cost[t] = c;
-    atomicAdd(&h[cost_rank(c)], 1u);
+    atomicAdd(&h[xcd_group(t, a.nsx, a.region) * kBuckets + cost_rank(c)], 1u);
   }
   __syncthreads();
-  for (int i = tid; i < kBuckets; i += 256)
+  for (int i = tid; i < kXcdGroups * kBuckets; i += 256)
     if (h[i] != 0u) atomicAdd(&a.tile_hist[i], h[i]);
 }
 
-// Exclusive prefix sum of the bucket histogram (one workgroup).
-__global__ __launch_bounds__(1024) void plan_scan_kernel(unsigned* hist) {
+// Exclusive prefix sum of each group's bucket histogram (one workgroup per
+// group).
+__global__ __launch_bounds__(kBuckets) void plan_scan_kernel(unsigned* hist) {
   __shared__ unsigned v[kBuckets];
   const int tid = threadIdx.x;
-  const unsigned own = hist[tid];
+  unsigned* h = hist + blockIdx.x * kBuckets;
+  const unsigned own = h[tid];
   v[tid] = own;
   __syncthreads();
   for (int off = 1; off < kBuckets; off <<= 1) {
@@ -1211,31 +1227,36 @@ __global__ __launch_bounds__(1024) void plan_scan_kernel(unsigned* hist) {
     v[tid] += add;
     __syncthreads();
   }
-  hist[tid] = v[tid] - own;
+  h[tid] = v[tid] - own;
 }
 
-// Tile list in bucket order; every workgroup reserves one range per bucket
-// it holds tiles of, so positions are unique (order within a bucket is
-// arbitrary and does not affect any pixel).
-__global__ __launch_bounds__(256) void plan_scatter_kernel(const int* cost, int n, unsigned* base,
+// Launch order.  Within its group a super-tile's position follows its
+// bucket (every workgroup reserves one range per bucket it holds tiles of,
+// so positions are unique; the order within a bucket is arbitrary and
+// changes no pixel); slot position * G + group then puts the k-th longest
+// super-tile of group g at workgroup index 8 k + g.  G = 1 for batches.
+template <int G>
+__global__ __launch_bounds__(256) void plan_scatter_kernel(const int* cost, int n, int nsx,
+                                                           int region, unsigned* base,
                                                            int* order) {
-  __shared__ unsigned cnt[kBuckets];
-  __shared__ unsigned off[kBuckets];
+  __shared__ unsigned cnt[G * kBuckets];
+  __shared__ unsigned off[G * kBuckets];
   const int tid = threadIdx.x;
-  for (int i = tid; i < kBuckets; i += 256) cnt[i] = 0u;
+  for (int i = tid; i < G * kBuckets; i += 256) cnt[i] = 0u;
   __syncthreads();
   const int t = blockIdx.x * 256 + tid;
-  int r = 0;
+  int key = 0, g = 0;
   unsigned local = 0u;
   if (t < n) {
-    r = cost_rank(cost[t]);
-    local = atomicAdd(&cnt[r], 1u);
+    g = G == 1 ? 0 : xcd_group(t, nsx, region);
+    key = g * kBuckets + cost_rank(cost[t]);
+    local = atomicAdd(&cnt[key], 1u);
   }
   __syncthreads();
-  for (int i = tid; i < kBuckets; i += 256)
+  for (int i = tid; i < G * kBuckets; i += 256)
     if (cnt[i] != 0u) off[i] = atomicAdd(&base[i], cnt[i]);
   __syncthreads();
-  if (t < n) order[off[r] + local] = t;
+  if (t < n) order[(int)(off[key] + local) * G + g] = t;
 }
 
 // Batch class: clear the bucket counters and every request's sample
@@ -1300,14 +1321,17 @@ hipError_t mark(hipEvent_t ev, hipStream_t st) {
 template <int P, int STORE, bool SHADE, bool FAST, bool EQ>
 hipError_t launch_brick(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
   const unsigned blocks = (unsigned)((a.ntiles + 255) / 256);
-  plan_zero_kernel<<<1, 256, 0, st>>>(a.tile_hist);
+  const int nhist = kXcdGroups * kBuckets;
+  const unsigned zblocks = (unsigned)((max(a.nslots, nhist) + 255) / 256);
+  plan_zero_kernel<<<zblocks, 256, 0, st>>>(a.tile_hist, nhist, a.tile_order, a.nslots);
   plan_cost_kernel<<<blocks, 256, 0, st>>>(a);
-  plan_scan_kernel<<<1, kBuckets, 0, st>>>(a.tile_hist);
-  plan_scatter_kernel<<<blocks, 256, 0, st>>>(a.tile_cost, a.ntiles, a.tile_hist, a.tile_order);
+  plan_scan_kernel<<<kXcdGroups, kBuckets, 0, st>>>(a.tile_hist);
+  plan_scatter_kernel<kXcdGroups>
+      <<<blocks, 256, 0, st>>>(a.tile_cost, a.ntiles, a.nsx, a.region, a.tile_hist, a.tile_order);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = mark(ev.begin, st);
   if (e != hipSuccess) return e;
-  render_brick_kernel<P, STORE, SHADE, FAST, EQ, kLanesPerRay><<<a.ntiles, 256, a.lds_bytes, st>>>(a);
+  render_brick_kernel<P, STORE, SHADE, FAST, EQ, kLanesPerRay><<<a.nslots, 256, a.lds_bytes, st>>>(a);
   e = hipGetLastError();
   return e == hipSuccess ? mark(ev.end, st) : e;
 }
@@ -1339,7 +1363,8 @@ hipError_t launch_batch_class(const BatchDev& b, int lds_bytes, hipStream_t st) 
   batch_zero_kernel<<<1, 256, 0, st>>>(b);
   batch_cost_kernel<<<blocks, 256, 0, st>>>(b);
   plan_scan_kernel<<<1, kBuckets, 0, st>>>(b.tile_hist);
-  plan_scatter_kernel<<<blocks, 256, 0, st>>>(b.tile_cost, b.ntiles, b.tile_hist, b.tile_order);
+  plan_scatter_kernel<1>
+      <<<blocks, 256, 0, st>>>(b.tile_cost, b.ntiles, 1, 1, b.tile_hist, b.tile_order);
   render_batch_kernel<P, STORE, SHADE, FAST, EQ, kLanesPerRay><<<b.ntiles, 256, lds_bytes, st>>>(b);
   return hipGetLastError();
 }

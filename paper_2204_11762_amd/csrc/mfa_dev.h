@@ -17,6 +17,17 @@ constexpr int kLanesPerRay = 4;
 constexpr int kTileW = kLanesPerRay == 4 ? 4 : 8;
 constexpr int kTileH = 64 / kLanesPerRay / kTileW;
 
+// Launch order of single frames: super-tiles are grouped by square regions
+// of `region` x `region` super-tiles into one group per XCD (the hardware
+// deals workgroup b to XCD b mod 8), so that each XCD's L2 holds the
+// control points of its own regions.  The region side is at most
+// kMaxRegion and small enough for about 64 regions, so that every group
+// has work on small frames too.
+constexpr int kXcdGroups = 8;
+constexpr int kMaxRegion = 4;
+// Counters of the tile sort (kXcdGroups x 512 buckets).
+constexpr int kPlanHistWords = kXcdGroups * 512;
+
 // Waves per SIMD that the brick ray caster of kernel degree P is compiled
 // for (four workgroups of four waves per CU, or three for the variants
 // whose registers would otherwise spill), and the LDS one workgroup may use
@@ -107,11 +118,14 @@ struct RenderArgsDev {
   int32_t knot_off[3];  // offset (in doubles) of each axis' knots in LDS
   int32_t lds_bytes;    // dynamic LDS size of one workgroup
   int32_t ntiles;       // super-tiles (2x2 tiles) of the image
+  int32_t nsx;          // super-tiles per image row
+  int32_t region;       // side of the square regions of the XCD grouping (super-tiles)
+  int32_t nslots;       // launch slots: kXcdGroups x the largest group (>= ntiles)
   int32_t tile_w;       // tile size in pixels (kTileW x kTileH)
   int32_t tile_h;
   int32_t* tile_cost;   // ntiles work estimates (scratch)
-  int32_t* tile_order;  // ntiles super-tile indices, longest first (scratch)
-  unsigned* tile_hist;  // 1024 bucket counters of the tile sort (scratch)
+  int32_t* tile_order;  // nslots super-tile indices, -1 for empty slots (scratch)
+  unsigned* tile_hist;  // kPlanHistWords bucket counters of the tile sort (scratch)
 };
 
 struct EvalArgsDev {
@@ -132,7 +146,7 @@ struct BatchDev {
   int32_t ntiles;             // super-tiles of all requests of the class
   int32_t* tile_cost;         // ntiles work estimates (scratch)
   int32_t* tile_order;        // ntiles class-wide super-tile indices, longest first
-  unsigned* tile_hist;        // 1024 bucket counters (scratch)
+  unsigned* tile_hist;        // 512 bucket counters (scratch)
 };
 
 // Kernel variant of a batch class and the dynamic LDS of its launch.

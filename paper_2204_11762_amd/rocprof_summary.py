@@ -27,7 +27,8 @@ import re
 import statistics
 import sys
 
-RENDER_RE = re.compile(r"render_brick_kernel<(\d+), (\d+), (true|false), (true|false), (\d+)>")
+# render_brick_kernel<P, STORE, ...>: degree and storage of the hot kernel
+RENDER_RE = re.compile(r"render_brick_kernel<(\d+), (\d+),")
 
 
 def kernel_table(stats_csv: str) -> list[dict]:
