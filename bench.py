@@ -189,7 +189,7 @@ def gpu_leg(b, ctx, wk, store: int, steps: int, warmup: int, log, nominal_frames
             e1.record(stream)
             torch.cuda.synchronize()
             nominal_ms = e0.elapsed_time(e1) / nsteps
-        log(f"store={'fp32' if store == 0 else 'bf16'}: {samples} samples/frame, "
+        log(f"store={('fp32', 'bf16', 'fp16')[store]}: {samples} samples/frame, "
             f"{wall / steps * 1e3:.3f} ms/frame wall, frame p50 {np.median(lat):.3f} ms, "
             f"render kernel mean {kern.mean():.4f} ms")
         return {"samples": samples, "nominal": nominal, "wall": wall, "lat": lat, "kern": kern,
@@ -337,6 +337,58 @@ def serve_leg(b, ctx, log, rate: float, duration: float):
             b.mfa_model_free(ctx, h)
 
 
+def morton_order(xyz: np.ndarray, bits: int = 10) -> np.ndarray:
+    """Permutation that sorts points in [0,1]^3 along a Morton (Z-order) curve."""
+    q = np.clip((xyz * (1 << bits)).astype(np.int64), 0, (1 << bits) - 1)
+    code = np.zeros(len(xyz), dtype=np.int64)
+    for bit in range(bits):
+        for k in range(3):
+            code |= ((q[:, k] >> bit) & 1) << (3 * bit + k)
+    return np.argsort(code, kind="stable")
+
+
+def eval_leg(b, ctx, wk, steps: int, log, n_points: int = 1 << 24):
+    """Value + gradient queries at n_points points of the 256^3 model
+    (uniformly random, then sorted along a Morton curve), against the HBM
+    roofline: algorithmic bytes per point = (p+1)^3 stored control points +
+    24 B position + 16 B value and gradient."""
+    import torch
+    p = int(max(wk.model.degree))
+    xyz = wl.uniform_points(np.random.default_rng(9), n_points)
+    orders = {"random": np.arange(n_points), "morton": morton_order(xyz)}
+    out = {}
+    for store, name in ((0, "fp32"), (1, "bf16")):
+        h = b.mfa_model_upload(ctx, wk.model, store)
+        try:
+            elem = 4 if store == 0 else 2
+            per_point = (p + 1) ** 3 * elem + 24 + 16
+            for oname, perm in orders.items():
+                x = torch.from_numpy(np.ascontiguousarray(xyz[perm])).cuda()
+                v = torch.empty(n_points, dtype=torch.float32, device="cuda")
+                g = torch.empty((n_points, 3), dtype=torch.float32, device="cuda")
+                b.mfa_eval_points(ctx, h, x, v, g)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(steps):
+                    b.mfa_eval_points(ctx, h, x, v, g)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / steps
+                gbs = n_points * per_point / (ms * 1e-3) / 1e9
+                out[f"{name}_{oname}"] = {"ms": ms, "points_per_s": n_points / (ms * 1e-3),
+                                          "algorithmic_bytes_per_point": per_point,
+                                          "achieved_GBps": gbs, "frac_of_8TBps": gbs / 8000.0}
+                log(f"eval {name} {oname}: {ms:.3f} ms for {n_points} points, "
+                    f"{gbs:.0f} GB/s algorithmic")
+                del x, v, g
+        finally:
+            b.mfa_model_free(ctx, h)
+    out["points"] = n_points
+    return out
+
+
 def rmse_on(image, base):
     if base is None:
         return None
@@ -351,7 +403,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--store", choices=["bf16", "fp32"], default="bf16",
+    ap.add_argument("--store", choices=["bf16", "fp32", "fp16"], default="bf16",
                     help="storage of the headline number (both are measured)")
     ap.add_argument("--cpu-rays", type=int, default=-1,
                     help="rays of the oracle's bounded sample: -1 = every ray that meets "
@@ -364,12 +416,14 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (a plain copy "
                          "kernel of known traffic, for scaling HBM counters)")
-    ap.add_argument("--legs", default="fp32,bf16", help="storages to measure")
+    ap.add_argument("--legs", default="fp32,bf16,fp16", help="storages to measure")
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="timed repetitions of the batching workload (0 = skip it)")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="duration of the served request stream (0 = skip it)")
     ap.add_argument("--serve-rate", type=float, default=400.0, help="requests per second")
+    ap.add_argument("--eval-steps", type=int, default=10,
+                    help="timed repetitions of the point-query micro-benchmark (0 = skip it)")
     args = ap.parse_args()
 
     def log(msg):
@@ -410,10 +464,13 @@ def main():
     ctx = b.mfa_create(0)
     try:
         legs = {}
-        for name, store in (("fp32", 0), ("bf16", 1)):
+        for name, store in (("fp32", 0), ("bf16", 1), ("fp16", 2)):
             if name in args.legs.split(","):
                 legs[name] = gpu_leg(b, ctx, wk, store, args.steps, args.warmup, log,
                                      nominal_frames=not args.no_nominal)
+        evals = None
+        if args.eval_steps > 0:
+            evals = eval_leg(b, ctx, wk, args.eval_steps, log)
         batch = None
         if args.batch_steps > 0:
             batch = batch_leg(b, ctx, args.batch_steps, 2, log)
@@ -471,12 +528,14 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
                      "traffic": measured_traffic(args.store),
-                     "kernel": "render_brick_kernel<3,%s,shade,fast,4>" % (
-                         "1" if args.store == "bf16" else "0"),
+                     "kernel": "render_brick_kernel<3,%d,shade,fast,eq,4>" % (
+                         {"fp32": 0, "bf16": 1, "fp16": 2}[args.store]),
                      "kernel_ms": kern_ms, "flops_per_sample": flops_per_sample(p),
                      "flops_per_launch": flops},
         "legs": {k: summary(v, k) for k, v in legs.items()},
     }
+    if evals is not None:
+        line["eval"] = evals
     if batch is not None:
         line["batch"] = batch
     if serve is not None:

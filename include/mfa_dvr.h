@@ -48,6 +48,7 @@ typedef int32_t mfa_status;
  * and all accumulation are FP32 in either case. */
 #define MFA_STORE_F32 0
 #define MFA_STORE_BF16 1 /* FP64 -> FP32 -> BF16, each step round-to-nearest-even */
+#define MFA_STORE_F16 2  /* FP64 -> FP32 -> IEEE binary16, each step RNE; |rounded| <= 65504 */
 
 #define MFA_CAMERA_ORTHO 0
 #define MFA_CAMERA_PERSP 1
@@ -63,7 +64,7 @@ typedef int32_t mfa_status;
  * [lo, hi] (lo < hi per axis) affinely onto the unit parameter cube. */
 typedef struct mfa_model_desc {
   int32_t degree[3];
-  int32_t store; /* MFA_STORE_F32 or MFA_STORE_BF16 */
+  int32_t store; /* MFA_STORE_F32, MFA_STORE_BF16 or MFA_STORE_F16 */
   int64_t n_ctrl[3];
   const double* knots[3];
   const double* ctrl;

@@ -29,6 +29,7 @@ STATUS_NAMES = {0: "MFA_OK", -1: "MFA_ERR_INVALID", -2: "MFA_ERR_MODEL", -3: "MF
                 -4: "MFA_ERR_DEVICE", -5: "MFA_ERR_HANDLE", -6: "MFA_ERR_TIMEOUT"}
 MFA_STORE_F32 = 0
 MFA_STORE_BF16 = 1
+MFA_STORE_F16 = 2
 MFA_CAMERA_ORTHO = 0
 MFA_CAMERA_PERSP = 1
 

@@ -16,7 +16,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmfadvr.so")
-SOURCES = ["kernels.hip", "abi.cpp"]
+# One translation unit per storage type keeps each compile short; they are
+# compiled in parallel and linked into one library.
+SOURCES = ["kernels_f32.hip", "kernels_bf16.hip", "kernels_f16.hip", "kernels.hip", "abi.cpp"]
 ARCH = "gfx950"
 
 
@@ -40,11 +42,7 @@ def compile_flags() -> list[str]:
     ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source and link the shared library; returns its path."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *compile_flags(), "-shared", "-o", tmp,
-           *[os.path.join(CSRC, s) for s in SOURCES]]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -52,12 +50,29 @@ def build(verbose: bool = False) -> str:
     noise = "'-packed-fp32-ops' is not a recognized feature"
     err = "\n".join(l for l in res.stderr.splitlines() if noise not in l)
     if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({res.returncode}):\n{err}")
+        raise RuntimeError(f"hipcc failed ({res.returncode}): {' '.join(cmd)}\n{err}")
     if verbose and err.strip():
         print(err, file=sys.stderr)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source and link the shared library; returns its path."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+    cc = hipcc()
+    with tempfile.TemporaryDirectory(prefix="mfadvr_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.splitext(src)[0] + ".o") for src in SOURCES]
+        jobs = [[cc, *compile_flags(), "-c", "-o", obj, os.path.join(CSRC, src)]
+                for src, obj in zip(SOURCES, objs)]
+        workers = max(1, min(len(jobs), os.cpu_count() or 1))
+        with ThreadPoolExecutor(max_workers=workers) as pool:
+            for fut in [pool.submit(_run, j, verbose) for j in jobs]:
+                fut.result()
+        tmp = LIB + ".tmp"
+        _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
     os.replace(tmp, LIB)
     return LIB
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    build(verbose="-v" in sys.argv)

@@ -110,7 +110,7 @@ mfa_status validate_model(const mfa_model_desc* d, std::string& msg) {
     msg = "null model descriptor";
     return MFA_ERR_INVALID;
   }
-  if (d->store != MFA_STORE_F32 && d->store != MFA_STORE_BF16) {
+  if (d->store != MFA_STORE_F32 && d->store != MFA_STORE_BF16 && d->store != MFA_STORE_F16) {
     msg = "unknown storage precision";
     return MFA_ERR_MODEL;
   }
@@ -139,6 +139,11 @@ mfa_status validate_model(const mfa_model_desc* d, std::string& msg) {
     const double v = d->ctrl[i];
     if (!std::isfinite(v) || !std::isfinite(float(v))) {
       msg = "control points must be finite and within FP32 range";
+      return MFA_ERR_MODEL;
+    }
+    // binary16: float values of magnitude >= 65520 round to infinity
+    if (d->store == MFA_STORE_F16 && std::fabs(float(v)) >= 65520.0f) {
+      msg = "control points must lie within the FP16 range (|x| < 65520)";
       return MFA_ERR_MODEL;
     }
   }
@@ -260,6 +265,35 @@ uint16_t to_bf16(double x) {
   std::memcpy(&u, &f, 4);
   u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even on the upper half
   return uint16_t(u >> 16);
+}
+
+// IEEE binary16 encoding of float(x), rounded to nearest even (subnormals
+// included; magnitudes that round above 65504 give infinity, which the
+// model check refuses).
+uint16_t to_f16(double x) {
+  const float f = float(x);
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  const uint32_t sign = (u >> 16) & 0x8000u;
+  const int e32 = int((u >> 23) & 0xFFu);
+  const uint32_t man = u & 0x7FFFFFu;
+  if (e32 == 0xFF) return uint16_t(sign | 0x7C00u);
+  const int e = e32 - 127 + 15;
+  if (e >= 31) return uint16_t(sign | 0x7C00u);
+  if (e >= 1) {
+    uint32_t h = (uint32_t(e) << 10) | (man >> 13);
+    const uint32_t rem = man & 0x1FFFu;
+    if (rem > 0x1000u || (rem == 0x1000u && (h & 1u))) ++h;  // a carry may raise the exponent
+    return uint16_t(sign | h);
+  }
+  if (e32 == 0 || e < -10) return uint16_t(sign);
+  const uint32_t m = man | 0x800000u;
+  const int shift = 14 - e;
+  uint32_t q = m >> shift;
+  const uint32_t rem = m & ((1u << shift) - 1u);
+  const uint32_t halfway = 1u << (shift - 1);
+  if (rem > halfway || (rem == halfway && (q & 1u))) ++q;
+  return uint16_t(sign | q);
 }
 
 // Per-span table rows (layout in mfa_dev.h), computed in FP64 and rounded
@@ -573,7 +607,8 @@ mfa_status mfa_model_upload(mfa_ctx* ctx, const mfa_model_desc* d, int64_t* mode
     for (int64_t i = 0; i < total; ++i) c[i] = float(d->ctrl[i]);
   } else {
     uint16_t* c = reinterpret_cast<uint16_t*>(host.data() + off_ctrl);
-    for (int64_t i = 0; i < total; ++i) c[i] = to_bf16(d->ctrl[i]);
+    for (int64_t i = 0; i < total; ++i)
+      c[i] = d->store == MFA_STORE_BF16 ? to_bf16(d->ctrl[i]) : to_f16(d->ctrl[i]);
   }
 
   DeviceGuard g(ctx->device);

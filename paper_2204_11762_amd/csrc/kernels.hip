@@ -1,1440 +1,24 @@
-// HIP kernels for gfx950 (CDNA4): MFA value/gradient queries and the fused
-// MFA ray caster.
-//
-// Per sample (Sect. 3.1, Algorithm 1) a lane
-//   1. forms the sample position in FP64 and normalises it to [0,1]^3,
-//   2. locates the knot span on each axis (exact FP64 comparisons: a
-//      bisection for the first sample of a ray, then a walk, since each
-//      coordinate is monotone along a ray),
-//   3. evaluates the p+1 non-zero B-spline basis functions and their first
-//      derivatives per axis (Cox--de Boor triangle, FP32, reciprocals of
-//      the knot differences read from a per-span table),
-//   4. gathers the (p+1)^3 control-point block as (p+1)^2 rows of p+1
-//      consecutive x values (one bounds-checked buffer load per row) and
-//      contracts it sum-factorised: x first (value and d/dx weights), then
-//      y, then z, giving the value and all three derivatives at once,
-//   5. looks up the RGBA transfer function, applies Phong shading from the
-//      analytic gradient, composites front to back and stops the ray once
-//      the accumulated opacity exceeds the limit.
-// The main ray caster (render_brick_kernel) gives each wave a 4x4 pixel
-// tile with four lanes per ray and stages the control points of a round of
-// samples in LDS; the fallback (render_global_kernel, used when the knots
-// or transfer function do not fit in LDS) gives each lane one ray of a
-// 16x16 tile and gathers from global memory.  In both, neighbouring rays
-// run in one wave, so their gathers share cache lines.
-//
-// Mixed per-axis degrees run in the kernel of the largest degree P: an axis
-// of degree q < P uses the window of P+1 control points that starts at its
-// first non-zero function, with zero weights in the last P-q positions.
-// The control-point buffer is padded with zeros, so every row load of the
-// window stays inside the allocation.
+// Storage-type dispatch of the kernel launchers declared in mfa_dev.h.  The
+// kernels themselves are in kernels_impl.h; each storage type's variants
+// are instantiated in their own translation unit (kernels_f32.hip,
+// kernels_bf16.hip, kernels_f16.hip).
 
-#include <hip/hip_runtime.h>
-
-#include "mfa_dev.h"
+#include "kernels_impl.h"
 
 namespace mfa {
-namespace {
 
-constexpr uint32_t kRsrcWord3 = 0x00020000u;  // raw buffer, 32-bit data format (gfx9)
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
-                                           (int)kRsrcWord3);
-}
-
-__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
-__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
-
-// Row of P+1 consecutive control points along x, starting at element e >= 0.
-template <int P, int STORE>
-__device__ __forceinline__ void load_row(__amdgpu_buffer_rsrc_t rs, int e, float (&r)[P + 1]) {
-  if constexpr (STORE == 0) {
-    const uint32_t off = (uint32_t)e * 4u;
-    if constexpr (P == 1) {
-      const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
-      r[0] = __uint_as_float(v[0]);
-      r[1] = __uint_as_float(v[1]);
-    } else if constexpr (P == 2) {
-      const auto v = __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0);
-      r[0] = __uint_as_float(v[0]);
-      r[1] = __uint_as_float(v[1]);
-      r[2] = __uint_as_float(v[2]);
-    } else if constexpr (P == 3) {
-      const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-      r[0] = __uint_as_float(v[0]);
-      r[1] = __uint_as_float(v[1]);
-      r[2] = __uint_as_float(v[2]);
-      r[3] = __uint_as_float(v[3]);
-    } else {
-      const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-      const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 16u, 0, 0);
-      r[0] = __uint_as_float(v[0]);
-      r[1] = __uint_as_float(v[1]);
-      r[2] = __uint_as_float(v[2]);
-      r[3] = __uint_as_float(v[3]);
-      r[4] = __uint_as_float(w);
-    }
-  } else {
-    // BF16: read whole aligned dwords and realign by 16 bits for odd e.
-    const uint32_t off = (uint32_t)(e >> 1) * 4u;
-    const uint32_t sh = (uint32_t)(e & 1) * 16u;
-    if constexpr (P == 1) {
-      const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
-      const uint32_t w0 = __builtin_amdgcn_alignbit(v[1], v[0], sh);
-      r[0] = bf16_lo(w0);
-      r[1] = bf16_hi(w0);
-    } else if constexpr (P == 2) {
-      const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
-      const uint32_t w0 = __builtin_amdgcn_alignbit(v[1], v[0], sh);
-      const uint32_t w1 = __builtin_amdgcn_alignbit(v[1], v[1], sh);
-      r[0] = bf16_lo(w0);
-      r[1] = bf16_hi(w0);
-      r[2] = bf16_lo(w1);
-    } else if constexpr (P == 3) {
-      const auto v = __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0);
-      const uint32_t w0 = __builtin_amdgcn_alignbit(v[1], v[0], sh);
-      const uint32_t w1 = __builtin_amdgcn_alignbit(v[2], v[1], sh);
-      r[0] = bf16_lo(w0);
-      r[1] = bf16_hi(w0);
-      r[2] = bf16_lo(w1);
-      r[3] = bf16_hi(w1);
-    } else {
-      const auto v = __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0);
-      const uint32_t w0 = __builtin_amdgcn_alignbit(v[1], v[0], sh);
-      const uint32_t w1 = __builtin_amdgcn_alignbit(v[2], v[1], sh);
-      const uint32_t w2 = __builtin_amdgcn_alignbit(v[2], v[2], sh);
-      r[0] = bf16_lo(w0);
-      r[1] = bf16_hi(w0);
-      r[2] = bf16_lo(w1);
-      r[3] = bf16_hi(w1);
-      r[4] = bf16_lo(w2);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// knot spans (exact FP64 comparisons)
-// ---------------------------------------------------------------------------
-
-// Largest s in [p, n-1] with U[s] <= u (u in [0,1]); u = 1 gives n-1.
-__device__ __forceinline__ int span_search(const double* __restrict__ U, int n, int p, double u) {
-  if (u >= U[n]) return n - 1;
-  int lo = p, hi = n;  // U[lo] <= u < U[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (U[mid] <= u)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-// Same result, starting from a nearby span s.
-__device__ __forceinline__ int span_walk(const double* __restrict__ U, int n, int p, double u,
-                                         int s) {
-  while (s < n - 1 && U[s + 1] <= u) ++s;
-  while (s > p && U[s] > u) --s;
-  return s;
-}
-
-// ---------------------------------------------------------------------------
-// basis functions of one axis
-// ---------------------------------------------------------------------------
-
-// Degree-Q basis N[0..Q] = N_{s-Q..s,Q}(u) and parametric derivatives
-// dN[0..Q], from d = u - U_s and the span's table row.  The triangle raises
-// the degree one step at a time; at the last step the scaled lower-degree
-// values tmp_r = N_{s-Q+1+r,Q-1} / (U_{s+r+1} - U_{s+1-Q+r}) give the
-// derivative N'_{s-Q+r,Q} = Q (tmp_{r-1} - tmp_r).
-template <int Q>
-__device__ __forceinline__ void basis_deg(const float* __restrict__ row, float d, float* N,
-                                          float* dN) {
-  constexpr int S = table_stride(Q);
-  float t[S];
-  const float4* r4 = reinterpret_cast<const float4*>(row);
-#pragma unroll
-  for (int i = 0; i < S / 4; ++i) {
-    const float4 v = r4[i];
-    t[4 * i + 0] = v.x;
-    t[4 * i + 1] = v.y;
-    t[4 * i + 2] = v.z;
-    t[4 * i + 3] = v.w;
-  }
-  float left[Q + 1], right[Q + 1];
-  left[1] = d;
-#pragma unroll
-  for (int j = 2; j <= Q; ++j) left[j] = d + t[table_dl(Q, j)];
-#pragma unroll
-  for (int j = 1; j <= Q; ++j) right[j] = t[table_dr(Q, j)] - d;
-  float T[Q];
-  N[0] = 1.0f;
-#pragma unroll
-  for (int q = 1; q <= Q; ++q) {
-    float saved = 0.0f;
-#pragma unroll
-    for (int r = 0; r < q; ++r) {
-      const float tmp = N[r] * t[table_inv(Q, q, r)];
-      N[r] = fmaf(right[r + 1], tmp, saved);
-      saved = left[q - r] * tmp;
-      if (q == Q) T[r] = tmp;
-    }
-    N[q] = saved;
-  }
-  constexpr float fq = (float)Q;
-  dN[0] = -fq * T[0];
-#pragma unroll
-  for (int r = 1; r < Q; ++r) dN[r] = fq * (T[r - 1] - T[r]);
-  dN[Q] = fq * T[Q - 1];
-}
-
-// Window of P+1 weights for an axis of runtime degree q <= P: entries
-// 0..q hold the non-zero functions, the rest are zero.
-template <int P>
-__device__ __forceinline__ void axis_basis(int q, const float* __restrict__ row, float d,
-                                           float (&N)[P + 1], float (&dN)[P + 1]) {
-  if (q == P) {
-    basis_deg<P>(row, d, N, dN);
-    return;
-  }
-#pragma unroll
-  for (int i = 0; i <= P; ++i) {
-    N[i] = 0.0f;
-    dN[i] = 0.0f;
-  }
-  if constexpr (P >= 2) {
-    if (q == 1) basis_deg<1>(row, d, N, dN);
-  }
-  if constexpr (P >= 3) {
-    if (q == 2) basis_deg<2>(row, d, N, dN);
-  }
-  if constexpr (P >= 4) {
-    if (q == 3) basis_deg<3>(row, d, N, dN);
-  }
-}
-
-// Uniform knots (U_{p+k} = k/m on an interior span, m = n - p): in the
-// normalised coordinate t = (u - U_s) m in [0,1) the p+1 non-zero
-// functions are the cardinal B-spline pieces and their t-derivatives.
-template <int Q>
-__device__ __forceinline__ void cardinal(float t, float* N, float* dN) {
-  if constexpr (Q == 1) {
-    N[0] = 1.0f - t;
-    N[1] = t;
-    dN[0] = -1.0f;
-    dN[1] = 1.0f;
-  } else if constexpr (Q == 2) {
-    const float s = 1.0f - t;
-    N[0] = 0.5f * s * s;
-    N[1] = fmaf(t, s, 0.5f);
-    N[2] = 0.5f * t * t;
-    dN[0] = -s;
-    dN[1] = s - t;
-    dN[2] = t;
-  } else if constexpr (Q == 3) {
-    const float t2 = t * t;
-    const float s = 1.0f - t;
-    const float s2 = s * s;
-    N[0] = s2 * s * (1.0f / 6.0f);
-    N[1] = fmaf(t2, fmaf(t, 0.5f, -1.0f), 2.0f / 3.0f);
-    N[2] = fmaf(t, fmaf(t, fmaf(t, -0.5f, 0.5f), 0.5f), 1.0f / 6.0f);
-    N[3] = t2 * t * (1.0f / 6.0f);
-    dN[0] = -0.5f * s2;
-    dN[1] = t * fmaf(1.5f, t, -2.0f);
-    dN[2] = fmaf(t, fmaf(t, -1.5f, 1.0f), 0.5f);
-    dN[3] = 0.5f * t2;
-  } else {
-    // triangle with the uniform knot differences: left[j] = t + j - 1,
-    // right[j] = j - t, every order-q difference equal to q
-    float left[Q + 1], right[Q + 1], T[Q];
-#pragma unroll
-    for (int j = 1; j <= Q; ++j) {
-      left[j] = t + (float)(j - 1);
-      right[j] = (float)j - t;
-    }
-    N[0] = 1.0f;
-#pragma unroll
-    for (int q = 1; q <= Q; ++q) {
-      float saved = 0.0f;
-#pragma unroll
-      for (int r = 0; r < q; ++r) {
-        const float tmp = N[r] * (1.0f / (float)q);
-        N[r] = fmaf(right[r + 1], tmp, saved);
-        saved = left[q - r] * tmp;
-        if (q == Q) T[r] = tmp;
-      }
-      N[q] = saved;
-    }
-    constexpr float fq = (float)Q;
-    dN[0] = -fq * T[0];
-#pragma unroll
-    for (int r = 1; r < Q; ++r) dN[r] = fq * (T[r - 1] - T[r]);
-    dN[Q] = fq * T[Q - 1];
-  }
-}
-
-template <int P>
-__device__ __forceinline__ void cardinal_window(int q, float t, float (&N)[P + 1],
-                                                float (&dN)[P + 1]) {
-  if (q == P) {
-    cardinal<P>(t, N, dN);
-    return;
-  }
-#pragma unroll
-  for (int i = 0; i <= P; ++i) {
-    N[i] = 0.0f;
-    dN[i] = 0.0f;
-  }
-  if constexpr (P >= 2) {
-    if (q == 1) cardinal<1>(t, N, dN);
-  }
-  if constexpr (P >= 3) {
-    if (q == 2) cardinal<2>(t, N, dN);
-  }
-  if constexpr (P >= 4) {
-    if (q == 3) cardinal<3>(t, N, dN);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// sum-factorised contraction of the (P+1)^3 block
-// ---------------------------------------------------------------------------
-
-// f = sum N^x_a N^y_b N^z_c P_abc and the three derivative sums, x first:
-// each row (b,c) is contracted with N^x and dN^x, then y, then z.
-// fetch(b, c, row) supplies row[a] = P_{a,b,c} of the window.
-template <int P, bool GRAD, class Fetch>
-__device__ __forceinline__ void contract(const float (&N)[3][P + 1], const float (&dN)[3][P + 1],
-                                         Fetch fetch, float& f, float (&g)[3]) {
-  float a0[P + 1][P + 1], a1[P + 1][P + 1];
-#pragma unroll
-  for (int c = 0; c <= P; ++c) {
-#pragma unroll
-    for (int b = 0; b <= P; ++b) {
-      float row[P + 1];
-      fetch(b, c, row);
-      float s0 = N[0][0] * row[0];
-      float s1 = dN[0][0] * row[0];
-#pragma unroll
-      for (int a = 1; a <= P; ++a) {
-        s0 = fmaf(N[0][a], row[a], s0);
-        if (GRAD) s1 = fmaf(dN[0][a], row[a], s1);
-      }
-      a0[c][b] = s0;
-      a1[c][b] = s1;
-    }
-  }
-  float b0[P + 1], bx[P + 1], by[P + 1];
-#pragma unroll
-  for (int c = 0; c <= P; ++c) {
-    float s0 = N[1][0] * a0[c][0];
-    float sx = N[1][0] * a1[c][0];
-    float sy = dN[1][0] * a0[c][0];
-#pragma unroll
-    for (int b = 1; b <= P; ++b) {
-      s0 = fmaf(N[1][b], a0[c][b], s0);
-      if (GRAD) {
-        sx = fmaf(N[1][b], a1[c][b], sx);
-        sy = fmaf(dN[1][b], a0[c][b], sy);
-      }
-    }
-    b0[c] = s0;
-    bx[c] = sx;
-    by[c] = sy;
-  }
-  float v = N[2][0] * b0[0];
-  float gx = N[2][0] * bx[0];
-  float gy = N[2][0] * by[0];
-  float gz = dN[2][0] * b0[0];
-#pragma unroll
-  for (int c = 1; c <= P; ++c) {
-    v = fmaf(N[2][c], b0[c], v);
-    if (GRAD) {
-      gx = fmaf(N[2][c], bx[c], gx);
-      gy = fmaf(N[2][c], by[c], gy);
-      gz = fmaf(dN[2][c], b0[c], gz);
-    }
-  }
-  f = v;
-  g[0] = gx;
-  g[1] = gy;
-  g[2] = gz;
-}
-
-// ---------------------------------------------------------------------------
-// value and gradient query at arbitrary points (global-memory gathers)
-// ---------------------------------------------------------------------------
-
-// Value f and world-space gradient g at parameters u (each in [0,1]).
-// span[] carries the spans between calls along one ray; first = true
-// locates them from scratch.
-template <int P, int STORE, bool GRAD>
-__device__ __forceinline__ void query(const ModelDev& m, __amdgpu_buffer_rsrc_t rs,
-                                      const double (&u)[3], int (&span)[3], bool first, float& f,
-                                      float (&g)[3]) {
-  float N[3][P + 1], dN[3][P + 1];
-  int w[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const AxisDev& A = m.ax[k];
-    const int s = first ? span_search(A.knots, A.n, A.p, u[k])
-                        : span_walk(A.knots, A.n, A.p, u[k], span[k]);
-    span[k] = s;
-    const float d = (float)(u[k] - A.knots[s]);
-    const float* row = A.tab + (size_t)(s - A.p) * (size_t)table_stride(A.p);
-    axis_basis<P>(A.p, row, d, N[k], dN[k]);
-    w[k] = s - A.p;
-  }
-  const int e0 = w[0] + m.nx * w[1] + m.nxy * w[2];
-  const int nx = m.nx, nxy = m.nxy;
-  contract<P, GRAD>(
-      N, dN,
-      [&](int b, int c, float (&row)[P + 1]) { load_row<P, STORE>(rs, e0 + b * nx + c * nxy, row); },
-      f, g);
-  if (GRAD) {
-    g[0] *= m.ax[0].gscale;
-    g[1] *= m.ax[1].gscale;
-    g[2] *= m.ax[2].gscale;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// rays
-// ---------------------------------------------------------------------------
-
-struct Ray {
-  double o[3];
-  double d[3];
-  double t0;
-  int nr;  // samples on the ray (0 = miss)
-};
-
-// Ray through the centre of pixel (r, c) and its samples inside the box.
-// Plain FP64 operations in the stated order (no contraction), so that the
-// entry parameter and the sample count are the IEEE results of the
-// defining formulas.
-__device__ __forceinline__ Ray make_ray(const CamParams& a, int r, int c) {
-#pragma clang fp contract(off)
-  Ray ray;
-  const double W = (double)a.width;
-  const double H = (double)a.height;
-  const double ca = 2.0 * ((double)c + 0.5) / W - 1.0;
-  const double cb = 1.0 - 2.0 * ((double)r + 0.5) / H;
-  if (a.kind == 0) {
-    const double sa = ca * a.cam0;
-    const double sb = cb * a.cam1;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      ray.o[k] = a.eye[k] + sa * a.R[k] + sb * a.V[k];
-      ray.d[k] = a.F[k];
-    }
-  } else {
-    const double sa = ca * a.cam0 * a.cam1;
-    const double sb = cb * a.cam0;
-    double dv[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) dv[k] = a.F[k] + sa * a.R[k] + sb * a.V[k];
-    const double len = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      ray.o[k] = a.eye[k];
-      ray.d[k] = dv[k] / len;
-    }
-  }
-  double t0 = 0.0, t1 = __builtin_inf();
-  bool miss = false;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const double dk = ray.d[k], ok = ray.o[k];
-    if (dk != 0.0) {
-      const double ta = (a.lo[k] - ok) / dk;
-      const double tb = (a.hi[k] - ok) / dk;
-      t0 = fmax(t0, fmin(ta, tb));
-      t1 = fmin(t1, fmax(ta, tb));
-    } else if (ok < a.lo[k] || ok > a.hi[k]) {
-      miss = true;
-    }
-  }
-  ray.t0 = t0;
-  ray.nr = 0;
-  if (!miss && t1 > t0) {
-    const double L = floor((t1 - t0) / a.step);
-    ray.nr = (int)fmin(L, (double)kMaxSamplesPerRay);
-  }
-  return ray;
-}
-
-// Parameters of sample s: u = clamp((o + t d - lo) / (hi - lo), 0, 1),
-// t = t0 + (s + 1/2) step, with the same unfused operations.
-__device__ __forceinline__ void sample_params(const CamParams& a, const Ray& ray, int s,
-                                              double (&u)[3]) {
-#pragma clang fp contract(off)
-  const double t = ray.t0 + ((double)s + 0.5) * a.step;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const double x = ray.o[k] + t * ray.d[k];
-    const double v = (x - a.lo[k]) * a.inv_ext[k];
-    u[k] = fmin(fmax(v, 0.0), 1.0);
-  }
-}
-
-__device__ __forceinline__ float ipowf(float x, int k) {
-  float r = 1.0f;
-  while (k) {
-    if (k & 1) r *= x;
-    x *= x;
-    k >>= 1;
-  }
-  return r;
-}
-
-// Transfer function and Phong shading of a sample of value f and world
-// gradient g: shaded colour (sr, sg, sb) and opacity alpha.
-template <bool SHADE, class TfFetch>
-__device__ __forceinline__ void shade_sample(const RenderArgsDev& a, float f, const float (&g)[3],
-                                             float vx, float vy, float vz, TfFetch tf, float& sr,
-                                             float& sg, float& sb, float& alpha) {
-  float x = (f - a.tf_lo) * a.tf_scale;
-  x = fminf(fmaxf(x, 0.0f), 1.0f) * (float)(a.ntf - 1);
-  const int i = min((int)x, a.ntf - 2);
-  const float t = x - (float)i;
-  const float4 c0 = tf(i);
-  const float4 c1 = tf(i + 1);
-  sr = fmaf(t, c1.x - c0.x, c0.x);
-  sg = fmaf(t, c1.y - c0.y, c0.y);
-  sb = fmaf(t, c1.z - c0.z, c0.z);
-  alpha = fmaf(t, c1.w - c0.w, c0.w);
-  if (SHADE) {
-    const float lx = a.light[0], ly = a.light[1], lz = a.light[2];
-    const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
-    const float inv = (g2 >= 1e-12f) ? rsqrtf(g2) : 1e6f;
-    const float nx = g[0] * inv, ny = g[1] * inv, nz = g[2] * inv;
-    const float ndl = nx * lx + ny * ly + nz * lz;
-    const float diff = fabsf(ndl);
-    const float rx = 2.0f * ndl * nx - lx;
-    const float ry = 2.0f * ndl * ny - ly;
-    const float rz = 2.0f * ndl * nz - lz;
-    const float rv = rx * vx + ry * vy + rz * vz;
-    const float spec = a.ks * ipowf(fmaxf(rv, 0.0f), a.shininess);
-    const float kdiff = a.ka + a.kd * diff;
-    sr = fminf(1.0f, fmaf(kdiff, sr, spec));
-    sg = fminf(1.0f, fmaf(kdiff, sg, spec));
-    sb = fminf(1.0f, fmaf(kdiff, sb, spec));
-  }
-}
-
-// One front-to-back compositing step; false once the accumulated opacity
-// exceeds the termination limit.
-__device__ __forceinline__ bool composite_one(float ert, float sr, float sg, float sb, float alpha,
-                                              float& cr, float& cg, float& cb, float& A) {
-  const float wgt = (1.0f - A) * alpha;
-  cr = fmaf(wgt, sr, cr);
-  cg = fmaf(wgt, sg, cg);
-  cb = fmaf(wgt, sb, cb);
-  A += wgt;
-  return !(A > ert);
-}
-
-// Transfer function, Phong shading and one front-to-back compositing step
-// for a sample of value f and world gradient g.  Returns false once the
-// accumulated opacity exceeds the termination limit.
-template <bool SHADE, class TfFetch>
-__device__ __forceinline__ bool shade_composite(const RenderArgsDev& a, float f, const float (&g)[3],
-                                                float vx, float vy, float vz, TfFetch tf,
-                                                float& cr, float& cg, float& cb, float& A) {
-  float x = (f - a.tf_lo) * a.tf_scale;
-  x = fminf(fmaxf(x, 0.0f), 1.0f) * (float)(a.ntf - 1);
-  const int i = min((int)x, a.ntf - 2);
-  const float t = x - (float)i;
-  const float4 c0 = tf(i);
-  const float4 c1 = tf(i + 1);
-  float sr = fmaf(t, c1.x - c0.x, c0.x);
-  float sg = fmaf(t, c1.y - c0.y, c0.y);
-  float sb = fmaf(t, c1.z - c0.z, c0.z);
-  const float alpha = fmaf(t, c1.w - c0.w, c0.w);
-  if (SHADE) {
-    const float lx = a.light[0], ly = a.light[1], lz = a.light[2];
-    const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
-    const float inv = (g2 >= 1e-12f) ? rsqrtf(g2) : 1e6f;
-    const float nx = g[0] * inv, ny = g[1] * inv, nz = g[2] * inv;
-    const float ndl = nx * lx + ny * ly + nz * lz;
-    const float diff = fabsf(ndl);
-    const float rx = 2.0f * ndl * nx - lx;
-    const float ry = 2.0f * ndl * ny - ly;
-    const float rz = 2.0f * ndl * nz - lz;
-    const float rv = rx * vx + ry * vy + rz * vz;
-    const float spec = a.ks * ipowf(fmaxf(rv, 0.0f), a.shininess);
-    const float kdiff = a.ka + a.kd * diff;
-    sr = fminf(1.0f, fmaf(kdiff, sr, spec));
-    sg = fminf(1.0f, fmaf(kdiff, sg, spec));
-    sb = fminf(1.0f, fmaf(kdiff, sb, spec));
-  }
-  const float wgt = (1.0f - A) * alpha;
-  cr = fmaf(wgt, sr, cr);
-  cg = fmaf(wgt, sg, cg);
-  cb = fmaf(wgt, sb, cb);
-  A += wgt;
-  return !(A > a.ert);
-}
-
-__device__ __forceinline__ void count_samples(const RenderArgsDev& a, int count, int lane) {
-  if (a.samples != nullptr) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) count += __shfl_xor(count, off, 64);
-    if (lane == 0 && count != 0) atomicAdd(a.samples, (unsigned long long)count);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// fallback ray caster: all data from global memory
-// ---------------------------------------------------------------------------
-
-// Used when the knots or transfer function of a request do not fit the LDS
-// budget of the brick kernel.
-template <int P, int STORE, bool SHADE>
-__global__ __launch_bounds__(256) void render_global_kernel(RenderArgsDev a) {
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6;
-  const int lane = tid & 63;
-  const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
-  const int py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
-  const bool inside = px < a.width && py < a.height;
-  int count = 0;
-  if (inside) {
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.m.ctrl, a.m.ctrl_bytes);
-    const Ray ray = make_ray(a.cam, py, px);
-    float cr = 0.0f, cg = 0.0f, cb = 0.0f, A = 0.0f;
-    const float vx = -(float)ray.d[0], vy = -(float)ray.d[1], vz = -(float)ray.d[2];
-    const float4* tfp = a.tf;
-    auto tf = [&](int i) { return tfp[i]; };
-    int span[3] = {0, 0, 0};
-    for (int s = 0; s < ray.nr; ++s) {
-      double u[3];
-      sample_params(a.cam, ray, s, u);
-      float f, g[3];
-      query<P, STORE, SHADE>(a.m, rs, u, span, s == 0, f, g);
-      ++count;
-      if (!shade_composite<SHADE>(a, f, g, vx, vy, vz, tf, cr, cg, cb, A)) break;
-    }
-    float4 o;
-    o.x = cr;
-    o.y = cg;
-    o.z = cb;
-    o.w = A;
-    reinterpret_cast<float4*>(a.out)[(size_t)py * (size_t)a.width + (size_t)px] = o;
-  }
-  count_samples(a, count, lane);
-}
-
-// ---------------------------------------------------------------------------
-// LDS-brick ray caster
-// ---------------------------------------------------------------------------
-
-struct SpanState {
-  int s;      // current span
-  double lo;  // U_s
-  double hi;  // U_{s+1}
-};
-
-// Largest s in [p, n-1] with K[s] <= u by bisection (K in LDS).
-__device__ __forceinline__ int lds_span_search(const double* K, int n, int p, double u) {
-  if (u >= K[n]) return n - 1;
-  int lo = p, hi = n;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (K[mid] <= u)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-// Move the cached span to the one of u (a few steps at most between
-// consecutive samples); knots from LDS.
-__device__ __forceinline__ void span_step(const double* K, int n, int p, double u, SpanState& st) {
-  if (u >= st.hi && st.s < n - 1) {
-    do {
-      ++st.s;
-      st.lo = st.hi;
-      st.hi = K[st.s + 1];
-    } while (u >= st.hi && st.s < n - 1);
-  } else if (u < st.lo && st.s > p) {
-    do {
-      --st.s;
-      st.hi = st.lo;
-      st.lo = K[st.s];
-    } while (u < st.lo && st.s > p);
-  }
-}
-
-// Basis window of one axis for the current span.  Uniform knots on an
-// interior span use the cardinal pieces (derivatives in t = u m units);
-// otherwise the triangle with the span's reciprocal table (derivatives in
-// u units, rescaled to t units for uniform models so that one gradient
-// factor per axis applies).
-template <int P, bool UNIFORM>
-__device__ __forceinline__ void axis_weights(const AxisDev& A, const SpanState& st, double u,
-                                             float (&N)[P + 1], float (&dN)[P + 1]) {
-  const int q = A.p;
-  if constexpr (UNIFORM) {
-    if (st.s >= 2 * q - 1 && st.s <= A.n - q) {
-      const float t = (float)((u - st.lo) * A.m);
-      cardinal_window<P>(q, t, N, dN);
-      return;
-    }
-  }
-  const float d = (float)(u - st.lo);
-  const float* row = A.tab + (size_t)(st.s - q) * (size_t)table_stride(q);
-  axis_basis<P>(q, row, d, N, dN);
-  if constexpr (UNIFORM) {
-#pragma unroll
-    for (int i = 0; i <= P; ++i) dN[i] *= A.inv_m;
-  }
-}
-
-// Minimum (MAX = false) or maximum over the 64 lanes of a wave, returned as
-// a wave-uniform value.  Butterflies inside each row of 16 lanes by DPP
-// (pair swap, quad-half swap, half-row mirror, row mirror), then across
-// rows and halves with the row-swapping permutes.  Every lane of the wave
-// must be active.
-template <bool MAX>
-__device__ __forceinline__ unsigned wave_reduce_u32(unsigned v) {
-  auto op = [](unsigned x, unsigned y) { return MAX ? (x > y ? x : y) : (x < y ? x : y); };
-  constexpr int id = MAX ? 0 : -1;
-  v = op(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0xB1, 0xF, 0xF, false));
-  v = op(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x4E, 0xF, 0xF, false));
-  v = op(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x141, 0xF, 0xF, false));
-  v = op(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x140, 0xF, 0xF, false));
-  const auto r16 = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-  v = op(r16[0], r16[1]);
-  const auto r32 = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-  v = op(r32[0], r32[1]);
-  return __builtin_amdgcn_readfirstlane(v);
-}
-
-__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// Value of lane (group base + q) of each aligned group of L lanes (L = 1, 2
-// or 4, so a group never leaves its quad of lanes), by a DPP quad
-// permutation.
-template <int L, int Q>
-__device__ __forceinline__ float group_bcast(float v) {
-  if constexpr (L == 1) {
-    return v;
-  } else {
-    constexpr int b0 = (0 & ~(L - 1)) + Q, b1 = (1 & ~(L - 1)) + Q;
-    constexpr int b2 = (2 & ~(L - 1)) + Q, b3 = (3 & ~(L - 1)) + Q;
-    constexpr int ctrl = b0 | (b1 << 2) | (b2 << 4) | (b3 << 6);
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
-  }
-}
-
-// a / b for 0 <= a < 2^22, b >= 1, with inv_b ~ 1/b: float estimate plus
-// one correction step.
-__device__ __forceinline__ int div_small(int a, int b, float inv_b) {
-  int q = (int)((float)a * inv_b);
-  const int r = a - q * b;
-  q += (r >= b) ? 1 : 0;
-  q -= (r < 0) ? 1 : 0;
-  return q;
-}
-
-// Ray caster over pixel tiles, one tile per wave.  Workgroup b renders the
-// 2x2 tiles of entry b of a list of super-tiles sorted by decreasing
-// estimated work, and the hardware starts workgroups in index order, so the
-// longest rays start first while the four waves of a workgroup work on
-// neighbouring tiles.  LPR lanes share a ray (a tile has 64/LPR rays): lane e of a ray
-// evaluates samples e, e+LPR, e+2 LPR, ..., the group exchanges the shaded
-// samples through DPP and composites them in ray order, so a ray's serial
-// chain is LPR times shorter while the composited result is the same as
-// with one lane per ray.
-//
-// A wave marches its rays in rounds of `spr` samples.  Before a round it
-// stages, into its own LDS brick, every control point that the windows of
-// its active rays can touch during the round (the box of spans between the
-// smallest and largest parameters of the round's first and last samples);
-// the round's samples then gather from LDS.  The four waves of a workgroup
-// share the transfer function (and knots) in LDS and never wait for each
-// other after loading them.  Which wave renders which tile does not change
-// any pixel; on the FAST path the round boundaries of a ray (where FP32
-// stepping restarts from FP64) depend on the other live rays of its tile,
-// which moves results only at rounding level.
-//
-// Span location.  FAST (uniform knots U_{p+j} = j/m on every axis, every
-// degree >= 2): at the start of a round each lane takes, in FP64, the cell
-// c = floor(u m) of its first sample and the local coordinate t = u m - c;
-// the samples of the round then advance t in FP32 (t + i * dt) and take the
-// cell floor(t).  The knots themselves are never read.  A sample within
-// rounding of a knot may use the neighbouring polynomial piece, which for
-// degree >= 2 gives the same value and gradient up to rounding.  GENERAL:
-// every sample's span is located exactly in FP64 against the knots (kept in
-// LDS; cached bounds, stepping along the ray).
-//
-// Round length.  A round starts at `spr` samples and is halved while the
-// box of control points it touches exceeds the brick, so that nearly every
-// round gathers from LDS; a round that still does not fit at two samples
-// per lane gathers from global memory.
-template <int P, int STORE, bool SHADE, bool FAST, bool EQ, int LPR>
-__device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
-  static_assert(LPR == 1 || LPR == 2 || LPR == 4, "lanes per ray");
-  constexpr int TW = LPR == 4 ? 4 : 8;        // tile width in pixels
-  constexpr int TH = 64 / LPR / TW;           // tile height
-  extern __shared__ float4 lds4[];
-  char* lds = reinterpret_cast<char*>(lds4);
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6;
-  const int lane = tid & 63;
-
-  // transfer function and knots, shared by the four waves
-  float4* tf_lds = lds4;
-  for (int i = tid; i < a.ntf; i += 256) tf_lds[i] = a.tf[i];
-  double* knots = reinterpret_cast<double*>(lds + a.lds_knots);
-  if constexpr (!FAST) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int nk = a.m.ax[k].n + a.m.ax[k].p + 1;
-      for (int i = tid; i < nk; i += 256) knots[a.knot_off[k] + i] = a.m.ax[k].knots[i];
-    }
-  }
-  __syncthreads();
-  float* brick = reinterpret_cast<float*>(lds + a.lds_bricks) + wave * a.brick_cap;
-  const double* K[3] = {knots + a.knot_off[0], knots + a.knot_off[1], knots + a.knot_off[2]};
-  auto tf = [&](int i) { return tf_lds[i]; };
-
-  const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.m.ctrl, a.m.ctrl_bytes);
-  const int ntx = (a.width + TW - 1) / TW;
-  const int nx = a.m.nx, nxy = a.m.nxy;
-  const int S = a.spr;
-  const int ray_lane = lane / LPR;   // ray of this lane within the tile
-  const int e = lane % LPR;          // this lane's sample phase
-  float gfac[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-    gfac[k] = FAST ? a.m.ax[k].gscale * (float)a.m.ax[k].m : a.m.ax[k].gscale;
-  int count = 0;
-
-  // the workgroup renders super-tile sup (2x2 tiles), wave w its quadrant
-  const int nsx = (ntx + 1) >> 1;
-  const int tx = (sup % nsx) * 2 + (wave & 1);
-  const int ty = (sup / nsx) * 2 + (wave >> 1);
-  const int px = tx * TW + ray_lane % TW;
-  const int py = ty * TH + ray_lane / TW;
-  const bool inside = px < a.width && py < a.height;
-
-  // u_k(s) = ua_k + s ub_k: the sample parameters as an affine function of
-  // the sample index
-  int nr = 0;
-  double ua[3] = {0.0, 0.0, 0.0}, ub[3] = {0.0, 0.0, 0.0};
-  float vx = 0.0f, vy = 0.0f, vz = 0.0f;
-  if (inside) {
-    const Ray ray = make_ray(a.cam, py, px);
-    nr = ray.nr;
-    const double t_half = ray.t0 + 0.5 * a.cam.step;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      ua[k] = (ray.o[k] + t_half * ray.d[k] - a.cam.lo[k]) * a.cam.inv_ext[k];
-      ub[k] = a.cam.step * ray.d[k] * a.cam.inv_ext[k];
-    }
-    vx = -(float)ray.d[0];
-    vy = -(float)ray.d[1];
-    vz = -(float)ray.d[2];
-  }
-  auto param = [&](int s, int k) {
-    return fmin(fmax(fma((double)s, ub[k], ua[k]), 0.0), 1.0);
-  };
-
-  bool alive = nr > 0;
-  // GENERAL: exact span state per axis
-  SpanState st[3];
-  // FAST: per-lane increment of the local coordinate between the lane's
-  // consecutive samples (LPR samples apart)
-  float dt[3];
-  if constexpr (FAST) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) dt[k] = (float)(ub[k] * a.m.ax[k].m * (double)LPR);
-  } else {
-    if (alive) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double u = param(min(e, nr - 1), k);
-        st[k].s = lds_span_search(K[k], a.m.ax[k].n, a.m.ax[k].p, u);
-        st[k].lo = K[k][st[k].s];
-        st[k].hi = K[k][st[k].s + 1];
-      }
-    }
-  }
-  float cr = 0.0f, cg = 0.0f, cb = 0.0f, A = 0.0f;
-
-  for (int s0 = 0, sr = S;; s0 += sr) {
-    if (!__any(alive)) break;
-    // A round covers samples [s0, s0 + sr) of every live ray of the wave.
-    // It starts at the full length and is halved while the control points
-    // it touches do not fit the brick, down to two samples per lane.
-    int s1, blo[3], bext[3], pitch_y, pitch_z, nel;
-    bool fits;
-    for (sr = S;; sr >>= 1) {
-      s1 = alive ? min(s0 + sr, nr) : s0;
-      // spans of the parameter box of the round (with a margin of 1e-6 in
-      // u), reduced over the live rays of the wave
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const AxisDev& Ax = a.m.ax[k];
-        const int q = EQ ? P : Ax.p;
-        unsigned l = 0xFFFFFFFFu, h = 0u;
-        if (alive) {
-          const double u0 = param(s0, k), u1 = param(s1 - 1, k);
-          const double ul = fmax(fmin(u0, u1) - 1e-6, 0.0);
-          const double uh = fmin(fmax(u0, u1) + 1e-6, 1.0);
-          if constexpr (FAST) {
-            // cells of u m; a sample's cell (below) is computed the same way
-            const int m = Ax.n - q;
-            l = (unsigned)min(max((int)(ul * Ax.m), 0), m - 1);
-            h = (unsigned)min(max((int)(uh * Ax.m), 0), m - 1);
-          } else {
-            // non-negative floats order as their bit patterns
-            l = __float_as_uint((float)ul);
-            h = __float_as_uint((float)uh);
-          }
-        }
-        l = wave_reduce_u32<false>(l);
-        h = wave_reduce_u32<true>(h);
-        int sl, sh;
-        if constexpr (FAST) {
-          sl = q + (int)l;
-          sh = q + (int)h;
-        } else {
-          sl = lds_span_search(K[k], Ax.n, q, fmin((double)__uint_as_float(l), 1.0));
-          sh = lds_span_search(K[k], Ax.n, q, fmin((double)__uint_as_float(h), 1.0));
-        }
-        blo[k] = uniform_i(sl - q);
-        bext[k] = uniform_i(sh - sl + P + 1);
-      }
-      pitch_y = (bext[0] + 3) & ~3;
-      pitch_z = pitch_y * bext[1];
-      nel = pitch_z * bext[2];
-      fits = nel <= a.brick_cap;
-      if (fits || sr <= 2 * LPR) break;
-    }
-
-    if (fits) {
-      // Stage the brick: group gi = ix + gx (jy + bext1 kz) holds the four
-      // consecutive x values starting at x = 4 ix of row (jy, kz), at LDS
-      // offset 4 gi.  Lane L takes groups L, L + 64, ...; its (ix, jy, kz)
-      // and global element index advance by the mixed-radix digits of 64.
-      const int gx = pitch_y >> 2;
-      const int gxy = gx * bext[1];
-      const int ngroups = gxy * bext[2];
-      const float inv_gx = __builtin_amdgcn_rcpf((float)gx);
-      const int d_row = uniform_i(div_small(64, gx, inv_gx));
-      const int d_ix = 64 - d_row * gx;
-      const int d_kz = uniform_i(div_small(d_row, bext[1], __builtin_amdgcn_rcpf((float)bext[1])));
-      const int d_jy = d_row - d_kz * bext[1];
-      const int dg = 4 * d_ix + nx * d_jy + nxy * d_kz;   // step without carries
-      const int dg_c1 = nx - 4 * gx;                      // carry ix -> jy
-      const int dg_c2 = nxy - nx * bext[1];               // carry jy -> kz
-      const int kz = div_small(lane, gxy, __builtin_amdgcn_rcpf((float)gxy));
-      const int rem = lane - kz * gxy;
-      int jy = div_small(rem, gx, inv_gx);
-      int ix = rem - jy * gx;
-      int g = (blo[0] + 4 * ix) + nx * (blo[1] + jy) + nxy * (blo[2] + kz);
-      // four groups per lane in flight: loads past the last group read
-      // element 0 (and are dropped), only the LDS stores are predicated
-      for (int gi = lane; gi < ngroups; gi += 256) {
-        float v[4][4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          load_row<3, STORE>(rs, gi + 64 * u < ngroups ? g : 0, v[u]);
-          ix += d_ix;
-          jy += d_jy;
-          g += dg;
-          if (ix >= gx) {
-            ix -= gx;
-            jy += 1;
-            g += dg_c1;
-          }
-          if (jy >= bext[1]) {
-            jy -= bext[1];
-            g += dg_c2;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (gi + 64 * u < ngroups) {
-            float4 w;
-            w.x = v[u][0];
-            w.y = v[u][1];
-            w.z = v[u][2];
-            w.w = v[u][3];
-            *reinterpret_cast<float4*>(brick + 4 * (gi + 64 * u)) = w;
-          }
-        }
-      }
-    }
-    const int emax = nel - 1 - (P + P * pitch_y + P * pitch_z);
-
-    // FAST: cell c = floor(u m) (clamped to the spans) and local coordinate
-    // u m - c of this lane's first sample of the round, in FP64
-    int ca[3] = {0, 0, 0};
-    float ta[3] = {0.0f, 0.0f, 0.0f};
-    if constexpr (FAST) {
-      if (s0 + e < s1) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const AxisDev& Ax = a.m.ax[k];
-          const int m = Ax.n - (EQ ? P : Ax.p);
-          const double um = param(s0 + e, k) * Ax.m;
-          const int c = min(max((int)um, 0), m - 1);
-          ca[k] = c;
-          ta[k] = (float)(um - (double)c);
-        }
-      }
-    }
-
-    // one lane's sample: basis weights and window start of each axis
-    auto weights = [&](int s, int i, float (&N)[3][P + 1], float (&dN)[3][P + 1], int (&w)[3]) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const AxisDev& Ax = a.m.ax[k];
-        const int q = EQ ? P : Ax.p;
-        if constexpr (FAST) {
-          const int m = Ax.n - q;
-          const float t = fmaf((float)i, dt[k], ta[k]);
-          const float fl = floorf(t);
-          const int c = min(max(ca[k] + (int)fl, 0), m - 1);
-          const float tl = t - (float)(c - ca[k]);
-          w[k] = c;
-          if (c >= q - 1 && c <= m - q) {
-            if constexpr (EQ)
-              cardinal<P>(tl, N[k], dN[k]);
-            else
-              cardinal_window<P>(q, tl, N[k], dN[k]);
-          } else {
-            // boundary span: triangle with the span's reciprocal table
-            const float* row = Ax.tab + (size_t)c * (size_t)table_stride(q);
-            axis_basis<P>(q, row, tl * Ax.inv_m, N[k], dN[k]);
-#pragma unroll
-            for (int r = 0; r <= P; ++r) dN[k][r] *= Ax.inv_m;
-          }
-        } else {
-          const double u = param(s, k);
-          span_step(K[k], Ax.n, q, u, st[k]);
-          const float d = (float)(u - st[k].lo);
-          const float* row = Ax.tab + (size_t)(st[k].s - q) * (size_t)table_stride(q);
-          axis_basis<P>(q, row, d, N[k], dN[k]);
-          w[k] = st[k].s - q;
-        }
-      }
-    };
-
-    // shade this lane's sample, then composite the group's samples
-    // j, j+1, ..., j+LPR-1 in order; false once the ray terminates
-    auto finish = [&](int j, float f, const float (&g)[3], bool valid) {
-      float sr = 0.0f, sg = 0.0f, sb = 0.0f, alpha = 0.0f;
-      if (valid) {
-        float gw[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) gw[k] = g[k] * gfac[k];
-        shade_sample<SHADE>(a, f, gw, vx, vy, vz, tf, sr, sg, sb, alpha);
-      }
-      bool go = true;
-#define MFA_COMPOSITE_PHASE(Q)                                                      \
-  if constexpr ((Q) < LPR) {                                                        \
-    const float qr = group_bcast<LPR, (Q)>(sr), qg = group_bcast<LPR, (Q)>(sg);    \
-    const float qb = group_bcast<LPR, (Q)>(sb), qa = group_bcast<LPR, (Q)>(alpha); \
-    if (go && j + (Q) < s1) {                                                       \
-      count += (e == 0) ? 1 : 0;                                                    \
-      go = composite_one(a.ert, qr, qg, qb, qa, cr, cg, cb, A);                     \
-    }                                                                               \
-  }
-      MFA_COMPOSITE_PHASE(0)
-      MFA_COMPOSITE_PHASE(1)
-      MFA_COMPOSITE_PHASE(2)
-      MFA_COMPOSITE_PHASE(3)
-#undef MFA_COMPOSITE_PHASE
-      return go;
-    };
-
-    if (fits) {
-      for (int j = s0, i = 0; j < s1; j += LPR, ++i) {
-        const int s = j + e;
-        float f = 0.0f, g[3] = {0.0f, 0.0f, 0.0f};
-        if (s < s1) {
-          float N[3][P + 1], dN[3][P + 1];
-          int w[3];
-          weights(s, i, N, dN, w);
-          int e0 = (w[0] - blo[0]) + pitch_y * (w[1] - blo[1]) + pitch_z * (w[2] - blo[2]);
-          e0 = min(max(e0, 0), emax);
-          contract<P, SHADE>(
-              N, dN,
-              [&](int b, int c, float (&row)[P + 1]) {
-                const float* r = brick + e0 + b * pitch_y + c * pitch_z;
-#pragma unroll
-                for (int q = 0; q <= P; ++q) row[q] = r[q];
-              },
-              f, g);
-        }
-        if (!finish(j, f, g, s < s1)) {
-          alive = false;
-          break;
-        }
-      }
-    } else {
-      for (int j = s0, i = 0; j < s1; j += LPR, ++i) {
-        const int s = j + e;
-        float f = 0.0f, g[3] = {0.0f, 0.0f, 0.0f};
-        if (s < s1) {
-          float N[3][P + 1], dN[3][P + 1];
-          int w[3];
-          weights(s, i, N, dN, w);
-          const int e0 = w[0] + nx * w[1] + nxy * w[2];
-          contract<P, SHADE>(
-              N, dN,
-              [&](int b, int c, float (&row)[P + 1]) {
-                load_row<P, STORE>(rs, e0 + b * nx + c * nxy, row);
-              },
-              f, g);
-        }
-        if (!finish(j, f, g, s < s1)) {
-          alive = false;
-          break;
-        }
-      }
-    }
-    if (s1 >= nr) alive = false;
-  }
-  if (inside && e == 0) {
-    float4 o;
-    o.x = cr;
-    o.y = cg;
-    o.z = cb;
-    o.w = A;
-    reinterpret_cast<float4*>(a.out)[(size_t)py * (size_t)a.width + (size_t)px] = o;
-  }
-  count_samples(a, count, lane);
-}
-
-template <int P, int STORE, bool SHADE, bool FAST, bool EQ, int LPR>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    brick_waves_per_simd(P, FAST, EQ)))) void render_brick_kernel(RenderArgsDev a) {
-  const int sup = uniform_i(a.tile_order[blockIdx.x]);
-  if (sup < 0) return;   // empty launch slot of a smaller XCD group
-  brick_render<P, STORE, SHADE, FAST, EQ, LPR>(a, sup);
-}
-
-// Request of global super-tile t of a batch class: the largest r with
-// base[r] <= t (base holds the prefix sums of the requests' super-tiles).
-__device__ __forceinline__ int batch_request(const int32_t* base, int nreq, int t) {
-  int lo = 0, hi = nreq;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (base[mid] <= t)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-// The same ray caster over the super-tiles of every request of a batch
-// class; workgroup b renders entry b of the class's work-sorted list.
-template <int P, int STORE, bool SHADE, bool FAST, bool EQ, int LPR>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    brick_waves_per_simd(P, FAST, EQ)))) void render_batch_kernel(BatchDev b) {
-  const int t = uniform_i(b.tile_order[blockIdx.x]);
-  const int r = uniform_i(batch_request(b.tile_base, b.nreq, t));
-  brick_render<P, STORE, SHADE, FAST, EQ, LPR>(b.args[r], t - b.tile_base[r]);
-}
-
-// ---------------------------------------------------------------------------
-// tile order: counting sort of the tiles by decreasing estimated work
-// ---------------------------------------------------------------------------
-
-constexpr int kBuckets = 512;
-
-// Bucket of a work estimate (8 samples per bucket), largest work first.
-__device__ __forceinline__ int cost_rank(int c) { return kBuckets - 1 - min(c >> 3, kBuckets - 1); }
-
-// XCD group of super-tile t of a frame nsx super-tiles wide: square regions
-// of region x region super-tiles are dealt to the groups in a skewed
-// pattern, so that each group's regions are spread over the image.
-__device__ __forceinline__ int xcd_group(int t, int nsx, int region) {
-  const int sx = t % nsx, sy = t / nsx;
-  return ((sx / region) + 3 * (sy / region)) & (kXcdGroups - 1);
-}
-
-// Clear G x kBuckets counters and mark every launch slot empty.
-__global__ __launch_bounds__(256) void plan_zero_kernel(unsigned* hist, int nhist, int* order,
-                                                        int nslots) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < nhist) hist[i] = 0u;
-  if (i < nslots) order[i] = -1;
-}
-
-// Work estimate of every super-tile (2x2 tiles of tile_w x tile_h pixels):
-// the largest sample count among nine rays (corners, edge midpoints and
-// centre of its pixel rectangle).
-__device__ __forceinline__ int supertile_cost(const RenderArgsDev& a, int t) {
-  const int ntx = (a.width + a.tile_w - 1) / a.tile_w;
-  const int nsx = (ntx + 1) >> 1;
-  const int x0 = (t % nsx) * 2 * a.tile_w, y0 = (t / nsx) * 2 * a.tile_h;
-  const int x1 = min(x0 + 2 * a.tile_w - 1, a.width - 1);
-  const int y1 = min(y0 + 2 * a.tile_h - 1, a.height - 1);
-  const int xm = (x0 + x1) >> 1, ym = (y0 + y1) >> 1;
-  int c = 0;
-  c = max(c, make_ray(a.cam, y0, x0).nr);
-  c = max(c, make_ray(a.cam, y0, xm).nr);
-  c = max(c, make_ray(a.cam, y0, x1).nr);
-  c = max(c, make_ray(a.cam, ym, x0).nr);
-  c = max(c, make_ray(a.cam, ym, xm).nr);
-  c = max(c, make_ray(a.cam, ym, x1).nr);
-  c = max(c, make_ray(a.cam, y1, x0).nr);
-  c = max(c, make_ray(a.cam, y1, xm).nr);
-  c = max(c, make_ray(a.cam, y1, x1).nr);
-  return c;
-}
-
-// Single frame: work estimates and the per-group bucket histogram.
-__global__ __launch_bounds__(256) void plan_cost_kernel(RenderArgsDev a) {
-  __shared__ unsigned h[kXcdGroups * kBuckets];
-  const int tid = threadIdx.x;
-  for (int i = tid; i < kXcdGroups * kBuckets; i += 256) h[i] = 0u;
-  __syncthreads();
-  const int t = blockIdx.x * 256 + tid;
-  if (t < a.ntiles) {
-    const int c = supertile_cost(a, t);
-    a.tile_cost[t] = c;
-    atomicAdd(&h[xcd_group(t, a.nsx, a.region) * kBuckets + cost_rank(c)], 1u);
-  }
-  __syncthreads();
-  for (int i = tid; i < kXcdGroups * kBuckets; i += 256)
-    if (h[i] != 0u) atomicAdd(&a.tile_hist[i], h[i]);
-}
-
-// Exclusive prefix sum of each group's bucket histogram (one workgroup per
-// group).
-__global__ __launch_bounds__(kBuckets) void plan_scan_kernel(unsigned* hist) {
-  __shared__ unsigned v[kBuckets];
-  const int tid = threadIdx.x;
-  unsigned* h = hist + blockIdx.x * kBuckets;
-  const unsigned own = h[tid];
-  v[tid] = own;
-  __syncthreads();
-  for (int off = 1; off < kBuckets; off <<= 1) {
-    const unsigned add = tid >= off ? v[tid - off] : 0u;
-    __syncthreads();
-    v[tid] += add;
-    __syncthreads();
-  }
-  h[tid] = v[tid] - own;
-}
-
-// Launch order.  Within its group a super-tile's position follows its
-// bucket (every workgroup reserves one range per bucket it holds tiles of,
-// so positions are unique; the order within a bucket is arbitrary and
-// changes no pixel); slot position * G + group then puts the k-th longest
-// super-tile of group g at workgroup index 8 k + g.  G = 1 for batches.
-template <int G>
-__global__ __launch_bounds__(256) void plan_scatter_kernel(const int* cost, int n, int nsx,
-                                                           int region, unsigned* base,
-                                                           int* order) {
-  __shared__ unsigned cnt[G * kBuckets];
-  __shared__ unsigned off[G * kBuckets];
-  const int tid = threadIdx.x;
-  for (int i = tid; i < G * kBuckets; i += 256) cnt[i] = 0u;
-  __syncthreads();
-  const int t = blockIdx.x * 256 + tid;
-  int key = 0, g = 0;
-  unsigned local = 0u;
-  if (t < n) {
-    g = G == 1 ? 0 : xcd_group(t, nsx, region);
-    key = g * kBuckets + cost_rank(cost[t]);
-    local = atomicAdd(&cnt[key], 1u);
-  }
-  __syncthreads();
-  for (int i = tid; i < G * kBuckets; i += 256)
-    if (cnt[i] != 0u) off[i] = atomicAdd(&base[i], cnt[i]);
-  __syncthreads();
-  if (t < n) order[(int)(off[key] + local) * G + g] = t;
-}
-
-// Batch class: clear the bucket counters and every request's sample
-// counter (one workgroup).
-__global__ __launch_bounds__(256) void batch_zero_kernel(BatchDev b) {
-  for (int i = threadIdx.x; i < kBuckets; i += 256) b.tile_hist[i] = 0u;
-  for (int r = threadIdx.x; r < b.nreq; r += 256)
-    if (b.args[r].samples != nullptr) *b.args[r].samples = 0ull;
-}
-
-// Batch class: work estimate of every super-tile of every request, and the
-// bucket histogram.
-__global__ __launch_bounds__(256) void batch_cost_kernel(BatchDev b) {
-  __shared__ unsigned h[kBuckets];
-  const int tid = threadIdx.x;
-  for (int i = tid; i < kBuckets; i += 256) h[i] = 0u;
-  __syncthreads();
-  const int t = blockIdx.x * 256 + tid;
-  if (t < b.ntiles) {
-    const int r = batch_request(b.tile_base, b.nreq, t);
-    const int c = supertile_cost(b.args[r], t - b.tile_base[r]);
-    b.tile_cost[t] = c;
-    atomicAdd(&h[cost_rank(c)], 1u);
-  }
-  __syncthreads();
-  for (int i = tid; i < kBuckets; i += 256)
-    if (h[i] != 0u) atomicAdd(&b.tile_hist[i], h[i]);
-}
-
-template <int P, int STORE, bool GRAD>
-__global__ __launch_bounds__(256) void eval_kernel(EvalArgsDev a) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= a.n) return;
-  const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.m.ctrl, a.m.ctrl_bytes);
-  double u[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const double x = a.xyz[3 * i + k];
-    const double v = (x - a.m.ax[k].lo) * a.m.ax[k].inv_ext;
-    u[k] = fmin(fmax(v, 0.0), 1.0);
-  }
-  int span[3];
-  float f, g[3];
-  query<P, STORE, GRAD>(a.m, rs, u, span, true, f, g);
-  a.value[i] = f;
-  if (GRAD) {
-    a.grad[3 * i + 0] = g[0];
-    a.grad[3 * i + 1] = g[1];
-    a.grad[3 * i + 2] = g[2];
-  }
-}
-
-__global__ void zero_counter(unsigned long long* p) {
-  if (threadIdx.x == 0) p[0] = 0ull;
-}
-
-// Events recorded around the ray-casting kernel alone (not the planning).
-hipError_t mark(hipEvent_t ev, hipStream_t st) {
-  return ev == nullptr ? hipSuccess : hipEventRecord(ev, st);
-}
-
-template <int P, int STORE, bool SHADE, bool FAST, bool EQ>
-hipError_t launch_brick(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
-  const unsigned blocks = (unsigned)((a.ntiles + 255) / 256);
-  const int nhist = kXcdGroups * kBuckets;
-  const unsigned zblocks = (unsigned)((max(a.nslots, nhist) + 255) / 256);
-  plan_zero_kernel<<<zblocks, 256, 0, st>>>(a.tile_hist, nhist, a.tile_order, a.nslots);
-  plan_cost_kernel<<<blocks, 256, 0, st>>>(a);
-  plan_scan_kernel<<<kXcdGroups, kBuckets, 0, st>>>(a.tile_hist);
-  plan_scatter_kernel<kXcdGroups>
-      <<<blocks, 256, 0, st>>>(a.tile_cost, a.ntiles, a.nsx, a.region, a.tile_hist, a.tile_order);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = mark(ev.begin, st);
-  if (e != hipSuccess) return e;
-  render_brick_kernel<P, STORE, SHADE, FAST, EQ, kLanesPerRay><<<a.nslots, 256, a.lds_bytes, st>>>(a);
-  e = hipGetLastError();
-  return e == hipSuccess ? mark(ev.end, st) : e;
-}
-
-template <int P, int STORE, bool SHADE>
-hipError_t launch_render_ps(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
-  if (a.lds_bytes > 0) {
-    // EQ: every axis has the kernel's degree P (degree known at compile time)
-    const bool eq = a.eq != 0;
-    if constexpr (P >= 2) {
-      if (a.fast)
-        return eq ? launch_brick<P, STORE, SHADE, true, true>(a, st, ev)
-                  : launch_brick<P, STORE, SHADE, true, false>(a, st, ev);
-    }
-    return eq ? launch_brick<P, STORE, SHADE, false, true>(a, st, ev)
-              : launch_brick<P, STORE, SHADE, false, false>(a, st, ev);
-  }
-  hipError_t e = mark(ev.begin, st);
-  if (e != hipSuccess) return e;
-  const dim3 grid((a.width + 15) / 16, (a.height + 15) / 16);
-  render_global_kernel<P, STORE, SHADE><<<grid, 256, 0, st>>>(a);
-  e = hipGetLastError();
-  return e == hipSuccess ? mark(ev.end, st) : e;
-}
-
-template <int P, int STORE, bool SHADE, bool FAST, bool EQ>
-hipError_t launch_batch_class(const BatchDev& b, int lds_bytes, hipStream_t st) {
-  const unsigned blocks = (unsigned)((b.ntiles + 255) / 256);
-  batch_zero_kernel<<<1, 256, 0, st>>>(b);
-  batch_cost_kernel<<<blocks, 256, 0, st>>>(b);
-  plan_scan_kernel<<<1, kBuckets, 0, st>>>(b.tile_hist);
-  plan_scatter_kernel<1>
-      <<<blocks, 256, 0, st>>>(b.tile_cost, b.ntiles, 1, 1, b.tile_hist, b.tile_order);
-  render_batch_kernel<P, STORE, SHADE, FAST, EQ, kLanesPerRay><<<b.ntiles, 256, lds_bytes, st>>>(b);
-  return hipGetLastError();
-}
-
-template <int P, int STORE, bool SHADE>
-hipError_t batch_ps(const BatchDev& b, const BatchKey& k, hipStream_t st) {
-  if constexpr (P >= 2) {
-    if (k.fast)
-      return k.eq ? launch_batch_class<P, STORE, SHADE, true, true>(b, k.lds_bytes, st)
-                  : launch_batch_class<P, STORE, SHADE, true, false>(b, k.lds_bytes, st);
-  }
-  return k.eq ? launch_batch_class<P, STORE, SHADE, false, true>(b, k.lds_bytes, st)
-              : launch_batch_class<P, STORE, SHADE, false, false>(b, k.lds_bytes, st);
-}
-
-template <int P, int STORE>
-hipError_t batch_p(const BatchDev& b, const BatchKey& k, hipStream_t st) {
-  return k.shading ? batch_ps<P, STORE, true>(b, k, st) : batch_ps<P, STORE, false>(b, k, st);
-}
-
-template <int STORE>
-hipError_t batch_store(const BatchDev& b, const BatchKey& k, hipStream_t st) {
-  switch (k.pmax) {
-    case 1: return batch_p<1, STORE>(b, k, st);
-    case 2: return batch_p<2, STORE>(b, k, st);
-    case 3: return batch_p<3, STORE>(b, k, st);
-    case 4: return batch_p<4, STORE>(b, k, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int P, int STORE>
-hipError_t launch_render_p(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
-  return a.shading ? launch_render_ps<P, STORE, true>(a, st, ev)
-                   : launch_render_ps<P, STORE, false>(a, st, ev);
-}
-
-template <int P, int STORE>
-hipError_t launch_eval_p(const EvalArgsDev& a, hipStream_t st) {
-  const unsigned blocks = (unsigned)((a.n + 255) / 256);
-  if (a.grad)
-    eval_kernel<P, STORE, true><<<blocks, 256, 0, st>>>(a);
-  else
-    eval_kernel<P, STORE, false><<<blocks, 256, 0, st>>>(a);
-  return hipGetLastError();
-}
-
-template <int STORE>
-hipError_t dispatch_render(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
-  switch (a.m.pmax) {
-    case 1: return launch_render_p<1, STORE>(a, st, ev);
-    case 2: return launch_render_p<2, STORE>(a, st, ev);
-    case 3: return launch_render_p<3, STORE>(a, st, ev);
-    case 4: return launch_render_p<4, STORE>(a, st, ev);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int STORE>
-hipError_t dispatch_eval(const EvalArgsDev& a, hipStream_t st) {
-  switch (a.m.pmax) {
-    case 1: return launch_eval_p<1, STORE>(a, st);
-    case 2: return launch_eval_p<2, STORE>(a, st);
-    case 3: return launch_eval_p<3, STORE>(a, st);
-    case 4: return launch_eval_p<4, STORE>(a, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-}  // namespace
+extern template hipError_t render_for_store<0>(const RenderArgsDev&, hipStream_t,
+                                               const KernelEvents&);
+extern template hipError_t render_for_store<1>(const RenderArgsDev&, hipStream_t,
+                                               const KernelEvents&);
+extern template hipError_t render_for_store<2>(const RenderArgsDev&, hipStream_t,
+                                               const KernelEvents&);
+extern template hipError_t batch_for_store<0>(const BatchDev&, const BatchKey&, hipStream_t);
+extern template hipError_t batch_for_store<1>(const BatchDev&, const BatchKey&, hipStream_t);
+extern template hipError_t batch_for_store<2>(const BatchDev&, const BatchKey&, hipStream_t);
+extern template hipError_t eval_for_store<0>(const EvalArgsDev&, hipStream_t);
+extern template hipError_t eval_for_store<1>(const EvalArgsDev&, hipStream_t);
+extern template hipError_t eval_for_store<2>(const EvalArgsDev&, hipStream_t);
 
 hipError_t launch_render(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
   if (a.samples != nullptr) {
@@ -1442,17 +26,32 @@ hipError_t launch_render(const RenderArgsDev& a, hipStream_t st, const KernelEve
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return a.m.store == 0 ? dispatch_render<0>(a, st, ev) : dispatch_render<1>(a, st, ev);
+  switch (a.m.store) {
+    case 0: return render_for_store<0>(a, st, ev);
+    case 1: return render_for_store<1>(a, st, ev);
+    case 2: return render_for_store<2>(a, st, ev);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_render_batch(const BatchDev& b, const BatchKey& k, hipStream_t st) {
   if (b.ntiles <= 0) return hipSuccess;
-  return k.store == 0 ? batch_store<0>(b, k, st) : batch_store<1>(b, k, st);
+  switch (k.store) {
+    case 0: return batch_for_store<0>(b, k, st);
+    case 1: return batch_for_store<1>(b, k, st);
+    case 2: return batch_for_store<2>(b, k, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_eval(const EvalArgsDev& a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
-  return a.m.store == 0 ? dispatch_eval<0>(a, st) : dispatch_eval<1>(a, st);
+  switch (a.m.store) {
+    case 0: return eval_for_store<0>(a, st);
+    case 1: return eval_for_store<1>(a, st);
+    case 2: return eval_for_store<2>(a, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace mfa

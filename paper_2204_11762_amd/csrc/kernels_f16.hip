@@ -1,0 +1,11 @@
+// Kernel variants for FP16 control-point storage.
+
+#include "kernels_impl.h"
+
+namespace mfa {
+
+template hipError_t render_for_store<2>(const RenderArgsDev&, hipStream_t, const KernelEvents&);
+template hipError_t batch_for_store<2>(const BatchDev&, const BatchKey&, hipStream_t);
+template hipError_t eval_for_store<2>(const EvalArgsDev&, hipStream_t);
+
+}  // namespace mfa

@@ -70,7 +70,7 @@ struct ModelDev {
   AxisDev ax[3];
   const void* ctrl;     // n0*n1*n2 control points, x fastest
   uint32_t ctrl_bytes;  // size of ctrl in bytes (< 2^31)
-  int32_t store;        // 0 FP32, 1 BF16
+  int32_t store;        // 0 FP32, 1 BF16, 2 FP16
   int32_t nx;           // row stride (elements)
   int32_t nxy;          // slice stride (elements)
   int32_t pmax;         // largest degree; kernels are instantiated for it

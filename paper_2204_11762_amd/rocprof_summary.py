@@ -98,7 +98,7 @@ def per_leg(rows: list[dict]) -> dict:
         m = RENDER_RE.search(r["Kernel_Name"])
         if not m:
             continue
-        store = "bf16" if m.group(2) == "1" else "fp32"
+        store = {"0": "fp32", "1": "bf16", "2": "fp16"}[m.group(2)]
         legs.setdefault(store, []).append(float(r["Counter_Value"]))
         names[store] = short_name(r["Kernel_Name"])
     return {k: {"kernel": names[k], "dispatches": len(v), "kib_median": statistics.median(v),

@@ -95,6 +95,21 @@ def test_model_validation_errors(b, name):
     assert e.value.message
 
 
+def test_f16_range_and_unknown_storage(b):
+    spec = wl.c1().model
+    big = wl.ModelSpec(spec.degree, spec.knots, np.full((16, 16, 16), 65519.0))
+    b.mfa_validate_model(big, b.MFA_STORE_F16)          # rounds to 65504: accepted
+    b.mfa_validate_model(big, b.MFA_STORE_BF16)
+    over = wl.ModelSpec(spec.degree, spec.knots, np.full((16, 16, 16), -65520.0))
+    with pytest.raises(b.MFAError) as e:
+        b.mfa_validate_model(over, b.MFA_STORE_F16)     # rounds to -inf in binary16
+    assert e.value.status == b.MFA_ERR_MODEL
+    b.mfa_validate_model(over, b.MFA_STORE_BF16)
+    with pytest.raises(b.MFAError) as e:
+        b.mfa_validate_model(spec, 3)
+    assert e.value.status == b.MFA_ERR_MODEL
+
+
 def test_wrong_knot_length_and_null_pointers(b):
     spec = wl.c1().model
     d, keep = b.model_desc(spec)

@@ -4,7 +4,7 @@ FP64 oracle, through the C ABI."""
 import numpy as np
 import pytest
 
-from gpu_helpers import BF16_REL, FP32_REL, gpu_eval, normwise
+from gpu_helpers import BF16_REL, F16_REL, FP32_REL, gpu_eval, normwise
 from helpers import oracle_model
 from oracle import bspline as ob
 from oracle import quant
@@ -66,7 +66,7 @@ RANDOM_CASES = [
 
 
 @pytest.mark.parametrize("case", range(len(RANDOM_CASES)))
-@pytest.mark.parametrize("store", [0, 1])
+@pytest.mark.parametrize("store", [0, 1, 2])
 def test_eval_random_models(mfa, case, store):
     n, deg, beta, lo, hi = RANDOM_CASES[case]
     spec = wl.random_model(np.random.default_rng(100 + case), n=n, degree=deg,
@@ -74,11 +74,11 @@ def test_eval_random_models(mfa, case, store):
     if store == 0:
         _check(mfa, spec, 0, case, FP32_REL, FP32_REL)
     else:
-        # against the canonical FP64 model: storage error within the BF16 bound
-        _check(mfa, spec, 1, case, BF16_REL, None)
+        bound, deq = (BF16_REL, quant.dequant_bf16) if store == 1 else (F16_REL, quant.dequant_f16)
+        # against the canonical FP64 model: storage error within the storage bound
+        _check(mfa, spec, store, case, bound, None)
         # against the de-quantised model: arithmetic error only, FP32 bound
-        _check(mfa, spec, 1, case, FP32_REL, FP32_REL,
-               ref_ctrl=quant.dequant_bf16(spec.ctrl))
+        _check(mfa, spec, store, case, FP32_REL, FP32_REL, ref_ctrl=deq(spec.ctrl))
 
 
 def test_eval_c1_model(mfa):
@@ -101,6 +101,11 @@ def test_eval_c3_model_fp32(mfa, c3_model):
 def test_eval_c3_model_bf16(mfa, c3_model):
     ev, eg = _check(mfa, c3_model, 1, 4, BF16_REL, None)
     _check(mfa, c3_model, 1, 4, FP32_REL, FP32_REL, ref_ctrl=quant.dequant_bf16(c3_model.ctrl))
+
+
+def test_eval_c3_model_f16(mfa, c3_model):
+    _check(mfa, c3_model, 2, 5, F16_REL, None)
+    _check(mfa, c3_model, 2, 5, FP32_REL, FP32_REL, ref_ctrl=quant.dequant_f16(c3_model.ctrl))
 
 
 def test_eval_zero_points_is_noop(mfa):

@@ -8,7 +8,7 @@ import copy
 import numpy as np
 import pytest
 
-from gpu_helpers import (BF16_REL, BF16_RMSE, FP32_REL, FP32_RMSE, compare_image, gpu_eval,
+from gpu_helpers import (BF16_REL, BF16_RMSE, F16_RMSE, FP32_REL, FP32_RMSE, compare_image, gpu_eval,
                          gpu_render, normwise)
 from helpers import oracle_workload, oracle_model
 from oracle import bspline as ob
@@ -69,7 +69,7 @@ SMALL = [
 
 
 @pytest.mark.parametrize("case", range(len(SMALL)))
-@pytest.mark.parametrize("store", [0, 1])
+@pytest.mark.parametrize("store", [0, 1, 2])
 def test_small_full_frames(mfa, case, store):
     seed, n, deg, beta, lo, hi, (W, H), kind, shade, ert, head = SMALL[case]
     rng = np.random.default_rng(seed)
@@ -97,15 +97,17 @@ def test_small_full_frames(mfa, case, store):
             assert rep.rmse <= FP32_RMSE and rep.n_bad == 0
             _check_counts(rep, True)
         else:
+            name = "bf16" if store == 1 else "f16"
+            deq = quant.dequant_bf16 if store == 1 else quant.dequant_f16
             # arithmetic error only: against the de-quantised model
-            Mq = oracle_model(spec, ctrl=quant.dequant_bf16(spec.ctrl))
+            Mq = oracle_model(spec, ctrl=deq(spec.ctrl))
             rep = compare_image(img, cnt, wk, pix, TAU32, PX32, model=Mq)
-            _report(f"small{case} bf16 vs dequantised", rep)
+            _report(f"small{case} {name} vs dequantised", rep)
             assert rep.rmse <= FP32_RMSE and rep.n_bad == 0
             # and the total error against the FP64 model
             rep = compare_image(img, cnt, wk, pix, 3e-3, 5e-2)
-            _report(f"small{case} bf16 vs fp64", rep)
-            assert rep.rmse <= BF16_RMSE
+            _report(f"small{case} {name} vs fp64", rep)
+            assert rep.rmse <= (BF16_RMSE if store == 1 else F16_RMSE)
         # misses are exactly transparent black, and nothing is left unwritten
         M, c, _, p = oracle_workload(wk)
         r, cc = np.divmod(pix, W)

@@ -284,6 +284,36 @@ def test_bf16_rounding_known_values_and_torch():
     np.testing.assert_array_equal(quant.dequant_f32(y), y.astype(np.float32).astype(np.float64))
 
 
+def test_f16_rounding_known_values_and_libraries():
+    import torch
+    one = 1.0
+    cases = {
+        one: one,
+        one + 2.0 ** -11: one,                      # tie -> even
+        one + 3 * 2.0 ** -11: one + 2.0 ** -9,      # tie -> even (upwards)
+        one + 2.0 ** -11 + 2.0 ** -20: one + 2.0 ** -10,
+        65504.0: 65504.0,                           # largest finite
+        2.0 ** -14: 2.0 ** -14,                     # smallest normal
+        2.0 ** -24: 2.0 ** -24,                     # smallest subnormal
+        2.0 ** -25: 0.0,                            # tie -> even (zero)
+        3 * 2.0 ** -26: 2.0 ** -24,
+        -2.5: -2.5,
+        0.0: 0.0,
+        1.0 / 3.0: 0.333251953125,                  # 0x3555
+    }
+    x = np.array(list(cases.keys()))
+    np.testing.assert_array_equal(quant.dequant_f16(x), np.array(list(cases.values())))
+    assert quant.f16_bits(np.array([1.0 / 3.0]))[0] == 0x3555
+    assert quant.f16_bits(np.array([-65504.0]))[0] == 0xFBFF
+    rng = np.random.default_rng(15)
+    y = np.concatenate([rng.standard_normal(100000) * 3, rng.standard_normal(20000) * 1e-5,
+                        rng.uniform(-65000, 65000, 1000)])
+    f32 = y.astype(np.float32)
+    np.testing.assert_array_equal(quant.dequant_f16(y), f32.astype(np.float16).astype(np.float64))
+    ref = torch.from_numpy(f32).to(torch.float16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(quant.dequant_f16(y), ref)
+
+
 def _golden_pieces():
     import os
     from fractions import Fraction
