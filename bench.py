@@ -138,13 +138,20 @@ def host_cpu_model() -> str:
 # GPU leg
 # ---------------------------------------------------------------------------
 
-def gpu_leg(b, ctx, wk, store: int, steps: int, warmup: int, log, nominal_frames=True):
+def gpu_leg(b, ctx, wk, store: int, steps: int, warmup: int, log, nominal_frames=True,
+            autotune=True):
     import torch
     cam = wk.camera
     h = b.mfa_model_upload(ctx, wk.model, store)
     try:
         out = torch.zeros((cam.height, cam.width, 4), dtype=torch.float32, device="cuda")
         cnt = torch.zeros((1,), dtype=torch.int64, device="cuda")
+        tune = None
+        if autotune:
+            r = b.mfa_autotune(ctx, h, cam, wk.tf, wk.params, out, repeats=10)
+            tune = {"round_spans": r.round_spans, "best_ms": r.best_ms, "default_ms": r.default_ms}
+            log(f"autotune: {r.round_spans} spans per round ({r.best_ms:.4f} ms; "
+                f"default {r.default_ms:.4f} ms)")
         b.mfa_render(ctx, h, cam, wk.tf, wk.params, out, cnt)
         torch.cuda.synchronize()
         samples = int(cnt.item())
@@ -193,6 +200,7 @@ def gpu_leg(b, ctx, wk, store: int, steps: int, warmup: int, log, nominal_frames
             f"{wall / steps * 1e3:.3f} ms/frame wall, frame p50 {np.median(lat):.3f} ms, "
             f"render kernel mean {kern.mean():.4f} ms")
         return {"samples": samples, "nominal": nominal, "wall": wall, "lat": lat, "kern": kern,
+                "tune": tune,
                 "nominal_ms": nominal_ms, "image": image,
                 "model_bytes": b.mfa_model_bytes(ctx, h)}
     finally:
@@ -468,6 +476,19 @@ def main():
             if name in args.legs.split(","):
                 legs[name] = gpu_leg(b, ctx, wk, store, args.steps, args.warmup, log,
                                      nominal_frames=not args.no_nominal)
+        value_only = None
+        if "bf16" in legs:
+            # the same frame without shading: value queries only, no gradient
+            wk_v = copy.copy(wk)
+            wk_v.params = copy.copy(wk.params)
+            wk_v.params.shading = False
+            vleg = gpu_leg(b, ctx, wk_v, 1, max(20, args.steps // 4), 5, log, nominal_frames=False)
+            value_only = {"store": "bf16", "shading": False,
+                          "samples_per_frame": vleg["samples"],
+                          "samples_per_s": vleg["samples"] / (float(vleg["kern"].mean()) * 1e-3),
+                          "kernel_mean_ms": float(vleg["kern"].mean()),
+                          "note": "value only (no gradient, no Phong); a different frame, since "
+                                  "unshaded colours change where rays terminate"}
         evals = None
         if args.eval_steps > 0:
             evals = eval_leg(b, ctx, wk, args.eval_steps, log)
@@ -498,6 +519,7 @@ def main():
                 "p50_ms": float(np.percentile(leg["lat"], 50)),
                 "p99_ms": float(np.percentile(leg["lat"], 99)),
                 "kernel_mean_ms": float(leg["kern"].mean()),
+                "autotune": leg["tune"],
                 "nominal_samples_per_frame": leg["nominal"],
                 "nominal_samples_per_s": (None if leg["nominal"] is None
                                           else leg["nominal"] / (leg["nominal_ms"] * 1e-3)),
@@ -534,6 +556,8 @@ def main():
                      "flops_per_launch": flops},
         "legs": {k: summary(v, k) for k, v in legs.items()},
     }
+    if value_only is not None:
+        line["value_only"] = value_only
     if evals is not None:
         line["eval"] = evals
     if batch is not None:

@@ -217,6 +217,31 @@ mfa_status mfa_batch_render(mfa_ctx* ctx, int64_t batch, void* stream);
  * MFA_ERR_DEVICE. */
 mfa_status mfa_batch_free(mfa_ctx* ctx, int64_t batch);
 
+/* Result of mfa_autotune. */
+typedef struct mfa_tune_result {
+  float round_spans; /* chosen round length: knot spans along the fastest axis per lane */
+  int32_t candidates; /* configurations timed */
+  float best_ms;      /* median kernel time of the chosen configuration */
+  float default_ms;   /* median kernel time of the default (3 spans) */
+} mfa_tune_result;
+
+/* Autotuner of the ray caster for one model: renders the given request
+ * (into rgba_dev, which it overwrites) with each candidate round length
+ * (1.5, 2, 3, 4 and 6 knot spans per lane's round of samples; a round's
+ * control points are staged in LDS once), one warm-up and `repeats` timed
+ * launches each, all candidates interleaved and enqueued back to back on
+ * `stream` (the call returns after synchronising it), and keeps the length
+ * with the smallest median kernel time for every later render of the model
+ * (single frames, batches prepared afterwards, servers).  The tile shape
+ * (4x4 pixels, four lanes per ray) and the LDS budget are fixed by the
+ * kernels' occupancy.  Results of later renders change only by rounding
+ * (the FP32 sample stepping restarts from FP64 at each round).  out may be
+ * null.  Errors: MFA_ERR_HANDLE, MFA_ERR_INVALID (the request, or repeats
+ * outside [1, 1000]), MFA_ERR_DEVICE. */
+mfa_status mfa_autotune(mfa_ctx* ctx, int64_t model, const mfa_camera* camera, const mfa_tf* tf,
+                        const mfa_render_params* params, float* rgba_dev, int32_t repeats,
+                        void* stream, mfa_tune_result* out);
+
 /* ----------------------------------------------------------------------
  * Serving: a render server with continuous batching.
  *

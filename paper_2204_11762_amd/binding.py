@@ -35,7 +35,8 @@ MFA_CAMERA_PERSP = 1
 
 EXPORTED = ("mfa_create", "mfa_destroy", "mfa_set_memory_budget", "mfa_model_upload",
             "mfa_model_free", "mfa_model_bytes", "mfa_render", "mfa_eval_points",
-            "mfa_kernel_timing", "mfa_kernel_times", "mfa_batch_create", "mfa_batch_render",
+            "mfa_kernel_timing", "mfa_kernel_times", "mfa_autotune", "mfa_batch_create",
+            "mfa_batch_render",
             "mfa_batch_free", "mfa_server_create", "mfa_server_submit", "mfa_server_wait",
             "mfa_server_destroy", "mfa_validate_model",
             "mfa_validate_render", "mfa_last_error", "mfa_version")
@@ -79,6 +80,11 @@ class RenderRequest(C.Structure):
                 ("samples_dev", C.c_void_p)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("round_spans", C.c_float), ("candidates", C.c_int32), ("best_ms", C.c_float),
+                ("default_ms", C.c_float)]
+
+
 class ServerConfig(C.Structure):
     _fields_ = [("streams", C.c_int32), ("max_batch", C.c_int32), ("max_bytes", C.c_int64)]
 
@@ -107,6 +113,8 @@ def _load():
                             vp, vp, vp]),
         "mfa_eval_points": (st, [vp, i64, i64, vp, vp, vp, vp]),
         "mfa_kernel_timing": (st, [vp, C.c_int32]),
+        "mfa_autotune": (st, [vp, i64, C.POINTER(Camera), C.POINTER(TF), C.POINTER(RenderParams),
+                              vp, C.c_int32, vp, C.POINTER(TuneResult)]),
         "mfa_batch_create": (st, [vp, C.POINTER(RenderRequest), C.c_int32, C.POINTER(i64)]),
         "mfa_batch_render": (st, [vp, i64, vp]),
         "mfa_batch_free": (st, [vp, i64]),
@@ -293,6 +301,19 @@ def mfa_render(ctx: int, model: int, camera, tf, params, rgba, samples=None, str
     t, keep = tf_struct(tf)
     _check(lib.mfa_render(ctx, int(model), C.byref(camera_struct(camera)), C.byref(t),
                           C.byref(params_struct(params)), out, sp, _stream_ptr(stream)))
+
+
+def mfa_autotune(ctx: int, model: int, camera, tf, params, rgba, repeats: int = 5, stream=None):
+    """Tune the model's round length on one request (rgba is overwritten);
+    returns the TuneResult."""
+    import torch
+    out = _dev_tensor(rgba, torch.float32, (camera.height, camera.width, 4), "rgba")
+    t, keep = tf_struct(tf)
+    res = TuneResult()
+    _check(lib.mfa_autotune(ctx, int(model), C.byref(camera_struct(camera)), C.byref(t),
+                            C.byref(params_struct(params)), out, int(repeats), _stream_ptr(stream),
+                            C.byref(res)))
+    return res
 
 
 def mfa_batch_create(ctx: int, requests) -> int:

@@ -42,6 +42,9 @@ constexpr int kMaxImageSide = 1 << 15;
 constexpr int64_t kMaxEvalPoints = int64_t(1) << 38;
 // Requests of one render batch.
 constexpr int32_t kMaxBatch = 1 << 16;
+// Round lengths (knot spans along the fastest axis per lane's round) that
+// mfa_autotune times; 3 is the default.
+constexpr double kTuneRoundSpans[] = {1.5, 2.0, 3.0, 4.0, 6.0};
 constexpr size_t kMaxCachedTF = 64;
 // Render launches whose kernel duration one timing record holds.
 constexpr size_t kMaxTimedLaunches = 1 << 16;
@@ -319,6 +322,7 @@ struct DeviceModel {
   double lo[3], hi[3];
   int64_t nknots[3];
   int64_t batch_refs = 0;  // live batches that render this model
+  double round_spans = 3.0;  // knot spans along the fastest axis per lane's round (tunable)
 };
 
 // LDS plan of the brick ray caster for one request: transfer function,
@@ -350,13 +354,13 @@ void plan_bricks(const DeviceModel& dm, int ntf, double step, mfa::RenderArgsDev
   a.lds_bricks = tf_bytes + knot_bytes;
   a.brick_cap = cap;
   a.lds_bytes = tf_bytes + knot_bytes + 4 * cap * 4;
-  // about three knot spans along the worst axis per round
+  // about round_spans knot spans along the worst axis per lane's round
   double cells = 0.0;
   for (int k = 0; k < 3; ++k) {
     const double span_len = (dm.hi[k] - dm.lo[k]) / dm.md.ax[k].m;
     cells = std::max(cells, step / span_len);
   }
-  const int spr = cells > 0.0 ? int(3.0 * mfa::kLanesPerRay / cells) : 64;
+  const int spr = cells > 0.0 ? int(dm.round_spans * mfa::kLanesPerRay / cells) : 64;
   a.spr = std::max(4, std::min(64, spr));
 }
 
@@ -1009,6 +1013,94 @@ mfa_status mfa_kernel_times(mfa_ctx* ctx, float* ms_host, int64_t cap, int64_t* 
   }
   *count = int64_t(n);
   ctx->timed = 0;
+  return MFA_OK;
+}
+
+mfa_status mfa_autotune(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const mfa_tf* tf,
+                        const mfa_render_params* prm, float* rgba_dev, int32_t repeats,
+                        void* stream, mfa_tune_result* out) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  auto it = ctx->models.find(model);
+  if (it == ctx->models.end()) return fail(MFA_ERR_HANDLE, "unknown model handle");
+  if (repeats < 1 || repeats > 1000) return fail(MFA_ERR_INVALID, "repeats must be in [1, 1000]");
+  DeviceModel& dm = it->second;
+  mfa_status st = check_request(dm, cam, tf, prm, rgba_dev);
+  if (st != MFA_OK) return st;
+  DeviceGuard g(ctx->device);
+  if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
+  float4* tf_dev = nullptr;
+  st = tf_device(ctx, tf, &tf_dev);
+  if (st != MFA_OK) return st;
+  const hipStream_t hs = static_cast<hipStream_t>(stream);
+  // one launch record per candidate; launches of all candidates are
+  // interleaved (round robin) and enqueued back to back, with events around
+  // each ray-casting kernel, and the stream is synchronised once
+  constexpr int kCand = int(sizeof(kTuneRoundSpans) / sizeof(kTuneRoundSpans[0]));
+  const double saved = dm.round_spans;
+  std::vector<mfa::RenderArgsDev> args(kCand);
+  int64_t slots = 0;
+  for (int c = 0; c < kCand; ++c) {
+    dm.round_spans = kTuneRoundSpans[c];
+    build_render_args(dm, cam, tf, prm, rgba_dev, nullptr, tf_dev, args[c]);
+    slots = std::max<int64_t>(slots, args[c].nslots);
+  }
+  dm.round_spans = saved;
+  if (args[0].ntiles > 0) {
+    st = ensure_scratch(ctx, slots);
+    if (st != MFA_OK) return st;
+    int32_t* base = static_cast<int32_t*>(ctx->scratch);
+    for (auto& a : args) {
+      a.tile_cost = base;
+      a.tile_order = base + ctx->scratch_tiles;
+      a.tile_hist = reinterpret_cast<unsigned*>(base + 2 * ctx->scratch_tiles);
+    }
+  }
+  const int total = kCand * (repeats + 1);
+  std::vector<mfa::KernelEvents> evs(total);
+  hipError_t e = hipSuccess;
+  int made = 0;
+  for (; made < total && e == hipSuccess; ++made) {
+    e = hipEventCreate(&evs[made].begin);
+    if (e == hipSuccess) {
+      e = hipEventCreate(&evs[made].end);
+      if (e != hipSuccess) (void)hipEventDestroy(evs[made].begin);
+    }
+  }
+  if (e != hipSuccess) --made;
+  for (int r = 0, k = 0; r <= repeats && e == hipSuccess; ++r)   // round 0: warm-up
+    for (int c = 0; c < kCand && e == hipSuccess; ++c, ++k) e = mfa::launch_render(args[c], hs, evs[k]);
+  if (e == hipSuccess) e = hipStreamSynchronize(hs);
+  double best = saved, best_ms = 1e30, default_ms = 0.0;
+  for (int c = 0; c < kCand && e == hipSuccess; ++c) {
+    std::vector<float> ms;
+    for (int r = 1; r <= repeats && e == hipSuccess; ++r) {
+      float t = 0.0f;
+      e = hipEventElapsedTime(&t, evs[r * kCand + c].begin, evs[r * kCand + c].end);
+      ms.push_back(t);
+    }
+    if (e != hipSuccess) break;
+    std::sort(ms.begin(), ms.end());
+    const double med = ms[ms.size() / 2];
+    if (kTuneRoundSpans[c] == 3.0) default_ms = med;
+    if (med < best_ms) {
+      best_ms = med;
+      best = kTuneRoundSpans[c];
+    }
+  }
+  for (int i = 0; i < made; ++i) {
+    (void)hipEventDestroy(evs[i].begin);
+    (void)hipEventDestroy(evs[i].end);
+  }
+  if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("autotune launch", e));
+  const int32_t tried = kCand;
+  dm.round_spans = best;
+  if (out != nullptr) {
+    out->round_spans = float(best);
+    out->candidates = tried;
+    out->best_ms = float(best_ms);
+    out->default_ms = float(default_ms);
+  }
   return MFA_OK;
 }
 

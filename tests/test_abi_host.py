@@ -188,6 +188,7 @@ def test_null_context_and_handles(b):
     assert b.lib.mfa_batch_create(None, None, 1, C.byref(bh)) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_batch_render(None, 1, None) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_batch_free(None, 1) == b.MFA_ERR_HANDLE
+    assert b.lib.mfa_autotune(None, 1, None, None, None, None, 1, None, None) == b.MFA_ERR_HANDLE
     sh = C.c_void_p()
     assert b.lib.mfa_server_create(None, None, C.byref(sh)) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_server_submit(None, None, C.byref(bh)) == b.MFA_ERR_HANDLE

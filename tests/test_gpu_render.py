@@ -173,6 +173,36 @@ def test_kernel_timing(mfa):
         b.mfa_model_free(ctx, h)
 
 
+def test_autotune_keeps_parity(mfa):
+    """The autotuner picks one of its candidate round lengths, never one
+    slower than the default it timed, and renders after tuning still match
+    the oracle."""
+    import torch
+    b, ctx = mfa
+    wk = wl.c2()
+    wk.camera.width = wk.camera.height = 256
+    h = b.mfa_model_upload(ctx, wk.model, 1)
+    try:
+        scratch = torch.zeros((256, 256, 4), dtype=torch.float32, device="cuda")
+        res = b.mfa_autotune(ctx, h, wk.camera, wk.tf, wk.params, scratch, repeats=3)
+        print(f"\n  tuned round spans {res.round_spans}, {res.candidates} candidates, "
+              f"best {res.best_ms:.4f} ms, default {res.default_ms:.4f} ms")
+        assert res.candidates == 5
+        assert res.round_spans in (1.5, 2.0, 3.0, 4.0, 6.0)
+        assert 0 < res.best_ms <= res.default_ms
+        img, cnt = gpu_render(b, ctx, h, wk)
+        pix = wl.pixel_subset(256, 256, 1500, seed=8)
+        Mq = oracle_model(wk.model, ctrl=quant.dequant_bf16(wk.model.ctrl))
+        rep = compare_image(img, cnt, wk, pix, TAU32, PX32, model=Mq, count_exact=False)
+        _report("autotuned c2 256^2 bf16", rep)
+        assert rep.rmse <= FP32_RMSE and rep.n_bad == 0
+        with pytest.raises(b.MFAError) as ei:
+            b.mfa_autotune(ctx, h, wk.camera, wk.tf, wk.params, scratch, repeats=0)
+        assert ei.value.status == b.MFA_ERR_INVALID
+    finally:
+        b.mfa_model_free(ctx, h)
+
+
 def test_camera_inside_volume(mfa):
     b, ctx = mfa
     wk = wl.c2()
