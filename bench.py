@@ -397,6 +397,59 @@ def eval_leg(b, ctx, wk, steps: int, log, n_points: int = 1 << 24):
     return out
 
 
+def fields_leg(b, ctx, log, n_points: int = 1 << 22):
+    """Sect. 4 shaped measurements on the Gaussian beam (Eq. 1) sampled on a
+    128^3 grid: (i) point-query time against the number of control points
+    and the degree (least-squares fits, n in {32, 64, 128}, p in 1..4);
+    (ii) a 1000 x 1000 render of the fit with control points = data size and
+    degree 2."""
+    import torch
+    data = wl.field_grid(wl.gaussian_beam, 128)
+    rng = np.random.default_rng(17)
+    xyz = torch.from_numpy(np.ascontiguousarray(
+        wl.uniform_points(rng, n_points, wl.FIELD_LO, wl.FIELD_HI))).cuda()
+    v = torch.empty(n_points, dtype=torch.float32, device="cuda")
+    g = torch.empty((n_points, 3), dtype=torch.float32, device="cuda")
+    sweep = []
+    for n in (32, 64, 128):
+        for p in (1, 2, 3, 4):
+            spec = wl.fit_grid(data, n, p)
+            h = b.mfa_model_upload(ctx, spec)
+            try:
+                b.mfa_eval_points(ctx, h, xyz, v, g)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(5):
+                    b.mfa_eval_points(ctx, h, xyz, v, g)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / 5
+            finally:
+                b.mfa_model_free(ctx, h)
+            sweep.append({"n": n, "p": p, "ns_per_query": ms * 1e6 / n_points,
+                          "queries_per_s": n_points / (ms * 1e-3)})
+    log("eval sweep (ns per value+gradient query): " + ", ".join(
+        f"n{r['n']}p{r['p']} {r['ns_per_query']:.3f}" for r in sweep))
+    # paper-shaped render: control points = data size, degree 2, 1000 x 1000
+    spec = wl.fit_grid(data, 128, 2)
+    e = np.arange(256) / 255.0
+    table = np.stack([np.ones(256), np.zeros(256), np.zeros(256), 0.08 * e], axis=1)
+    wk = wl.Workload("gaussian-beam", spec,
+                     wl.orbit_camera(1000, 1000, 30.0, 20.0, radius=3.5, target=(0.0, 0.0, 0.0)),
+                     wl.TFSpec(table.astype(np.float32), 0.0, 255.0), wl.ParamSpec(step=2.0 / 256))
+    leg = gpu_leg(b, ctx, wk, 0, 50, 5, log, nominal_frames=False, autotune=False)
+    render = {"workload": "Gaussian beam (Eq. 1) 128^3 samples, least-squares MFA with 128^3 "
+                          "control points, degree 2, FP32; 1000x1000 perspective, step 1/128 of "
+                          "the box, ramp opacity, Phong",
+              "samples_per_frame": leg["samples"],
+              "ms_per_frame": leg["wall"] / 50 * 1e3,
+              "kernel_mean_ms": float(leg["kern"].mean()),
+              "samples_per_s": leg["samples"] / (float(leg["kern"].mean()) * 1e-3)}
+    return {"eval_sweep": sweep, "paper_shaped_render": render, "points": n_points}
+
+
 def rmse_on(image, base):
     if base is None:
         return None
@@ -430,6 +483,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="duration of the served request stream (0 = skip it)")
     ap.add_argument("--serve-rate", type=float, default=400.0, help="requests per second")
+    ap.add_argument("--no-fields", action="store_true",
+                    help="skip the closed-form field measurements")
     ap.add_argument("--eval-steps", type=int, default=10,
                     help="timed repetitions of the point-query micro-benchmark (0 = skip it)")
     args = ap.parse_args()
@@ -492,6 +547,7 @@ def main():
         evals = None
         if args.eval_steps > 0:
             evals = eval_leg(b, ctx, wk, args.eval_steps, log)
+        fields = None if args.no_fields else fields_leg(b, ctx, log)
         batch = None
         if args.batch_steps > 0:
             batch = batch_leg(b, ctx, args.batch_steps, 2, log)
@@ -560,6 +616,8 @@ def main():
         line["value_only"] = value_only
     if evals is not None:
         line["eval"] = evals
+    if fields is not None:
+        line["fields"] = fields
     if batch is not None:
         line["batch"] = batch
     if serve is not None:

@@ -215,8 +215,13 @@ class RenderResult:
 
 def render_pixels(model: Model, cam: Camera, tf: TransferFunction, prm: RenderParams,
                   pix: np.ndarray, o_max: float | None = None,
-                  chunk: int = 4096) -> RenderResult:
-    """Render the pixels with flat indices ``pix`` (row-major, row 0 top)."""
+                  chunk: int = 4096, field=None) -> RenderResult:
+    """Render the pixels with flat indices ``pix`` (row-major, row 0 top).
+
+    ``field``, if given, replaces the MFA by a closed-form field: a callable
+    taking world points (k, 3) and returning the values (k,) and world
+    gradients (k, 3); the model then only supplies the box.  Used to render
+    the ground truth of the closed-form test fields."""
     pix = np.asarray(pix, dtype=np.int64)
     m = len(pix)
     rgba = np.zeros((m, 4))
@@ -226,12 +231,12 @@ def render_pixels(model: Model, cam: Camera, tf: TransferFunction, prm: RenderPa
     omax = prm.ert_alpha if o_max is None else o_max
     for c0 in range(0, m, chunk):
         sl = slice(c0, min(m, c0 + chunk))
-        res = _render_chunk(model, cam, tf, prm, pix[sl], omax)
+        res = _render_chunk(model, cam, tf, prm, pix[sl], omax, field)
         rgba[sl], used[sl], nom[sl], near[sl] = res
     return RenderResult(rgba, used, nom, near)
 
 
-def _render_chunk(model, cam, tf, prm, pix, omax):
+def _render_chunk(model, cam, tf, prm, pix, omax, field=None):
     W = cam.width
     rows = pix // W
     cols = pix % W
@@ -259,11 +264,14 @@ def _render_chunk(model, cam, tf, prm, pix, omax):
         t = t0[idx] + (s + 0.5) * prm.step
         x = o[idx] + t[:, None] * d[idx]
         uvw = np.clip((x - lo) / ext, 0.0, 1.0)
-        f, df = eval_local(model, uvw)
+        if field is None:
+            f, df = eval_local(model, uvw)
+            g = df / ext
+        else:
+            f, g = field(lo + uvw * ext)
         col = tf_lookup(tf, f)
         rgb, alpha = col[:, :3], col[:, 3]
         if prm.shading:
-            g = df / ext
             light = np.broadcast_to(lvec, g.shape)
             rgb = phong(rgb, g, light, -d[idx], prm)
         w = (1.0 - A[idx]) * alpha

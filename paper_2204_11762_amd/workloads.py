@@ -401,6 +401,83 @@ def serve_config(seed: int = 41, rate: float = 400.0, duration_s: float = 2.0):
     return models, reqs, arrivals
 
 
+# ---------------------------------------------------------------------------
+# the paper's closed-form fields (Sect. 4.1.1) on the box [-1, 1]^3
+# ---------------------------------------------------------------------------
+
+FIELD_LO = (-1.0, -1.0, -1.0)
+FIELD_HI = (1.0, 1.0, 1.0)
+
+
+def gaussian_beam(x, y, z, v_min=0.0, v_max=255.0, mu=0.0, sigma=1.0 / 3.0, radius=math.sqrt(3.0)):
+    """Eq. (1): V_min + (V_max - V_min) G(|r| / R), G(l) = exp(-(l - mu)^2 / (2 sigma^2)).
+    Returns (value, gradient (..., 3))."""
+    x, y, z = (np.asarray(t, dtype=np.float64) for t in (x, y, z))
+    r = np.sqrt(x * x + y * y + z * z)
+    l = r / radius
+    G = np.exp(-(l - mu) ** 2 / (2.0 * sigma ** 2))
+    f = v_min + (v_max - v_min) * G
+    # dG/dl = -(l - mu) / sigma^2 G; dl/dx_k = x_k / (R r)  (mu = 0: smooth at r = 0)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        dl = np.where(r > 0, 1.0 / (radius * r), 0.0)
+    dGdl = -(l - mu) / sigma ** 2 * G
+    if mu == 0.0:
+        fac = (v_max - v_min) * (-G / (sigma ** 2 * radius ** 2))   # d/dx_k = fac x_k
+        g = np.stack([fac * x, fac * y, fac * z], axis=-1)
+    else:
+        g = np.stack([(v_max - v_min) * dGdl * dl * t for t in (x, y, z)], axis=-1)
+    return f, g
+
+
+def marschner_lobb(x, y, z, f_m=6.0, alpha=0.25):
+    """Eq. (2): (1 - sin(pi z / 2) + alpha (1 + rho(sqrt(x^2 + y^2)))) / (2 (1 + alpha)),
+    rho(r) = cos(2 pi f_M cos(pi r / 2)).  Returns (value, gradient (..., 3))."""
+    x, y, z = (np.asarray(t, dtype=np.float64) for t in (x, y, z))
+    r = np.sqrt(x * x + y * y)
+    inner = 2.0 * np.pi * f_m * np.cos(np.pi * r / 2.0)
+    rho = np.cos(inner)
+    den = 2.0 * (1.0 + alpha)
+    f = (1.0 - np.sin(np.pi * z / 2.0) + alpha * (1.0 + rho)) / den
+    # drho/dr = sin(inner) 2 pi f_M sin(pi r / 2) pi / 2; dr/dx = x / r
+    drho_dr = np.sin(inner) * 2.0 * np.pi * f_m * np.sin(np.pi * r / 2.0) * (np.pi / 2.0)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        q = np.where(r > 0, drho_dr / r, 0.0)   # drho_dr ~ r near 0: limit is finite
+    small = r < 1e-12
+    if np.any(small):
+        # drho/dr / r -> 2 pi f_M sin(2 pi f_M) (pi / 2)^2 as r -> 0
+        q = np.where(small, 2.0 * np.pi * f_m * np.sin(2.0 * np.pi * f_m) * (np.pi / 2.0) ** 2, q)
+    gx = alpha * q * x / den
+    gy = alpha * q * y / den
+    gz = -(np.pi / 2.0) * np.cos(np.pi * z / 2.0) / den
+    return f, np.stack([gx, gy, gz * np.ones_like(gx)], axis=-1)
+
+
+def field_grid(field, N: int) -> np.ndarray:
+    """The discrete dataset: the field at N^3 equally spaced points of
+    [-1, 1]^3, shape (N, N, N) indexed (z, y, x)."""
+    t = np.linspace(-1.0, 1.0, N)
+    zz, yy, xx = np.meshgrid(t, t, t, indexing="ij")
+    return field(xx, yy, zz)[0]
+
+
+def fit_grid(data: np.ndarray, n: int, p: int) -> ModelSpec:
+    """Least-squares MFA of an (N, N, N) grid dataset on [-1, 1]^3 with n
+    control points of degree p per axis on clamped uniform knots: the
+    tensor-product least-squares solution, applied one axis at a time (the
+    pseudo-inverse of a Kronecker product is the Kronecker product of the
+    pseudo-inverses).  Input preparation standing in for the MFA encoder."""
+    from scipy.interpolate import BSpline
+    N = data.shape[0]
+    U = clamped_uniform_knots(n, p)
+    sites = np.linspace(0.0, 1.0, N)
+    B = BSpline.design_matrix(sites, U, p).toarray()
+    Bp = np.linalg.pinv(B)                      # (n, N)
+    P = np.einsum("az,zyx->ayx", Bp, data)
+    P = np.einsum("by,ayx->abx", Bp, P)
+    P = np.einsum("cx,abx->abc", Bp, P)
+    return ModelSpec((p, p, p), (U, U.copy(), U.copy()), P, FIELD_LO, FIELD_HI)
+
+
 def pixel_subset(width: int, height: int, size: int, seed: int) -> np.ndarray:
     return np.sort(np.random.default_rng(seed).choice(width * height, size=size,
                                                       replace=False))

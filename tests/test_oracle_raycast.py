@@ -250,3 +250,17 @@ def test_c1_workload_facts():
     res = orc.render_pixels(M, cam, tf, prm, np.arange(0, 128 * 128, 97))
     assert (res.n_nominal == 256).all()
     assert (res.samples >= 1).all() and (res.samples < 256).all()
+
+
+def test_field_callback_reproduces_model_path():
+    """A closed-form field given as a callback is rendered by the same
+    steps: passing the model's own world evaluation as the field gives the
+    default image exactly."""
+    from oracle import bspline as ob
+    wk = wl.c1()
+    M, cam, tf, prm = oracle_workload(wk)
+    pix = np.arange(0, 128 * 128, 37)
+    ref = orc.render_pixels(M, cam, tf, prm, pix)
+    got = orc.render_pixels(M, cam, tf, prm, pix, field=lambda xyz: ob.eval_world(M, xyz))
+    np.testing.assert_allclose(got.rgba, ref.rgba, rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(got.samples, ref.samples)
