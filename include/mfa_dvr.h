@@ -61,7 +61,13 @@ typedef int32_t mfa_status;
  * non-decreasing and clamped (p+1 zeros first, p+1 ones last; interior
  * knots in (0,1) with multiplicity <= p).  Control points are FP64, finite,
  * x fastest: P[i,j,k] = ctrl[i + n0*(j + n1*k)].  The model maps the box
- * [lo, hi] (lo < hi per axis) affinely onto the unit parameter cube. */
+ * [lo, hi] (lo < hi per axis) affinely onto the unit parameter cube.
+ * With `weights` (finite, > 0, same layout) the model is rational: the
+ * field is sum N N N w P / sum N N N w, its gradient by the quotient rule;
+ * the device stores the homogeneous values w*P and w in the storage
+ * precision.  Rational models are rendered by the global-memory ray caster
+ * (the brick kernels are non-rational only).  Without weights (null) every
+ * weight is 1, which is how the paper uses the method. */
 typedef struct mfa_model_desc {
   int32_t degree[3];
   int32_t store; /* MFA_STORE_F32, MFA_STORE_BF16 or MFA_STORE_F16 */
@@ -70,6 +76,7 @@ typedef struct mfa_model_desc {
   const double* ctrl;
   double lo[3];
   double hi[3];
+  const double* weights; /* nullable: rational weights, n0*n1*n2 FP64 > 0, layout of ctrl */
 } mfa_model_desc;
 
 /* Fixed-point ray-cast camera (Sect. 3.1): one ray through the centre of

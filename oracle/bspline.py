@@ -6,8 +6,11 @@ bases: per axis a degree ``p`` and a clamped, non-decreasing knot vector
 paper's renderer queries the value and the first derivatives in all three
 directions at arbitrary points of the normalised domain (Sect. 3.1,
 Algorithm 1: value query and gradient query; the three derivatives are
-obtained together).  The paper uses non-rational models in all experiments
-and never states weights, so every weight is 1 here.
+obtained together).  The paper names rational B-splines but states no
+weights and uses non-rational models in its experiments: a model without
+weights is non-rational; with weights ``w_ijk > 0`` the field is the
+rational quotient ``f = sum N N N w P / sum N N N w`` and its gradient
+follows from the quotient rule.
 
 Definitions used (textbook B-splines; Cox--de Boor, de Boor):
 
@@ -21,7 +24,9 @@ Definitions used (textbook B-splines; Cox--de Boor, de Boor):
   denominator being 0;
 * ``N'_{i,p} = p/(U_{i+p}-U_i) N_{i,p-1} - p/(U_{i+p+1}-U_{i+1}) N_{i+1,p-1}``;
 * value ``f(u,v,w) = sum_{ijk} N_i(u) N_j(v) N_k(w) P_{ijk}``, and each
-  partial derivative is the same sum with one factor differentiated.
+  partial derivative is the same sum with one factor differentiated;
+* rational: numerator ``A = sum N N N w P`` and denominator
+  ``D = sum N N N w`` as above, ``f = A / D``, ``grad f = (grad A - f grad D) / D``.
 
 Control points are stored x-fastest: ``ctrl[k, j, i] = P_{ijk}``.
 
@@ -42,13 +47,15 @@ import numpy as np
 
 @dataclass
 class Model:
-    """A non-rational tensor-product B-spline volume over a box."""
+    """A tensor-product B-spline volume over a box (rational when weights
+    are given)."""
 
     degree: tuple            # (p_x, p_y, p_z)
     knots: tuple             # three float64 arrays, len n_k + p_k + 1
     ctrl: np.ndarray         # float64, shape (n_z, n_y, n_x), x fastest
     lo: np.ndarray           # float64 (3,), domain box corner
     hi: np.ndarray           # float64 (3,)
+    weights: np.ndarray | None = None   # float64 like ctrl, > 0; None: all 1
 
     @property
     def n(self):
@@ -210,17 +217,25 @@ def eval_local(model: Model, uvw: np.ndarray):
     iy = (sy - py)[:, None] + b[None, :]
     iz = (sz - pz)[:, None] + c[None, :]
     # block[m, c, b, a] = P[iz, iy, ix]
-    block = model.ctrl[iz[:, :, None, None], iy[:, None, :, None], ix[:, None, None, :]]
+    sel = (iz[:, :, None, None], iy[:, None, :, None], ix[:, None, None, :])
+    block = model.ctrl[sel]
 
-    def contract(wx, wy, wz):
+    def contract(wx, wy, wz, blk):
         w = wz[:, :, None, None] * wy[:, None, :, None] * wx[:, None, None, :]
-        return (w * block).sum(axis=(1, 2, 3))
+        return (w * blk).sum(axis=(1, 2, 3))
 
-    f = contract(Nx, Ny, Nz)
-    fu = contract(dNx, Ny, Nz)
-    fv = contract(Nx, dNy, Nz)
-    fw = contract(Nx, Ny, dNz)
-    return f, np.stack([fu, fv, fw], axis=-1)
+    def value_and_grad(blk):
+        return (contract(Nx, Ny, Nz, blk),
+                np.stack([contract(dNx, Ny, Nz, blk), contract(Nx, dNy, Nz, blk),
+                          contract(Nx, Ny, dNz, blk)], axis=-1))
+
+    if model.weights is None:
+        return value_and_grad(block)
+    wblock = model.weights[sel]
+    A, dA = value_and_grad(wblock * block)
+    D, dD = value_and_grad(wblock)
+    f = A / D
+    return f, (dA - f[:, None] * dD) / D[:, None]
 
 
 def eval_full(model: Model, uvw: np.ndarray):
@@ -241,17 +256,23 @@ def eval_full(model: Model, uvw: np.ndarray):
         Dx = [dbasis_full(i, px, Ux, u) for i in range(nx)]
         Dy = [dbasis_full(j, py, Uy, v) for j in range(ny)]
         Dz = [dbasis_full(k, pz, Uz, w) for k in range(nz)]
-        f = fu = fv = fw = 0.0
+        acc = np.zeros((2, 4))              # rows: numerator, denominator
         for k in range(nz):
             for j in range(ny):
                 for i in range(nx):
-                    P = float(model.ctrl[k, j, i])
-                    f += Bx[i] * By[j] * Bz[k] * P
-                    fu += Dx[i] * By[j] * Bz[k] * P
-                    fv += Bx[i] * Dy[j] * Bz[k] * P
-                    fw += Bx[i] * By[j] * Dz[k] * P
-        out_f[m] = f
-        out_g[m] = (fu, fv, fw)
+                    w = 1.0 if model.weights is None else float(model.weights[k, j, i])
+                    terms = (Bx[i] * By[j] * Bz[k], Dx[i] * By[j] * Bz[k],
+                             Bx[i] * Dy[j] * Bz[k], Bx[i] * By[j] * Dz[k])
+                    for r, t in enumerate(terms):
+                        acc[0, r] += t * w * float(model.ctrl[k, j, i])
+                        acc[1, r] += t * w
+        if model.weights is None:
+            out_f[m] = acc[0, 0]
+            out_g[m] = acc[0, 1:]
+        else:
+            f = acc[0, 0] / acc[1, 0]
+            out_f[m] = f
+            out_g[m] = (acc[0, 1:] - f * acc[1, 1:]) / acc[1, 0]
     return out_f, out_g
 
 
@@ -263,6 +284,8 @@ def grad_hodograph(model: Model, uvw: np.ndarray) -> np.ndarray:
     control points ``Q_i = p (P_{i+1} - P_i) / (U_{i+p+1} - U_{i+1})``.
     """
     uvw = np.atleast_2d(np.asarray(uvw, dtype=np.float64))
+    if model.weights is not None:
+        raise ValueError("grad_hodograph: non-rational models only")
     out = np.zeros((len(uvw), 3))
     for axis in range(3):
         p = model.degree[axis]

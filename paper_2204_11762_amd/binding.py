@@ -52,7 +52,8 @@ class MFAError(RuntimeError):
 class ModelDesc(C.Structure):
     _fields_ = [("degree", C.c_int32 * 3), ("store", C.c_int32), ("n_ctrl", C.c_int64 * 3),
                 ("knots", C.POINTER(C.c_double) * 3), ("ctrl", C.POINTER(C.c_double)),
-                ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("weights", C.POINTER(C.c_double))]
 
 
 class Camera(C.Structure):
@@ -182,6 +183,12 @@ def model_desc(spec, store: int = MFA_STORE_F32, keep: _Keep | None = None) -> t
         d.hi[k] = float(spec.hi[k])
     d.n_ctrl[0], d.n_ctrl[1], d.n_ctrl[2] = nx, ny, nz
     d.ctrl = keep.f64(ctrl.reshape(-1))
+    w = getattr(spec, "weights", None)
+    if w is not None:
+        w = np.asarray(w, dtype=np.float64)
+        if w.shape != ctrl.shape:
+            raise ValueError("weights must have the shape of ctrl")
+        d.weights = keep.f64(w.reshape(-1))
     d.store = int(store)
     return d, keep
 

@@ -138,16 +138,35 @@ mfa_status validate_model(const mfa_model_desc* d, std::string& msg) {
     return MFA_ERR_INVALID;
   }
   const int64_t total = nx * ny * nz;
-  for (int64_t i = 0; i < total; ++i) {
-    const double v = d->ctrl[i];
+  // stored values: P, or w*P and w for a rational model
+  auto storable = [&](double v, const char* what) {
     if (!std::isfinite(v) || !std::isfinite(float(v))) {
-      msg = "control points must be finite and within FP32 range";
-      return MFA_ERR_MODEL;
+      msg = std::string(what) + " must be finite and within FP32 range";
+      return false;
     }
     // binary16: float values of magnitude >= 65520 round to infinity
     if (d->store == MFA_STORE_F16 && std::fabs(float(v)) >= 65520.0f) {
-      msg = "control points must lie within the FP16 range (|x| < 65520)";
-      return MFA_ERR_MODEL;
+      msg = std::string(what) + " must lie within the FP16 range (|x| < 65520)";
+      return false;
+    }
+    return true;
+  };
+  for (int64_t i = 0; i < total; ++i) {
+    if (!storable(d->ctrl[i], "control points")) return MFA_ERR_MODEL;
+    if (d->weights != nullptr) {
+      const double w = d->weights[i];
+      if (!(std::isfinite(w) && w > 0.0)) {
+        msg = "rational weights must be finite and positive";
+        return MFA_ERR_MODEL;
+      }
+      // the weight must stay positive after rounding to the storage precision
+      if (!storable(w, "rational weights") || !storable(w * d->ctrl[i], "weighted control points"))
+        return MFA_ERR_MODEL;
+      if (float(w) < FLT_MIN || (d->store == MFA_STORE_F16 && w < 6.2e-5) ||
+          (d->store == MFA_STORE_BF16 && w < 1.2e-38)) {
+        msg = "rational weights too small for the storage precision";
+        return MFA_ERR_MODEL;
+      }
     }
   }
   return MFA_OK;
@@ -594,7 +613,9 @@ mfa_status mfa_model_upload(mfa_ctx* ctx, const mfa_model_desc* d, int64_t* mode
   }
   const size_t off_ctrl = off;
   const size_t ctrl_bytes = elem * size_t(total + kCtrlPadElems);
-  const size_t bytes = align256(off_ctrl + ctrl_bytes);
+  const bool rational = d->weights != nullptr;
+  const size_t off_w = align256(off_ctrl + ctrl_bytes);
+  const size_t bytes = rational ? align256(off_w + ctrl_bytes) : off_w;
 
   if (ctx->budget > 0 && ctx->used + int64_t(bytes) > ctx->budget)
     return fail(MFA_ERR_NOMEM, "model exceeds the context's memory budget");
@@ -606,13 +627,22 @@ mfa_status mfa_model_upload(mfa_ctx* ctx, const mfa_model_desc* d, int64_t* mode
     build_table(d->knots[k], n[k], d->degree[k],
                 reinterpret_cast<float*>(host.data() + off_tab[k]));
   }
-  if (d->store == MFA_STORE_F32) {
-    float* c = reinterpret_cast<float*>(host.data() + off_ctrl);
-    for (int64_t i = 0; i < total; ++i) c[i] = float(d->ctrl[i]);
+  // stored plane(s): P, or w*P (homogeneous numerator) and w
+  auto store_plane = [&](size_t off_plane, auto value) {
+    if (d->store == MFA_STORE_F32) {
+      float* c = reinterpret_cast<float*>(host.data() + off_plane);
+      for (int64_t i = 0; i < total; ++i) c[i] = float(value(i));
+    } else {
+      uint16_t* c = reinterpret_cast<uint16_t*>(host.data() + off_plane);
+      for (int64_t i = 0; i < total; ++i)
+        c[i] = d->store == MFA_STORE_BF16 ? to_bf16(value(i)) : to_f16(value(i));
+    }
+  };
+  if (rational) {
+    store_plane(off_ctrl, [&](int64_t i) { return d->weights[i] * d->ctrl[i]; });
+    store_plane(off_w, [&](int64_t i) { return d->weights[i]; });
   } else {
-    uint16_t* c = reinterpret_cast<uint16_t*>(host.data() + off_ctrl);
-    for (int64_t i = 0; i < total; ++i)
-      c[i] = d->store == MFA_STORE_BF16 ? to_bf16(d->ctrl[i]) : to_f16(d->ctrl[i]);
+    store_plane(off_ctrl, [&](int64_t i) { return d->ctrl[i]; });
   }
 
   DeviceGuard g(ctx->device);
@@ -658,6 +688,9 @@ mfa_status mfa_model_upload(mfa_ctx* ctx, const mfa_model_desc* d, int64_t* mode
   dm.md.uniform = uniform;
   dm.md.ctrl = base + off_ctrl;
   dm.md.ctrl_bytes = uint32_t(ctrl_bytes);
+  dm.md.rational = rational ? 1 : 0;
+  dm.md.wctrl = rational ? base + off_w : nullptr;
+  dm.md.wctrl_bytes = rational ? uint32_t(ctrl_bytes) : 0u;
   dm.md.store = d->store;
   dm.md.nx = int32_t(n[0]);
   dm.md.nxy = int32_t(n[0] * n[1]);
@@ -772,6 +805,12 @@ void build_render_args(const DeviceModel& dm, const mfa_camera* cam, const mfa_t
   a.fast = dm.md.uniform && dm.md.ax[0].p >= 2 && dm.md.ax[1].p >= 2 && dm.md.ax[2].p >= 2;
   a.eq = dm.md.ax[0].p == dm.md.pmax && dm.md.ax[1].p == dm.md.pmax && dm.md.ax[2].p == dm.md.pmax;
   plan_bricks(dm, tf->n, prm->step, a);
+  if (dm.md.rational) {
+    // the brick kernels are non-rational: rational models use the global kernel
+    a.lds_bytes = 0;
+    a.spr = 0;
+    a.brick_cap = 0;
+  }
   a.tile_w = mfa::kTileW;
   a.tile_h = mfa::kTileH;
   a.ntiles = 0;

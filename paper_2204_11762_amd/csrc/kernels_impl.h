@@ -384,11 +384,13 @@ __device__ __forceinline__ void contract(const float (&N)[3][P + 1], const float
 
 // Value f and world-space gradient g at parameters u (each in [0,1]).
 // span[] carries the spans between calls along one ray; first = true
-// locates them from scratch.
-template <int P, int STORE, bool GRAD>
+// locates them from scratch.  RAT: rs holds w*P and rsw holds w; the value
+// is the quotient of the two contractions and the gradient follows from the
+// quotient rule, (grad A - f grad D) / D.
+template <int P, int STORE, bool GRAD, bool RAT>
 __device__ __forceinline__ void query(const ModelDev& m, __amdgpu_buffer_rsrc_t rs,
-                                      const double (&u)[3], int (&span)[3], bool first, float& f,
-                                      float (&g)[3]) {
+                                      __amdgpu_buffer_rsrc_t rsw, const double (&u)[3],
+                                      int (&span)[3], bool first, float& f, float (&g)[3]) {
   float N[3][P + 1], dN[3][P + 1];
   int w[3];
 #pragma unroll
@@ -408,6 +410,21 @@ __device__ __forceinline__ void query(const ModelDev& m, __amdgpu_buffer_rsrc_t 
       N, dN,
       [&](int b, int c, float (&row)[P + 1]) { load_row<P, STORE>(rs, e0 + b * nx + c * nxy, row); },
       f, g);
+  if constexpr (RAT) {
+    float d, gd[3];
+    contract<P, GRAD>(
+        N, dN,
+        [&](int b, int c, float (&row)[P + 1]) {
+          load_row<P, STORE>(rsw, e0 + b * nx + c * nxy, row);
+        },
+        d, gd);
+    const float inv = 1.0f / d;
+    f *= inv;
+    if (GRAD) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) g[k] = (g[k] - f * gd[k]) * inv;
+    }
+  }
   if (GRAD) {
     g[0] *= m.ax[0].gscale;
     g[1] *= m.ax[1].gscale;
@@ -608,7 +625,7 @@ __device__ __forceinline__ void count_samples(const RenderArgsDev& a, int count,
 
 // Used when the knots or transfer function of a request do not fit the LDS
 // budget of the brick kernel.
-template <int P, int STORE, bool SHADE>
+template <int P, int STORE, bool SHADE, bool RAT>
 __global__ __launch_bounds__(256) void render_global_kernel(RenderArgsDev a) {
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
@@ -619,6 +636,8 @@ __global__ __launch_bounds__(256) void render_global_kernel(RenderArgsDev a) {
   int count = 0;
   if (inside) {
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.m.ctrl, a.m.ctrl_bytes);
+    const __amdgpu_buffer_rsrc_t rsw = make_rsrc(RAT ? a.m.wctrl : a.m.ctrl,
+                                                 RAT ? a.m.wctrl_bytes : a.m.ctrl_bytes);
     const Ray ray = make_ray(a.cam, py, px);
     float cr = 0.0f, cg = 0.0f, cb = 0.0f, A = 0.0f;
     const float vx = -(float)ray.d[0], vy = -(float)ray.d[1], vz = -(float)ray.d[2];
@@ -629,7 +648,7 @@ __global__ __launch_bounds__(256) void render_global_kernel(RenderArgsDev a) {
       double u[3];
       sample_params(a.cam, ray, s, u);
       float f, g[3];
-      query<P, STORE, SHADE>(a.m, rs, u, span, s == 0, f, g);
+      query<P, STORE, SHADE, RAT>(a.m, rs, rsw, u, span, s == 0, f, g);
       ++count;
       if (!shade_composite<SHADE>(a, f, g, vx, vy, vz, tf, cr, cg, cb, A)) break;
     }
@@ -1302,11 +1321,13 @@ __global__ __launch_bounds__(256) void batch_cost_kernel(BatchDev b) {
     if (h[i] != 0u) atomicAdd(&b.tile_hist[i], h[i]);
 }
 
-template <int P, int STORE, bool GRAD>
+template <int P, int STORE, bool GRAD, bool RAT>
 __global__ __launch_bounds__(256) void eval_kernel(EvalArgsDev a) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= a.n) return;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.m.ctrl, a.m.ctrl_bytes);
+  const __amdgpu_buffer_rsrc_t rsw = make_rsrc(RAT ? a.m.wctrl : a.m.ctrl,
+                                               RAT ? a.m.wctrl_bytes : a.m.ctrl_bytes);
   double u[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -1316,7 +1337,7 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgsDev a) {
   }
   int span[3];
   float f, g[3];
-  query<P, STORE, GRAD>(a.m, rs, u, span, true, f, g);
+  query<P, STORE, GRAD, RAT>(a.m, rs, rsw, u, span, true, f, g);
   a.value[i] = f;
   if (GRAD) {
     a.grad[3 * i + 0] = g[0];
@@ -1368,7 +1389,10 @@ hipError_t launch_render_ps(const RenderArgsDev& a, hipStream_t st, const Kernel
   hipError_t e = mark(ev.begin, st);
   if (e != hipSuccess) return e;
   const dim3 grid((a.width + 15) / 16, (a.height + 15) / 16);
-  render_global_kernel<P, STORE, SHADE><<<grid, 256, 0, st>>>(a);
+  if (a.m.rational)
+    render_global_kernel<P, STORE, SHADE, true><<<grid, 256, 0, st>>>(a);
+  else
+    render_global_kernel<P, STORE, SHADE, false><<<grid, 256, 0, st>>>(a);
   e = hipGetLastError();
   return e == hipSuccess ? mark(ev.end, st) : e;
 }
@@ -1422,9 +1446,11 @@ template <int P, int STORE>
 hipError_t launch_eval_p(const EvalArgsDev& a, hipStream_t st) {
   const unsigned blocks = (unsigned)((a.n + 255) / 256);
   if (a.grad)
-    eval_kernel<P, STORE, true><<<blocks, 256, 0, st>>>(a);
+    a.m.rational ? eval_kernel<P, STORE, true, true><<<blocks, 256, 0, st>>>(a)
+                 : eval_kernel<P, STORE, true, false><<<blocks, 256, 0, st>>>(a);
   else
-    eval_kernel<P, STORE, false><<<blocks, 256, 0, st>>>(a);
+    a.m.rational ? eval_kernel<P, STORE, false, true><<<blocks, 256, 0, st>>>(a)
+                 : eval_kernel<P, STORE, false, false><<<blocks, 256, 0, st>>>(a);
   return hipGetLastError();
 }
 

@@ -75,6 +75,9 @@ struct ModelDev {
   int32_t nxy;          // slice stride (elements)
   int32_t pmax;         // largest degree; kernels are instantiated for it
   int32_t uniform;      // 1: every axis has knots U_{p+k} = k/(n-p) exactly
+  int32_t rational;     // 1: ctrl holds w*P and wctrl holds w (homogeneous values)
+  uint32_t wctrl_bytes;
+  const void* wctrl;    // rational weights in the storage precision, layout of ctrl
 };
 
 // Camera, box and step: everything the ray setup of a pixel reads.

@@ -48,6 +48,7 @@ class ModelSpec:
     ctrl: np.ndarray                   # float64 (n_z, n_y, n_x), x fastest
     lo: tuple = (0.0, 0.0, 0.0)
     hi: tuple = (1.0, 1.0, 1.0)
+    weights: np.ndarray | None = None  # rational weights like ctrl (> 0), or None
 
     @property
     def n(self):

@@ -7,9 +7,13 @@ from oracle import raycast as orc
 
 
 def oracle_model(spec, ctrl=None):
+    """Oracle model of a spec; with ``ctrl`` given (de-quantised values) the
+    caller sets the matching weights of a rational model."""
+    w = getattr(spec, "weights", None)
     return ob.Model(tuple(spec.degree), tuple(np.asarray(k, dtype=np.float64) for k in spec.knots),
                     np.asarray(spec.ctrl if ctrl is None else ctrl, dtype=np.float64),
-                    np.asarray(spec.lo, dtype=np.float64), np.asarray(spec.hi, dtype=np.float64))
+                    np.asarray(spec.lo, dtype=np.float64), np.asarray(spec.hi, dtype=np.float64),
+                    weights=None if (ctrl is not None or w is None) else np.asarray(w, np.float64))
 
 
 def oracle_camera(c):

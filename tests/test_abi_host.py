@@ -95,6 +95,26 @@ def test_model_validation_errors(b, name):
     assert e.value.message
 
 
+def test_rational_weight_validation(b):
+    spec = wl.c1().model
+    ok = wl.ModelSpec(spec.degree, spec.knots, spec.ctrl,
+                      weights=np.random.default_rng(1).uniform(0.5, 2.0, spec.ctrl.shape))
+    b.mfa_validate_model(ok)
+    for bad in (0.0, -1.0, np.nan, np.inf):
+        w = np.ones(spec.ctrl.shape)
+        w[3, 4, 5] = bad
+        with pytest.raises(b.MFAError) as e:
+            b.mfa_validate_model(wl.ModelSpec(spec.degree, spec.knots, spec.ctrl, weights=w))
+        assert e.value.status == b.MFA_ERR_MODEL
+    # a weight below the FP16 normal range is refused for FP16 storage only
+    w = np.ones(spec.ctrl.shape)
+    w[0, 0, 0] = 1e-6
+    tiny = wl.ModelSpec(spec.degree, spec.knots, spec.ctrl, weights=w)
+    b.mfa_validate_model(tiny, b.MFA_STORE_BF16)
+    with pytest.raises(b.MFAError):
+        b.mfa_validate_model(tiny, b.MFA_STORE_F16)
+
+
 def test_f16_range_and_unknown_storage(b):
     spec = wl.c1().model
     big = wl.ModelSpec(spec.degree, spec.knots, np.full((16, 16, 16), 65519.0))

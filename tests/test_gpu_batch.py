@@ -155,3 +155,40 @@ def test_batch_errors(mfa):
     finally:
         for h in handles:
             b.mfa_model_free(ctx, h)
+
+
+def test_batch_config_full_size_sampled(mfa):
+    """The batching workload at full size (64 requests, 4 BF16 models with
+    Beta(2,5) knots, degrees 2/3/4/3, images up to 1024^2), rendered as one
+    batch exactly as the benchmark times it: 400 sampled pixels of one
+    request per model against the oracle on the de-quantised model."""
+    import torch
+    b, ctx = mfa
+    models, reqs = wl.batch_config()
+    handles, outs, cnts, breqs = _setup(b, ctx, models, reqs)
+    batch = None
+    try:
+        batch = b.mfa_batch_create(ctx, breqs)
+        b.mfa_batch_render(ctx, batch)
+        torch.cuda.synchronize()
+        seen = set()
+        for i, r in enumerate(reqs):
+            if r.model in seen:
+                continue
+            seen.add(r.model)
+            spec, store = models[r.model]
+            wk = _workload(models, r)
+            W, H = r.camera.width, r.camera.height
+            pix = wl.pixel_subset(W, H, 400, seed=50 + i)
+            got = outs[i].cpu().numpy().astype(np.float64)
+            Mq = oracle_model(spec, ctrl=quant.dequant_bf16(spec.ctrl))
+            rep = compare_image(got, int(cnts[i].item()), wk, pix, TAU32, PX32, model=Mq)
+            print(f"\n  request {i} ({W}x{H}, degree {spec.degree[0]}): rmse {rep.rmse:.2e} "
+                  f"ambiguous {rep.n_ambiguous}")
+            assert rep.rmse <= FP32_RMSE and rep.n_bad == 0
+        assert len(seen) == len(models)
+    finally:
+        if batch is not None:
+            b.mfa_batch_free(ctx, batch)
+        for h in handles:
+            b.mfa_model_free(ctx, h)

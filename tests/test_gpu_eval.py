@@ -108,6 +108,65 @@ def test_eval_c3_model_f16(mfa, c3_model):
     _check(mfa, c3_model, 2, 5, FP32_REL, FP32_REL, ref_ctrl=quant.dequant_f16(c3_model.ctrl))
 
 
+def _rational_case(seed, degree, n=(7, 8, 6)):
+    rng = np.random.default_rng(seed)
+    spec = wl.random_model(rng, n=n, degree=degree, beta_knots=True, lo=(-1, 0, 0),
+                           hi=(1, 2, 1))
+    spec.weights = rng.uniform(0.2, 5.0, spec.ctrl.shape)
+    return spec
+
+
+def _dequant_rational(spec, deq):
+    """The stored homogeneous values as a rational model: w*P and w each
+    rounded to the storage precision."""
+    wq = deq(spec.weights)
+    return oracle_model(spec, ctrl=deq(spec.weights * spec.ctrl) / wq), wq
+
+
+@pytest.mark.parametrize("degree", [(1, 2, 3), (3, 3, 3), (4, 2, 2)])
+@pytest.mark.parametrize("store", [0, 1, 2])
+def test_eval_rational_models(mfa, degree, store):
+    b, ctx = mfa
+    spec = _rational_case(200 + sum(degree), degree)
+    deq = {0: quant.dequant_f32, 1: quant.dequant_bf16, 2: quant.dequant_f16}[store]
+    M, wq = _dequant_rational(spec, deq)
+    M.weights = wq
+    h = b.mfa_model_upload(ctx, spec, store)
+    try:
+        xyz = _points(spec, np.random.default_rng(7))
+        f, g = gpu_eval(b, ctx, h, xyz)
+        F, G = ob.eval_world(M, xyz)
+        ev, eg = normwise(f, F), normwise(g, G)
+        print(f"\n  rational {degree} store {store}: value rel {ev:.3e}  grad rel {eg:.3e}")
+        assert ev <= FP32_REL and eg <= FP32_REL
+    finally:
+        b.mfa_model_free(ctx, h)
+
+
+def test_eval_rational_reciprocal_closed_form(mfa):
+    """Weights (1, 1, 2) and values (1, 1, 1/2) of degree 2 along x give
+    f = 1 / (1 + u^2) exactly (a closed form independent of any evaluator)."""
+    b, ctx = mfa
+    U2 = np.array([0, 0, 0, 1, 1, 1], float)
+    U1 = np.array([0, 0, 1, 1], float)
+    ctrl = np.empty((2, 2, 3))
+    ctrl[:, :, :] = [1.0, 1.0, 0.5]
+    w = np.empty((2, 2, 3))
+    w[:, :, :] = [1.0, 1.0, 2.0]
+    spec = wl.ModelSpec((2, 1, 1), (U2, U1, U1), ctrl, weights=w)
+    h = b.mfa_model_upload(ctx, spec)
+    try:
+        xyz = wl.uniform_points(np.random.default_rng(3), 4000)
+        f, g = gpu_eval(b, ctx, h, xyz)
+        u = xyz[:, 0]
+        assert normwise(f, 1.0 / (1.0 + u * u)) <= FP32_REL
+        gx = -2.0 * u / (1.0 + u * u) ** 2
+        assert np.abs(g[:, 0] - gx).max() <= FP32_REL * np.abs(gx).max()
+        assert np.abs(g[:, 1:]).max() <= 1e-6
+    finally:
+        b.mfa_model_free(ctx, h)
+
+
 def test_eval_zero_points_is_noop(mfa):
     import torch
     b, ctx = mfa

@@ -121,6 +121,34 @@ def test_small_full_frames(mfa, case, store):
         b.mfa_model_free(ctx, h)
 
 
+@pytest.mark.parametrize("store", [0, 1])
+def test_rational_full_frames(mfa, store):
+    """Rational models (random positive weights) on the global-memory ray
+    caster, full frames against the oracle on the stored homogeneous values."""
+    b, ctx = mfa
+    rng = np.random.default_rng(60 + store)
+    spec = wl.random_model(rng, n=(9, 8, 10), degree=(3, 2, 3), beta_knots=True)
+    spec.weights = rng.uniform(0.3, 3.0, spec.ctrl.shape)
+    cam = wl.orbit_camera(45, 37, 120.0, 25.0, radius=2.2)
+    P = np.asarray(spec.ctrl)
+    tf = wl.pwl_tf(9, P.min(), P.max(), alpha_max=0.15)
+    prm = wl.ParamSpec(step=1.0 / 97.0, light_dir=(0.3, -0.5, 0.8))
+    wk = wl.Workload("rational", spec, cam, tf, prm)
+    deq = quant.dequant_f32 if store == 0 else quant.dequant_bf16
+    wq = deq(spec.weights)
+    Mq = oracle_model(spec, ctrl=deq(spec.weights * spec.ctrl) / wq)
+    Mq.weights = wq
+    h = b.mfa_model_upload(ctx, spec, store)
+    try:
+        img, cnt = gpu_render(b, ctx, h, wk)
+        rep = compare_image(img, cnt, wk, np.arange(45 * 37), TAU32, PX32, model=Mq)
+        _report(f"rational store {store}", rep)
+        assert rep.rmse <= FP32_RMSE and rep.n_bad == 0
+        _check_counts(rep, True)
+    finally:
+        b.mfa_model_free(ctx, h)
+
+
 def test_determinism_and_stream(mfa):
     import torch
     b, ctx = mfa

@@ -348,3 +348,63 @@ def test_uniform_pieces_match_hand_derived_fixture():
                 N, dN = ob.basis_local(s, u, p, U)
                 assert abs(N[i] - nv) <= 1e-14, (p, j, t, i)
                 assert abs(dN[i] - m * dv) <= 1e-12, (p, j, t, i)
+
+
+def _rational_reciprocal_model():
+    """Degree 2 along x with weights (1, 1, 2) and values (1, 1, 1/2): the
+    denominator is (1-u)^2 + 2u(1-u) + 2u^2 = 1 + u^2 and the numerator
+    (1-u)^2 + 2u(1-u) + u^2 = 1, so f = 1 / (1 + u^2) exactly; constant in
+    y and z (degree 1, two control points each)."""
+    U2 = np.array([0, 0, 0, 1, 1, 1], float)
+    U1 = np.array([0, 0, 1, 1], float)
+    ctrl = np.empty((2, 2, 3))
+    ctrl[:, :, :] = [1.0, 1.0, 0.5]
+    w = np.empty((2, 2, 3))
+    w[:, :, :] = [1.0, 1.0, 2.0]
+    return ob.Model((2, 1, 1), (U2, U1, U1), ctrl, np.zeros(3), np.ones(3), weights=w)
+
+
+def test_rational_reproduces_reciprocal_quadratic():
+    M = _rational_reciprocal_model()
+    rng = np.random.default_rng(21)
+    uvw = rng.random((500, 3))
+    uvw[:5, 0] = [0.0, 1.0, 0.5, 0.25, 1e-9]
+    u = uvw[:, 0]
+    f, g = ob.eval_local(M, uvw)
+    np.testing.assert_allclose(f, 1.0 / (1.0 + u * u), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(g[:, 0], -2.0 * u / (1.0 + u * u) ** 2, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(g[:, 1:], 0.0, atol=1e-15)
+    fb, gb = ob.eval_full(M, uvw[:40])
+    np.testing.assert_allclose(fb, f[:40], atol=1e-15)
+    np.testing.assert_allclose(gb, g[:40], atol=1e-14)
+
+
+@pytest.mark.parametrize("degree", [(1, 2, 3), (3, 3, 3), (4, 2, 2)])
+def test_rational_constant_weights_and_brute_force(degree):
+    rng = np.random.default_rng(22)
+    spec = wl.random_model(rng, n=(6, 7, 5), degree=degree, beta_knots=True)
+    M0 = ob.Model(spec.degree, spec.knots, spec.ctrl, np.zeros(3), np.ones(3))
+    Mc = ob.Model(spec.degree, spec.knots, spec.ctrl, np.zeros(3), np.ones(3),
+                  weights=np.full(spec.ctrl.shape, 3.7))
+    uvw = rng.random((60, 3))
+    f0, g0 = ob.eval_local(M0, uvw)
+    fc, gc = ob.eval_local(Mc, uvw)
+    np.testing.assert_allclose(fc, f0, rtol=1e-14, atol=1e-14)
+    np.testing.assert_allclose(gc, g0, rtol=1e-13, atol=1e-13)
+    Mw = ob.Model(spec.degree, spec.knots, spec.ctrl, np.zeros(3), np.ones(3),
+                  weights=rng.uniform(0.2, 5.0, spec.ctrl.shape))
+    fl, gl = ob.eval_local(Mw, uvw)
+    fb, gb = ob.eval_full(Mw, uvw)
+    np.testing.assert_allclose(fl, fb, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(gl, gb, rtol=1e-12, atol=1e-12)
+    # the rational value is a convex combination of the control points
+    assert (fl >= spec.ctrl.min() - 1e-12).all() and (fl <= spec.ctrl.max() + 1e-12).all()
+    # central differences of the rational value
+    h = 1e-6
+    for ax in range(3):
+        e = np.zeros(3)
+        e[ax] = h
+        inner = np.clip(uvw, 2 * h, 1 - 2 * h)
+        fd = (ob.eval_local(Mw, inner + e)[0] - ob.eval_local(Mw, inner - e)[0]) / (2 * h)
+        ga = ob.eval_local(Mw, inner)[1][:, ax]
+        assert np.abs(fd - ga).max() <= 1e-6 * max(1.0, np.abs(ga).max())
