@@ -35,19 +35,27 @@ from paper_2204_11762_amd import workloads as wl  # noqa: E402
 
 METRIC = "MFA samples/s (value+grad) BF16 vs FP32 at stated err; p50/p99 frame latency"
 PEAK_FP32_VALU = 157.3e12     # MI355X FP32 vector peak (packed issue)
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2204_11762_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2204_11762_amd", "csrc")
+# every source that the device code is compiled from
+KERNEL_SOURCES = ["mfa_dev.h", "kernels_impl.h", "kernels.hip", "kernels_f32.hip",
+                  "kernels_bf16.hip", "kernels_f16.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_256cubed_traffic.json")
 
 
 def kernel_source_hash() -> str:
+    """SHA-256 over the device sources (names and contents, in a fixed order)."""
     import hashlib
-    with open(KERNEL_SOURCE, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(name.encode() + b"\0")
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def measured_traffic(store: str):
     """HBM bytes per launch of the render kernel from the committed counter
-    summary, or None if the summary was taken on a different kernel source."""
+    summary, or None if the summary was taken on different device sources."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -139,7 +147,7 @@ def host_cpu_model() -> str:
 # ---------------------------------------------------------------------------
 
 def gpu_leg(b, ctx, wk, store: int, steps: int, warmup: int, log, nominal_frames=True,
-            autotune=True):
+            autotune=False):
     import torch
     cam = wk.camera
     h = b.mfa_model_upload(ctx, wk.model, store)
@@ -483,6 +491,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="duration of the served request stream (0 = skip it)")
     ap.add_argument("--serve-rate", type=float, default=400.0, help="requests per second")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the library's autotuner on each storage leg's frame before timing")
     ap.add_argument("--no-fields", action="store_true",
                     help="skip the closed-form field measurements")
     ap.add_argument("--eval-steps", type=int, default=10,
@@ -530,14 +540,15 @@ def main():
         for name, store in (("fp32", 0), ("bf16", 1), ("fp16", 2)):
             if name in args.legs.split(","):
                 legs[name] = gpu_leg(b, ctx, wk, store, args.steps, args.warmup, log,
-                                     nominal_frames=not args.no_nominal)
+                                     nominal_frames=not args.no_nominal, autotune=args.autotune)
         value_only = None
         if "bf16" in legs:
             # the same frame without shading: value queries only, no gradient
             wk_v = copy.copy(wk)
             wk_v.params = copy.copy(wk.params)
             wk_v.params.shading = False
-            vleg = gpu_leg(b, ctx, wk_v, 1, max(20, args.steps // 4), 5, log, nominal_frames=False)
+            vleg = gpu_leg(b, ctx, wk_v, 1, max(20, args.steps // 4), 5, log, nominal_frames=False,
+                           autotune=args.autotune)
             value_only = {"store": "bf16", "shading": False,
                           "samples_per_frame": vleg["samples"],
                           "samples_per_s": vleg["samples"] / (float(vleg["kern"].mean()) * 1e-3),
