@@ -103,7 +103,9 @@ typedef struct mfa_camera {
 /* Transfer function (Algorithm 1: colour and opacity transfer functions),
  * as one RGBA table of n entries (2 <= n <= MFA_MAX_TF), host memory,
  * linearly interpolated over [v_lo, v_hi] (v_lo < v_hi); values outside
- * the range clamp to the end entries. */
+ * the range clamp to the end entries.  Entries are finite, and every
+ * opacity (the fourth value of an entry) lies in [0, 1]; otherwise
+ * MFA_ERR_INVALID. */
 typedef struct mfa_tf {
   int32_t n;
   int32_t reserved;

@@ -246,6 +246,10 @@ mfa_status validate_render(const mfa_camera* c, const mfa_tf* tf, const mfa_rend
       msg = "transfer function entries must be finite";
       return MFA_ERR_INVALID;
     }
+    if (i % 4 == 3 && !(tf->rgba[i] >= 0.0f && tf->rgba[i] <= 1.0f)) {
+      msg = "transfer function opacities must lie in [0, 1]";
+      return MFA_ERR_INVALID;
+    }
   }
   if (!(p->step > 0.0) || !std::isfinite(p->step)) {
     msg = "step must be positive";

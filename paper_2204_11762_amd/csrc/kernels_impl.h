@@ -512,21 +512,46 @@ __device__ __forceinline__ void sample_params(const CamParams& a, const Ray& ray
   }
 }
 
-__device__ __forceinline__ float ipowf(float x, int k) {
-  float r = 1.0f;
-  while (k) {
-    if (k & 1) r *= x;
+// x^k for a wave-uniform k >= 0 by binary powering: each trailing zero bit
+// of k costs one squaring, each further bit one squaring and (if set) one
+// multiply into the result.
+__device__ __forceinline__ float ipow_uniform(float x, int k) {
+  if (k == 0) return 1.0f;
+  while ((k & 1) == 0) {
     x *= x;
     k >>= 1;
   }
+  float r = x;
+  for (k >>= 1; k != 0; k >>= 1) {
+    x *= x;
+    if (k & 1) r *= x;
+  }
   return r;
+}
+
+// Per-ray terms of the specular lobe.  With r = 2 (n.l) n - l the
+// reflected light direction, r.v = 2 (n.l)(n.v) - l.v, so a ray keeps 2v
+// and l.v, and a sample needs only the two dot products g.l and g.(2v).
+struct EyeTerms {
+  float v2x, v2y, v2z;  // twice the unit direction towards the eye
+  float lv;             // l.v
+};
+
+__device__ __forceinline__ EyeTerms eye_terms(const RenderArgsDev& a, float vx, float vy,
+                                              float vz) {
+  EyeTerms t;
+  t.v2x = 2.0f * vx;
+  t.v2y = 2.0f * vy;
+  t.v2z = 2.0f * vz;
+  t.lv = a.light[0] * vx + a.light[1] * vy + a.light[2] * vz;
+  return t;
 }
 
 // Transfer function and Phong shading of a sample of value f and world
 // gradient g: shaded colour (sr, sg, sb) and opacity alpha.
 template <bool SHADE, class TfFetch>
 __device__ __forceinline__ void shade_sample(const RenderArgsDev& a, float f, const float (&g)[3],
-                                             float vx, float vy, float vz, TfFetch tf, float& sr,
+                                             const EyeTerms& eye, TfFetch tf, float& sr,
                                              float& sg, float& sb, float& alpha) {
   float x = (f - a.tf_lo) * a.tf_scale;
   x = fminf(fmaxf(x, 0.0f), 1.0f) * (float)(a.ntf - 1);
@@ -539,18 +564,15 @@ __device__ __forceinline__ void shade_sample(const RenderArgsDev& a, float f, co
   sb = fmaf(t, c1.z - c0.z, c0.z);
   alpha = fmaf(t, c1.w - c0.w, c0.w);
   if (SHADE) {
-    const float lx = a.light[0], ly = a.light[1], lz = a.light[2];
+    // n = g / |g|; diffuse |n.l|; specular max(0, r.v)^k
     const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
     const float inv = (g2 >= 1e-12f) ? rsqrtf(g2) : 1e6f;
-    const float nx = g[0] * inv, ny = g[1] * inv, nz = g[2] * inv;
-    const float ndl = nx * lx + ny * ly + nz * lz;
-    const float diff = fabsf(ndl);
-    const float rx = 2.0f * ndl * nx - lx;
-    const float ry = 2.0f * ndl * ny - ly;
-    const float rz = 2.0f * ndl * nz - lz;
-    const float rv = rx * vx + ry * vy + rz * vz;
-    const float spec = a.ks * ipowf(fmaxf(rv, 0.0f), a.shininess);
-    const float kdiff = a.ka + a.kd * diff;
+    const float gl = g[0] * a.light[0] + g[1] * a.light[1] + g[2] * a.light[2];
+    const float gv2 = g[0] * eye.v2x + g[1] * eye.v2y + g[2] * eye.v2z;
+    const float ndl = gl * inv;
+    const float rv = fmaf(ndl, gv2 * inv, -eye.lv);
+    const float spec = a.ks * ipow_uniform(fmaxf(rv, 0.0f), a.shininess);
+    const float kdiff = a.ka + a.kd * fabsf(ndl);
     sr = fminf(1.0f, fmaf(kdiff, sr, spec));
     sg = fminf(1.0f, fmaf(kdiff, sg, spec));
     sb = fminf(1.0f, fmaf(kdiff, sb, spec));
@@ -567,48 +589,6 @@ __device__ __forceinline__ bool composite_one(float ert, float sr, float sg, flo
   cb = fmaf(wgt, sb, cb);
   A += wgt;
   return !(A > ert);
-}
-
-// Transfer function, Phong shading and one front-to-back compositing step
-// for a sample of value f and world gradient g.  Returns false once the
-// accumulated opacity exceeds the termination limit.
-template <bool SHADE, class TfFetch>
-__device__ __forceinline__ bool shade_composite(const RenderArgsDev& a, float f, const float (&g)[3],
-                                                float vx, float vy, float vz, TfFetch tf,
-                                                float& cr, float& cg, float& cb, float& A) {
-  float x = (f - a.tf_lo) * a.tf_scale;
-  x = fminf(fmaxf(x, 0.0f), 1.0f) * (float)(a.ntf - 1);
-  const int i = min((int)x, a.ntf - 2);
-  const float t = x - (float)i;
-  const float4 c0 = tf(i);
-  const float4 c1 = tf(i + 1);
-  float sr = fmaf(t, c1.x - c0.x, c0.x);
-  float sg = fmaf(t, c1.y - c0.y, c0.y);
-  float sb = fmaf(t, c1.z - c0.z, c0.z);
-  const float alpha = fmaf(t, c1.w - c0.w, c0.w);
-  if (SHADE) {
-    const float lx = a.light[0], ly = a.light[1], lz = a.light[2];
-    const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
-    const float inv = (g2 >= 1e-12f) ? rsqrtf(g2) : 1e6f;
-    const float nx = g[0] * inv, ny = g[1] * inv, nz = g[2] * inv;
-    const float ndl = nx * lx + ny * ly + nz * lz;
-    const float diff = fabsf(ndl);
-    const float rx = 2.0f * ndl * nx - lx;
-    const float ry = 2.0f * ndl * ny - ly;
-    const float rz = 2.0f * ndl * nz - lz;
-    const float rv = rx * vx + ry * vy + rz * vz;
-    const float spec = a.ks * ipowf(fmaxf(rv, 0.0f), a.shininess);
-    const float kdiff = a.ka + a.kd * diff;
-    sr = fminf(1.0f, fmaf(kdiff, sr, spec));
-    sg = fminf(1.0f, fmaf(kdiff, sg, spec));
-    sb = fminf(1.0f, fmaf(kdiff, sb, spec));
-  }
-  const float wgt = (1.0f - A) * alpha;
-  cr = fmaf(wgt, sr, cr);
-  cg = fmaf(wgt, sg, cg);
-  cb = fmaf(wgt, sb, cb);
-  A += wgt;
-  return !(A > a.ert);
 }
 
 __device__ __forceinline__ void count_samples(const RenderArgsDev& a, int count, int lane) {
@@ -640,7 +620,7 @@ __global__ __launch_bounds__(256) void render_global_kernel(RenderArgsDev a) {
                                                  RAT ? a.m.wctrl_bytes : a.m.ctrl_bytes);
     const Ray ray = make_ray(a.cam, py, px);
     float cr = 0.0f, cg = 0.0f, cb = 0.0f, A = 0.0f;
-    const float vx = -(float)ray.d[0], vy = -(float)ray.d[1], vz = -(float)ray.d[2];
+    const EyeTerms eye = eye_terms(a, -(float)ray.d[0], -(float)ray.d[1], -(float)ray.d[2]);
     const float4* tfp = a.tf;
     auto tf = [&](int i) { return tfp[i]; };
     int span[3] = {0, 0, 0};
@@ -650,7 +630,9 @@ __global__ __launch_bounds__(256) void render_global_kernel(RenderArgsDev a) {
       float f, g[3];
       query<P, STORE, SHADE, RAT>(a.m, rs, rsw, u, span, s == 0, f, g);
       ++count;
-      if (!shade_composite<SHADE>(a, f, g, vx, vy, vz, tf, cr, cg, cb, A)) break;
+      float sr, sg, sb, alpha;
+      shade_sample<SHADE>(a, f, g, eye, tf, sr, sg, sb, alpha);
+      if (!composite_one(a.ert, sr, sg, sb, alpha, cr, cg, cb, A)) break;
     }
     float4 o;
     o.x = cr;
@@ -766,6 +748,17 @@ __device__ __forceinline__ float group_bcast(float v) {
   }
 }
 
+// Sum over each aligned group of L lanes (L = 1, 2 or 4), returned to every
+// lane of the group: pair swap, then (L = 4) half-quad swap, by DPP.
+template <int L>
+__device__ __forceinline__ float group_sum(float v) {
+  if constexpr (L >= 2)
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+  if constexpr (L >= 4)
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+  return v;
+}
+
 // a / b for 0 <= a < 2^22, b >= 1, with inv_b ~ 1/b: float estimate plus
 // one correction step.
 __device__ __forceinline__ int div_small(int a, int b, float inv_b) {
@@ -862,7 +855,7 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
   // the sample index
   int nr = 0;
   double ua[3] = {0.0, 0.0, 0.0}, ub[3] = {0.0, 0.0, 0.0};
-  float vx = 0.0f, vy = 0.0f, vz = 0.0f;
+  EyeTerms eye = {0.0f, 0.0f, 0.0f, 0.0f};
   if (inside) {
     const Ray ray = make_ray(a.cam, py, px);
     nr = ray.nr;
@@ -872,9 +865,7 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
       ua[k] = (ray.o[k] + t_half * ray.d[k] - a.cam.lo[k]) * a.cam.inv_ext[k];
       ub[k] = a.cam.step * ray.d[k] * a.cam.inv_ext[k];
     }
-    vx = -(float)ray.d[0];
-    vy = -(float)ray.d[1];
-    vz = -(float)ray.d[2];
+    eye = eye_terms(a, -(float)ray.d[0], -(float)ray.d[1], -(float)ray.d[2]);
   }
   auto param = [&](int s, int k) {
     return fmin(fmax(fma((double)s, ub[k], ua[k]), 0.0), 1.0);
@@ -1037,21 +1028,25 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
           const int m = Ax.n - q;
           const float t = fmaf((float)i, dt[k], ta[k]);
           const float fl = floorf(t);
-          const int c = min(max(ca[k] + (int)fl, 0), m - 1);
-          const float tl = t - (float)(c - ca[k]);
-          w[k] = c;
+          int c = ca[k] + (int)fl;
           if (c >= q - 1 && c <= m - q) {
+            // interior cell: cardinal pieces at the fractional part
+            const float tl = t - fl;
             if constexpr (EQ)
               cardinal<P>(tl, N[k], dN[k]);
             else
               cardinal_window<P>(q, tl, N[k], dN[k]);
           } else {
-            // boundary span: triangle with the span's reciprocal table
+            // boundary span, or a cell that FP32 stepping moved past either
+            // end (clamped): triangle with the span's reciprocal table
+            c = min(max(c, 0), m - 1);
+            const float tl = t - (float)(c - ca[k]);
             const float* row = Ax.tab + (size_t)c * (size_t)table_stride(q);
             axis_basis<P>(q, row, tl * Ax.inv_m, N[k], dN[k]);
 #pragma unroll
             for (int r = 0; r <= P; ++r) dN[k][r] *= Ax.inv_m;
           }
+          w[k] = c;
         } else {
           const double u = param(s, k);
           span_step(K[k], Ax.n, q, u, st[k]);
@@ -1063,31 +1058,45 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
       }
     };
 
-    // shade this lane's sample, then composite the group's samples
-    // j, j+1, ..., j+LPR-1 in order; false once the ray terminates
+    // Shade this lane's sample, then run the opacity chain of the group's
+    // samples j, j+1, ..., j+LPR-1 in order; false once the ray terminates.
+    // Every lane of a ray runs the same chain (each sample's alpha comes
+    // from its lane by a quad broadcast), keeps the compositing weight of
+    // its own sample and accumulates only its own colour; the partial
+    // colours of a ray are summed once at the end.  The phases run without
+    // branches: a sample past the round's end has alpha 0 and leaves the
+    // state unchanged, and after termination the weights are 0.
     auto finish = [&](int j, float f, const float (&g)[3], bool valid) {
       float sr = 0.0f, sg = 0.0f, sb = 0.0f, alpha = 0.0f;
       if (valid) {
         float gw[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) gw[k] = g[k] * gfac[k];
-        shade_sample<SHADE>(a, f, gw, vx, vy, vz, tf, sr, sg, sb, alpha);
+        shade_sample<SHADE>(a, f, gw, eye, tf, sr, sg, sb, alpha);
       }
+      // Opacities lie in [0, 1] (checked on the host), so A <= 1 and a
+      // reached sample's weight (1 - A) alpha is +0 or positive; -0 marks
+      // a sample after the termination, which adds nothing and is not
+      // counted.
       bool go = true;
-#define MFA_COMPOSITE_PHASE(Q)                                                      \
-  if constexpr ((Q) < LPR) {                                                        \
-    const float qr = group_bcast<LPR, (Q)>(sr), qg = group_bcast<LPR, (Q)>(sg);    \
-    const float qb = group_bcast<LPR, (Q)>(sb), qa = group_bcast<LPR, (Q)>(alpha); \
-    if (go && j + (Q) < s1) {                                                       \
-      count += (e == 0) ? 1 : 0;                                                    \
-      go = composite_one(a.ert, qr, qg, qb, qa, cr, cg, cb, A);                     \
-    }                                                                               \
+      float my_w = -0.0f;
+#define MFA_COMPOSITE_PHASE(Q)                          \
+  if constexpr ((Q) < LPR) {                            \
+    const float qa = group_bcast<LPR, (Q)>(alpha);      \
+    const float wq = go ? (1.0f - A) * qa : -0.0f;      \
+    if (e == (Q)) my_w = wq;                            \
+    A += wq;                                            \
+    go = go && !(A > a.ert);                            \
   }
       MFA_COMPOSITE_PHASE(0)
       MFA_COMPOSITE_PHASE(1)
       MFA_COMPOSITE_PHASE(2)
       MFA_COMPOSITE_PHASE(3)
 #undef MFA_COMPOSITE_PHASE
+      cr = fmaf(my_w, sr, cr);
+      cg = fmaf(my_w, sg, cg);
+      cb = fmaf(my_w, sb, cb);
+      count += (valid && !signbit(my_w)) ? 1 : 0;
       return go;
     };
 
@@ -1099,7 +1108,9 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
           float N[3][P + 1], dN[3][P + 1];
           int w[3];
           weights(s, i, N, dN, w);
-          int e0 = (w[0] - blo[0]) + pitch_y * (w[1] - blo[1]) + pitch_z * (w[2] - blo[2]);
+          // 24-bit products: pitches and in-box offsets are far below 2^23
+          int e0 = (w[0] - blo[0]) + __mul24(pitch_y, w[1] - blo[1]) +
+                   __mul24(pitch_z, w[2] - blo[2]);
           e0 = min(max(e0, 0), emax);
           contract<P, SHADE>(
               N, dN,
@@ -1139,6 +1150,10 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
     }
     if (s1 >= nr) alive = false;
   }
+  // the colour of a ray is the sum of its lanes' partial colours
+  cr = group_sum<LPR>(cr);
+  cg = group_sum<LPR>(cg);
+  cb = group_sum<LPR>(cb);
   if (inside && e == 0) {
     float4 o;
     o.x = cr;

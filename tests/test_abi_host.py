@@ -178,6 +178,9 @@ RENDER_ERRORS = {
     "tf too long": lambda c, t, p: (c, _mod(t, table=np.zeros((5000, 4), np.float32)), p),
     "tf empty range": lambda c, t, p: (c, _mod(t, v_hi=t.v_lo), p),
     "tf nan": lambda c, t, p: (c, _mod(t, table=np.full((8, 4), np.nan, np.float32)), p),
+    "tf opacity above 1": lambda c, t, p: (c, _mod(t, table=np.full((8, 4), 1.01, np.float32)), p),
+    "tf opacity negative": lambda c, t, p: (c, _mod(t, table=np.where(
+        np.arange(4)[None, :] == 3, -1e-3, 0.5).repeat(8, axis=0).astype(np.float32)), p),
     "step 0": lambda c, t, p: (c, t, _mod(p, step=0.0)),
     "step negative": lambda c, t, p: (c, t, _mod(p, step=-0.1)),
     "step nan": lambda c, t, p: (c, t, _mod(p, step=float("nan"))),
