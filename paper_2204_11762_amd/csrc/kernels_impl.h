@@ -714,14 +714,17 @@ __device__ __forceinline__ void axis_weights(const AxisDev& A, const SpanState& 
 // Minimum (MAX = false) or maximum over the 64 lanes of a wave, returned as
 // a wave-uniform value.  Butterflies inside each row of 16 lanes by DPP
 // (pair swap, quad-half swap, half-row mirror, row mirror), then across
-// rows and halves with the row-swapping permutes.  Every lane of the wave
-// must be active.
-template <bool MAX>
+// rows and halves with the row-swapping permutes.  QUAD: v is already the
+// same in the four lanes of each aligned quad, so the two in-quad steps
+// are skipped.  Every lane of the wave must be active.
+template <bool MAX, bool QUAD = false>
 __device__ __forceinline__ unsigned wave_reduce_u32(unsigned v) {
   auto op = [](unsigned x, unsigned y) { return MAX ? (x > y ? x : y) : (x < y ? x : y); };
   constexpr int id = MAX ? 0 : -1;
-  v = op(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0xB1, 0xF, 0xF, false));
-  v = op(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x4E, 0xF, 0xF, false));
+  if constexpr (!QUAD) {
+    v = op(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0xB1, 0xF, 0xF, false));
+    v = op(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x4E, 0xF, 0xF, false));
+  }
   v = op(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x141, 0xF, 0xF, false));
   v = op(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x140, 0xF, 0xF, false));
   const auto r16 = __builtin_amdgcn_permlane16_swap(v, v, false, false);
@@ -924,8 +927,9 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
             h = __float_as_uint((float)uh);
           }
         }
-        l = wave_reduce_u32<false>(l);
-        h = wave_reduce_u32<true>(h);
+        // the box of a ray is the same in its LPR lanes
+        l = wave_reduce_u32<false, LPR == 4>(l);
+        h = wave_reduce_u32<true, LPR == 4>(h);
         int sl, sh;
         if constexpr (FAST) {
           sl = q + (int)l;
@@ -1058,22 +1062,23 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
       }
     };
 
-    // Shade this lane's sample, then run the opacity chain of the group's
-    // samples j, j+1, ..., j+LPR-1 in order; false once the ray terminates.
+    // shade(): transfer function and Phong shading of this lane's sample.
+    // composite(): the opacity chain of the group's samples j, j+1, ...,
+    // j+LPR-1 in order; false once the ray terminates.
     // Every lane of a ray runs the same chain (each sample's alpha comes
     // from its lane by a quad broadcast), keeps the compositing weight of
     // its own sample and accumulates only its own colour; the partial
     // colours of a ray are summed once at the end.  The phases run without
     // branches: a sample past the round's end has alpha 0 and leaves the
     // state unchanged, and after termination the weights are 0.
-    auto finish = [&](int j, float f, const float (&g)[3], bool valid) {
-      float sr = 0.0f, sg = 0.0f, sb = 0.0f, alpha = 0.0f;
-      if (valid) {
-        float gw[3];
+    auto shade = [&](float f, const float (&g)[3], float& sr, float& sg, float& sb,
+                     float& alpha) {
+      float gw[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) gw[k] = g[k] * gfac[k];
-        shade_sample<SHADE>(a, f, gw, eye, tf, sr, sg, sb, alpha);
-      }
+      for (int k = 0; k < 3; ++k) gw[k] = g[k] * gfac[k];
+      shade_sample<SHADE>(a, f, gw, eye, tf, sr, sg, sb, alpha);
+    };
+    auto composite = [&](int j, float sr, float sg, float sb, float alpha, bool valid) {
       // Opacities lie in [0, 1] (checked on the host), so A <= 1 and a
       // reached sample's weight (1 - A) alpha is +0 or positive; -0 marks
       // a sample after the termination, which adds nothing and is not
@@ -1103,8 +1108,10 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
     if (fits) {
       for (int j = s0, i = 0; j < s1; j += LPR, ++i) {
         const int s = j + e;
-        float f = 0.0f, g[3] = {0.0f, 0.0f, 0.0f};
+        // a lane past the round's end adds alpha 0 and colour 0
+        float sr = 0.0f, sg = 0.0f, sb = 0.0f, alpha = 0.0f;
         if (s < s1) {
+          float f, g[3];
           float N[3][P + 1], dN[3][P + 1];
           int w[3];
           weights(s, i, N, dN, w);
@@ -1120,8 +1127,9 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
                 for (int q = 0; q <= P; ++q) row[q] = r[q];
               },
               f, g);
+          shade(f, g, sr, sg, sb, alpha);
         }
-        if (!finish(j, f, g, s < s1)) {
+        if (!composite(j, sr, sg, sb, alpha, s < s1)) {
           alive = false;
           break;
         }
@@ -1129,8 +1137,10 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
     } else {
       for (int j = s0, i = 0; j < s1; j += LPR, ++i) {
         const int s = j + e;
-        float f = 0.0f, g[3] = {0.0f, 0.0f, 0.0f};
+        // a lane past the round's end adds alpha 0 and colour 0
+        float sr = 0.0f, sg = 0.0f, sb = 0.0f, alpha = 0.0f;
         if (s < s1) {
+          float f, g[3];
           float N[3][P + 1], dN[3][P + 1];
           int w[3];
           weights(s, i, N, dN, w);
@@ -1141,8 +1151,9 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
                 load_row<P, STORE>(rs, e0 + b * nx + c * nxy, row);
               },
               f, g);
+          shade(f, g, sr, sg, sb, alpha);
         }
-        if (!finish(j, f, g, s < s1)) {
+        if (!composite(j, sr, sg, sb, alpha, s < s1)) {
           alive = false;
           break;
         }
