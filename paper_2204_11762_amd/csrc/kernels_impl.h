@@ -290,6 +290,28 @@ __device__ __forceinline__ void cardinal(float t, float* N, float* dN) {
   }
 }
 
+// The cubic pieces scaled for the render kernel: 6 N and 2 dN/dt.  The
+// scaled derivatives are -s^2, t (3t - 4), 1 + t (2 - 3t) and t^2 with
+// s = 1 - t, so a sample's value and gradient come out of the contraction
+// multiplied by 6^3 and 2 * 6^2; the caller folds both factors into its
+// transfer-function and gradient constants.
+constexpr float kCubicValueScale = 216.0f;
+constexpr float kCubicGradScale = 72.0f;
+
+__device__ __forceinline__ void cardinal3_scaled(float t, float* N, float* dN) {
+  const float t2 = t * t;
+  const float s = 1.0f - t;
+  const float s2 = s * s;
+  N[0] = s2 * s;
+  N[1] = fmaf(t2, fmaf(t, 3.0f, -6.0f), 4.0f);
+  N[2] = fmaf(t, fmaf(t, fmaf(t, -3.0f, 3.0f), 3.0f), 1.0f);
+  N[3] = t2 * t;
+  dN[0] = -s2;
+  dN[1] = t * fmaf(t, 3.0f, -4.0f);
+  dN[2] = fmaf(t, fmaf(t, -3.0f, 2.0f), 1.0f);
+  dN[3] = t2;
+}
+
 template <int P>
 __device__ __forceinline__ void cardinal_window(int q, float t, float (&N)[P + 1],
                                                 float (&dN)[P + 1]) {
@@ -550,10 +572,11 @@ __device__ __forceinline__ EyeTerms eye_terms(const RenderArgsDev& a, float vx, 
 // Transfer function and Phong shading of a sample of value f and world
 // gradient g: shaded colour (sr, sg, sb) and opacity alpha.
 template <bool SHADE, class TfFetch>
-__device__ __forceinline__ void shade_sample(const RenderArgsDev& a, float f, const float (&g)[3],
-                                             const EyeTerms& eye, TfFetch tf, float& sr,
-                                             float& sg, float& sb, float& alpha) {
-  float x = (f - a.tf_lo) * a.tf_scale;
+__device__ __forceinline__ void shade_sample(const RenderArgsDev& a, float tf_lo, float tf_scale,
+                                             float f, const float (&g)[3], const EyeTerms& eye,
+                                             TfFetch tf, float& sr, float& sg, float& sb,
+                                             float& alpha) {
+  float x = (f - tf_lo) * tf_scale;
   x = fminf(fmaxf(x, 0.0f), 1.0f) * (float)(a.ntf - 1);
   const int i = min((int)x, a.ntf - 2);
   const float t = x - (float)i;
@@ -631,7 +654,7 @@ __global__ __launch_bounds__(256) void render_global_kernel(RenderArgsDev a) {
       query<P, STORE, SHADE, RAT>(a.m, rs, rsw, u, span, s == 0, f, g);
       ++count;
       float sr, sg, sb, alpha;
-      shade_sample<SHADE>(a, f, g, eye, tf, sr, sg, sb, alpha);
+      shade_sample<SHADE>(a, a.tf_lo, a.tf_scale, f, g, eye, tf, sr, sg, sb, alpha);
       if (!composite_one(a.ert, sr, sg, sb, alpha, cr, cg, cb, A)) break;
     }
     float4 o;
@@ -844,6 +867,14 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
 #pragma unroll
   for (int k = 0; k < 3; ++k)
     gfac[k] = FAST ? a.m.ax[k].gscale * (float)a.m.ax[k].m : a.m.ax[k].gscale;
+  // degree 3 on uniform knots: scaled cubic pieces (value x 216, gradient x 72)
+  constexpr bool kScaled = FAST && EQ && P == 3;
+  const float tf_lo = kScaled ? a.tf_lo * kCubicValueScale : a.tf_lo;
+  const float tf_scale = kScaled ? a.tf_scale * (1.0f / kCubicValueScale) : a.tf_scale;
+  if constexpr (kScaled) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gfac[k] *= 1.0f / kCubicGradScale;
+  }
   int count = 0;
 
   // the workgroup renders super-tile sup (2x2 tiles), wave w its quadrant
@@ -1036,7 +1067,9 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
           if (c >= q - 1 && c <= m - q) {
             // interior cell: cardinal pieces at the fractional part
             const float tl = t - fl;
-            if constexpr (EQ)
+            if constexpr (kScaled)
+              cardinal3_scaled(tl, N[k], dN[k]);
+            else if constexpr (EQ)
               cardinal<P>(tl, N[k], dN[k]);
             else
               cardinal_window<P>(q, tl, N[k], dN[k]);
@@ -1047,8 +1080,14 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
             const float tl = t - (float)(c - ca[k]);
             const float* row = Ax.tab + (size_t)c * (size_t)table_stride(q);
             axis_basis<P>(q, row, tl * Ax.inv_m, N[k], dN[k]);
+            // derivatives to t units, both in the scale of the interior pieces
+            const float nsc = kScaled ? 6.0f : 1.0f;
+            const float dsc = kScaled ? 2.0f * Ax.inv_m : Ax.inv_m;
 #pragma unroll
-            for (int r = 0; r <= P; ++r) dN[k][r] *= Ax.inv_m;
+            for (int r = 0; r <= P; ++r) {
+              N[k][r] *= nsc;
+              dN[k][r] *= dsc;
+            }
           }
           w[k] = c;
         } else {
@@ -1076,7 +1115,7 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
       float gw[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) gw[k] = g[k] * gfac[k];
-      shade_sample<SHADE>(a, f, gw, eye, tf, sr, sg, sb, alpha);
+      shade_sample<SHADE>(a, tf_lo, tf_scale, f, gw, eye, tf, sr, sg, sb, alpha);
     };
     auto composite = [&](int j, float sr, float sg, float sb, float alpha, bool valid) {
       // Opacities lie in [0, 1] (checked on the host), so A <= 1 and a
