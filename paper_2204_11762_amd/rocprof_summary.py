@@ -27,8 +27,9 @@ import re
 import statistics
 import sys
 
-# render_brick_kernel<P, STORE, ...>: degree and storage of the hot kernel
-RENDER_RE = re.compile(r"render_brick_kernel<(\d+), (\d+),")
+# render_brick_kernel<P, STORE, SHADE, ...>: degree, storage and shading of
+# the hot kernel
+RENDER_RE = re.compile(r"render_brick_kernel<(\d+), (\d+), (true|false),")
 
 
 def kernel_table(stats_csv: str) -> list[dict]:
@@ -98,7 +99,10 @@ def per_leg(rows: list[dict]) -> dict:
         m = RENDER_RE.search(r["Kernel_Name"])
         if not m:
             continue
+        # shaded frames are the storage's leg; value-only frames a leg of their own
         store = {"0": "fp32", "1": "bf16", "2": "fp16"}[m.group(2)]
+        if m.group(3) == "false":
+            store += "_value_only"
         legs.setdefault(store, []).append(float(r["Counter_Value"]))
         names[store] = short_name(r["Kernel_Name"])
     return {k: {"kernel": names[k], "dispatches": len(v), "kib_median": statistics.median(v),
