@@ -35,6 +35,8 @@ with the literal recursion (brute force, tiny models only), ``eval_local``
 uses the span and the ``p+1`` non-zero functions per axis (local support
 makes the two equal).  ``grad_hodograph`` differentiates through derivative
 control points, an algebraically different route to the same gradient.
+Second derivatives: ``hessian_full`` (literal recursion, brute force) and
+``hessian_hodograph`` (derivative control points applied twice).
 """
 
 from __future__ import annotations
@@ -304,6 +306,113 @@ def grad_hodograph(model: Model, uvw: np.ndarray) -> np.ndarray:
         f, _ = eval_local(dm, uvw)
         out[:, axis] = f
     return out
+
+
+# ---------------------------------------------------------------------------
+# second derivatives (Hessian)
+# ---------------------------------------------------------------------------
+# The model has analytic derivatives of every order (Sect. 3.1 notes that
+# the B-spline representation yields all derivatives together); second
+# derivatives are what curvature-based transfer functions need.  The six
+# components are ordered uu, vv, ww, uv, uw, vw.
+
+HESS_PAIRS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
+
+
+def d2basis_full(i: int, q: int, U, u: float) -> float:
+    """``N''_{i,q}(u)``: de Boor's derivative formula applied to the first
+    derivatives of the two degree q-1 functions."""
+    if q <= 1:
+        return 0.0
+    acc = 0.0
+    den1 = U[i + q] - U[i]
+    if den1 != 0.0:
+        acc += q / den1 * dbasis_full(i, q - 1, U, u)
+    den2 = U[i + q + 1] - U[i + 1]
+    if den2 != 0.0:
+        acc -= q / den2 * dbasis_full(i + 1, q - 1, U, u)
+    return acc
+
+
+def hessian_full(model: Model, uvw: np.ndarray) -> np.ndarray:
+    """Brute force parametric Hessian (m, 6): every control point, with each
+    axis factor differentiated as often as the axis occurs in the pair.
+    Scalar loops; tiny non-rational models only."""
+    if model.weights is not None:
+        raise ValueError("hessian_full: non-rational models only")
+    uvw = np.atleast_2d(np.asarray(uvw, dtype=np.float64))
+    nx, ny, nz = model.n
+    deg = model.degree
+    knots = [list(map(float, k)) for k in model.knots]
+    fns = (basis_full, dbasis_full, d2basis_full)
+    out = np.zeros((len(uvw), 6))
+    for m, pt in enumerate(uvw):
+        # B[axis][order][index]
+        B = [[[fns[o](i, deg[ax], knots[ax], pt[ax]) for i in range(model.n[ax])]
+              for o in range(3)] for ax in range(3)]
+        for h, (a, b) in enumerate(HESS_PAIRS):
+            order = [0, 0, 0]
+            order[a] += 1
+            order[b] += 1
+            acc = 0.0
+            for k in range(nz):
+                for j in range(ny):
+                    for i in range(nx):
+                        acc += (B[0][order[0]][i] * B[1][order[1]][j] * B[2][order[2]][k]
+                                * float(model.ctrl[k, j, i]))
+            out[m, h] = acc
+    return out
+
+
+def derivative_model(model: Model, axis: int):
+    """The derivative along ``axis`` as a B-spline model: degree p-1 on the
+    knot vector without its first and last knot, with control points
+    ``Q_i = p (P_{i+1} - P_i) / (U_{i+p+1} - U_{i+1})``.  A zero denominator
+    belongs to a degree p-1 function that vanishes everywhere, so its
+    ``Q_i`` is 0.  ``None`` when p = 0: the derivative is identically 0."""
+    if model.weights is not None:
+        raise ValueError("derivative_model: non-rational models only")
+    p = model.degree[axis]
+    if p == 0:
+        return None
+    U = np.asarray(model.knots[axis], dtype=np.float64)
+    n = model.n[axis]
+    ctrl_ax = 2 - axis                              # numpy axis of this direction
+    P = np.moveaxis(model.ctrl, ctrl_ax, 0)          # (n, ...)
+    den = U[p + 1:p + n] - U[1:n]                    # U_{i+p+1} - U_{i+1}, i = 0..n-2
+    shape = (-1,) + (1,) * (P.ndim - 1)
+    safe = np.where(den != 0.0, den, 1.0).reshape(shape)
+    Q = np.where((den != 0.0).reshape(shape), p * (P[1:] - P[:-1]) / safe, 0.0)
+    deg = list(model.degree)
+    deg[axis] = p - 1
+    knots = list(model.knots)
+    knots[axis] = U[1:-1]
+    return Model(tuple(deg), tuple(knots), np.moveaxis(Q, 0, ctrl_ax), model.lo, model.hi)
+
+
+def hessian_hodograph(model: Model, uvw: np.ndarray) -> np.ndarray:
+    """Parametric Hessian (m, 6) through derivative control points: for each
+    pair (a, b) the model is differentiated along a, then along b, and the
+    resulting spline's value is evaluated."""
+    uvw = np.atleast_2d(np.asarray(uvw, dtype=np.float64))
+    out = np.zeros((len(uvw), 6))
+    for h, (a, b) in enumerate(HESS_PAIRS):
+        da = derivative_model(model, a)
+        dab = None if da is None else derivative_model(da, b)
+        if dab is not None:
+            out[:, h], _ = eval_local(dab, uvw)
+    return out
+
+
+def eval_world_hessian(model: Model, xyz: np.ndarray):
+    """Value, world gradient and world Hessian (m, 6) at world points: each
+    parametric second derivative d2f/du_a du_b is divided by the two box
+    extents (chain rule of the affine normalisation)."""
+    f, g = eval_world(model, xyz)
+    H = hessian_hodograph(model, to_param(model, xyz))
+    ext = np.asarray(model.hi, dtype=np.float64) - np.asarray(model.lo, dtype=np.float64)
+    scale = np.array([1.0 / (ext[a] * ext[b]) for a, b in HESS_PAIRS])
+    return f, g, H * scale
 
 
 def to_param(model: Model, xyz: np.ndarray) -> np.ndarray:
