@@ -367,7 +367,9 @@ def eval_leg(b, ctx, wk, steps: int, log, n_points: int = 1 << 24):
     """Value + gradient queries at n_points points of the 256^3 model
     (uniformly random, then sorted along a Morton curve), against the HBM
     roofline: algorithmic bytes per point = (p+1)^3 stored control points +
-    24 B position + 16 B value and gradient."""
+    24 B position + 16 B value and gradient.  FP32 storage also times the
+    second-derivative query (value, gradient and six second derivatives:
+    40 B of results per point)."""
     import torch
     p = int(max(wk.model.degree))
     xyz = wl.uniform_points(np.random.default_rng(9), n_points)
@@ -398,6 +400,25 @@ def eval_leg(b, ctx, wk, steps: int, log, n_points: int = 1 << 24):
                                           "achieved_GBps": gbs, "frac_of_8TBps": gbs / 8000.0}
                 log(f"eval {name} {oname}: {ms:.3f} ms for {n_points} points, "
                     f"{gbs:.0f} GB/s algorithmic")
+                if store == 0:
+                    hs = torch.empty((n_points, 6), dtype=torch.float32, device="cuda")
+                    b.mfa_eval_hessian(ctx, h, x, v, hs, grad=g)
+                    torch.cuda.synchronize()
+                    e0.record()
+                    for _ in range(steps):
+                        b.mfa_eval_hessian(ctx, h, x, v, hs, grad=g)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ms = e0.elapsed_time(e1) / steps
+                    per_h = per_point + 24
+                    gbs = n_points * per_h / (ms * 1e-3) / 1e9
+                    out[f"{name}_{oname}_hessian"] = {
+                        "ms": ms, "points_per_s": n_points / (ms * 1e-3),
+                        "algorithmic_bytes_per_point": per_h, "achieved_GBps": gbs,
+                        "frac_of_8TBps": gbs / 8000.0}
+                    log(f"eval {name} {oname} with second derivatives: {ms:.3f} ms, "
+                        f"{gbs:.0f} GB/s algorithmic")
+                    del hs
                 del x, v, g
         finally:
             b.mfa_model_free(ctx, h)

@@ -336,6 +336,20 @@ mfa_status mfa_kernel_times(mfa_ctx* ctx, float* ms_host, int64_t cap, int64_t* 
 mfa_status mfa_eval_points(mfa_ctx* ctx, int64_t model, int64_t n, const double* xyz_dev,
                            float* value_dev, float* grad_dev, void* stream);
 
+/* Value, world gradient and world Hessian at n world points.  The model's
+ * derivatives of every order are analytic (Sect. 3.1: the representation
+ * gives all derivatives together); the second derivatives are what
+ * curvature-based transfer functions take.  Same points, value and
+ * gradient buffers and clamping as mfa_eval_points (grad_dev may be null);
+ * hess_dev: n*6 FP32 per point, d2f/dx2, d2f/dy2, d2f/dz2, d2f/dxdy,
+ * d2f/dxdz, d2f/dydz in world units, caller-owned device memory.  At a knot
+ * the span on its right is used (one-sided second derivatives where the
+ * model is only C^1 there).  Non-rational models only.  Errors:
+ * MFA_ERR_INVALID (n < 0, null buffers with n > 0), MFA_ERR_MODEL
+ * (rational model), MFA_ERR_HANDLE, MFA_ERR_DEVICE. */
+mfa_status mfa_eval_hessian(mfa_ctx* ctx, int64_t model, int64_t n, const double* xyz_dev,
+                            float* value_dev, float* grad_dev, float* hess_dev, void* stream);
+
 /* Host-only validation, callable without a GPU; the same checks that
  * mfa_model_upload and mfa_render run before touching the device. */
 mfa_status mfa_validate_model(const mfa_model_desc* desc);

@@ -35,6 +35,7 @@ MFA_CAMERA_PERSP = 1
 
 EXPORTED = ("mfa_create", "mfa_destroy", "mfa_set_memory_budget", "mfa_model_upload",
             "mfa_model_free", "mfa_model_bytes", "mfa_render", "mfa_eval_points",
+            "mfa_eval_hessian",
             "mfa_kernel_timing", "mfa_kernel_times", "mfa_autotune", "mfa_batch_create",
             "mfa_batch_render",
             "mfa_batch_free", "mfa_server_create", "mfa_server_submit", "mfa_server_wait",
@@ -113,6 +114,7 @@ def _load():
         "mfa_render": (st, [vp, i64, C.POINTER(Camera), C.POINTER(TF), C.POINTER(RenderParams),
                             vp, vp, vp]),
         "mfa_eval_points": (st, [vp, i64, i64, vp, vp, vp, vp]),
+        "mfa_eval_hessian": (st, [vp, i64, i64, vp, vp, vp, vp, vp]),
         "mfa_kernel_timing": (st, [vp, C.c_int32]),
         "mfa_autotune": (st, [vp, i64, C.POINTER(Camera), C.POINTER(TF), C.POINTER(RenderParams),
                               vp, C.c_int32, vp, C.POINTER(TuneResult)]),
@@ -428,3 +430,15 @@ def mfa_eval_points(ctx: int, model: int, xyz, value, grad=None, stream=None) ->
     pv = _dev_tensor(value, torch.float32, (n,), "value")
     pg = None if grad is None else _dev_tensor(grad, torch.float32, (n, 3), "grad")
     _check(lib.mfa_eval_points(ctx, int(model), n, px, pv, pg, _stream_ptr(stream)))
+
+
+def mfa_eval_hessian(ctx: int, model: int, xyz, value, hess, grad=None, stream=None) -> None:
+    """Value (n,), world Hessian (n, 6: xx yy zz xy xz yz) and optionally the
+    world gradient (n, 3), float32, at world points xyz (n, 3) float64."""
+    import torch
+    n = int(xyz.shape[0])
+    px = _dev_tensor(xyz, torch.float64, (n, 3), "xyz")
+    pv = _dev_tensor(value, torch.float32, (n,), "value")
+    ph = _dev_tensor(hess, torch.float32, (n, 6), "hess")
+    pg = None if grad is None else _dev_tensor(grad, torch.float32, (n, 3), "grad")
+    _check(lib.mfa_eval_hessian(ctx, int(model), n, px, pv, pg, ph, _stream_ptr(stream)))

@@ -1224,8 +1224,13 @@ mfa_status mfa_batch_free(mfa_ctx* ctx, int64_t batch) {
   return MFA_OK;
 }
 
-mfa_status mfa_eval_points(mfa_ctx* ctx, int64_t model, int64_t n, const double* xyz_dev,
-                           float* value_dev, float* grad_dev, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Point queries: value, optional world gradient, optional world Hessian.
+mfa_status eval_common(mfa_ctx* ctx, int64_t model, int64_t n, const double* xyz_dev,
+                       float* value_dev, float* grad_dev, float* hess_dev, void* stream) {
   g_last_error.clear();
   if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
   auto it = ctx->models.find(model);
@@ -1246,10 +1251,33 @@ mfa_status mfa_eval_points(mfa_ctx* ctx, int64_t model, int64_t n, const double*
   a.xyz = xyz_dev;
   a.value = value_dev;
   a.grad = grad_dev;
+  a.hess = hess_dev;
   a.n = n;
   const hipError_t e = mfa::launch_eval(a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("eval launch", e));
   return MFA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mfa_status mfa_eval_points(mfa_ctx* ctx, int64_t model, int64_t n, const double* xyz_dev,
+                           float* value_dev, float* grad_dev, void* stream) {
+  return eval_common(ctx, model, n, xyz_dev, value_dev, grad_dev, nullptr, stream);
+}
+
+mfa_status mfa_eval_hessian(mfa_ctx* ctx, int64_t model, int64_t n, const double* xyz_dev,
+                            float* value_dev, float* grad_dev, float* hess_dev, void* stream) {
+  g_last_error.clear();
+  if (ctx != nullptr && hess_dev == nullptr && n > 0)
+    return fail(MFA_ERR_INVALID, "null Hessian buffer");
+  if (ctx != nullptr) {
+    auto it = ctx->models.find(model);
+    if (it != ctx->models.end() && it->second.md.rational)
+      return fail(MFA_ERR_MODEL, "Hessian queries need a non-rational model");
+  }
+  return eval_common(ctx, model, n, xyz_dev, value_dev, grad_dev, hess_dev, stream);
 }
 
 }  // extern "C"

@@ -230,6 +230,100 @@ __device__ __forceinline__ void axis_basis(int q, const float* __restrict__ row,
   }
 }
 
+// Degree-Q basis with first and second parametric derivatives.  The values
+// and first derivatives are those of basis_deg.  The second derivatives
+// apply the derivative formula twice: the step to degree Q-1 leaves
+// tmp1_r = N_{s-Q+2+r,Q-2} / (U_{s+r+1} - U_{s+2-Q+r}), so the degree Q-1
+// functions have derivatives D_r = (Q-1)(tmp1_{r-1} - tmp1_r), and
+// N''_{s-Q+r,Q} = Q (E_{r-1} - E_r) with E_r = D_r / (U_{s+r+1} - U_{s+1-Q+r}),
+// the reciprocal of the last step (entries outside the ranges are 0).  All
+// reciprocals come from the span's table row.
+template <int Q>
+__device__ __forceinline__ void basis_deg2(const float* __restrict__ row, float d, float* N,
+                                           float* dN, float* ddN) {
+  constexpr int S = table_stride(Q);
+  float t[S];
+  const float4* r4 = reinterpret_cast<const float4*>(row);
+#pragma unroll
+  for (int i = 0; i < S / 4; ++i) {
+    const float4 v = r4[i];
+    t[4 * i + 0] = v.x;
+    t[4 * i + 1] = v.y;
+    t[4 * i + 2] = v.z;
+    t[4 * i + 3] = v.w;
+  }
+  float left[Q + 1], right[Q + 1];
+  left[1] = d;
+#pragma unroll
+  for (int j = 2; j <= Q; ++j) left[j] = d + t[table_dl(Q, j)];
+#pragma unroll
+  for (int j = 1; j <= Q; ++j) right[j] = t[table_dr(Q, j)] - d;
+  float T[Q], T1[Q];
+#pragma unroll
+  for (int r = 0; r < Q; ++r) T1[r] = 0.0f;
+  N[0] = 1.0f;
+#pragma unroll
+  for (int q = 1; q <= Q; ++q) {
+    float saved = 0.0f;
+#pragma unroll
+    for (int r = 0; r < q; ++r) {
+      const float tmp = N[r] * t[table_inv(Q, q, r)];
+      N[r] = fmaf(right[r + 1], tmp, saved);
+      saved = left[q - r] * tmp;
+      if (q == Q) T[r] = tmp;
+      if (q == Q - 1) T1[r] = tmp;
+    }
+    N[q] = saved;
+  }
+  constexpr float fq = (float)Q;
+  dN[0] = -fq * T[0];
+#pragma unroll
+  for (int r = 1; r < Q; ++r) dN[r] = fq * (T[r - 1] - T[r]);
+  dN[Q] = fq * T[Q - 1];
+  if constexpr (Q == 1) {
+    ddN[0] = 0.0f;
+    ddN[1] = 0.0f;
+  } else {
+    constexpr float fq1 = (float)(Q - 1);
+    float E[Q];
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+      const float a = r > 0 ? T1[r - 1] : 0.0f;
+      const float b = r < Q - 1 ? T1[r] : 0.0f;
+      E[r] = fq1 * (a - b) * t[table_inv(Q, Q, r)];
+    }
+    ddN[0] = -fq * E[0];
+#pragma unroll
+    for (int r = 1; r < Q; ++r) ddN[r] = fq * (E[r - 1] - E[r]);
+    ddN[Q] = fq * E[Q - 1];
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void axis_basis2(int q, const float* __restrict__ row, float d,
+                                            float (&N)[P + 1], float (&dN)[P + 1],
+                                            float (&ddN)[P + 1]) {
+  if (q == P) {
+    basis_deg2<P>(row, d, N, dN, ddN);
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i <= P; ++i) {
+    N[i] = 0.0f;
+    dN[i] = 0.0f;
+    ddN[i] = 0.0f;
+  }
+  if constexpr (P >= 2) {
+    if (q == 1) basis_deg2<1>(row, d, N, dN, ddN);
+  }
+  if constexpr (P >= 3) {
+    if (q == 2) basis_deg2<2>(row, d, N, dN, ddN);
+  }
+  if constexpr (P >= 4) {
+    if (q == 3) basis_deg2<3>(row, d, N, dN, ddN);
+  }
+}
+
 // Uniform knots (U_{p+k} = k/m on an interior span, m = n - p): in the
 // normalised coordinate t = (u - U_s) m in [0,1) the p+1 non-zero
 // functions are the cardinal B-spline pieces and their t-derivatives.
@@ -398,6 +492,83 @@ __device__ __forceinline__ void contract(const float (&N)[3][P + 1], const float
   g[0] = gx;
   g[1] = gy;
   g[2] = gz;
+}
+
+// Value, gradient and the six second derivatives (uu, vv, ww, uv, uw, vw),
+// sum-factorised like contract(): each row is contracted with N, dN and ddN
+// along x; then along y the six combinations that keep at most two
+// derivative orders in total; then along z.
+template <int P, class Fetch>
+__device__ __forceinline__ void contract_hess(const float (&N)[3][P + 1],
+                                              const float (&dN)[3][P + 1],
+                                              const float (&ddN)[3][P + 1], Fetch fetch,
+                                              float& f, float (&g)[3], float (&h)[6]) {
+  // a[o][c][b]: row (b, c) with the x factor differentiated o times
+  float a[3][P + 1][P + 1];
+#pragma unroll
+  for (int c = 0; c <= P; ++c) {
+#pragma unroll
+    for (int b = 0; b <= P; ++b) {
+      float row[P + 1];
+      fetch(b, c, row);
+      float s0 = N[0][0] * row[0], s1 = dN[0][0] * row[0], s2 = ddN[0][0] * row[0];
+#pragma unroll
+      for (int i = 1; i <= P; ++i) {
+        s0 = fmaf(N[0][i], row[i], s0);
+        s1 = fmaf(dN[0][i], row[i], s1);
+        s2 = fmaf(ddN[0][i], row[i], s2);
+      }
+      a[0][c][b] = s0;
+      a[1][c][b] = s1;
+      a[2][c][b] = s2;
+    }
+  }
+  // y: (x order, y order) = (0,0) (1,0) (0,1) (2,0) (1,1) (0,2)
+  float y00[P + 1], y10[P + 1], y01[P + 1], y20[P + 1], y11[P + 1], y02[P + 1];
+#pragma unroll
+  for (int c = 0; c <= P; ++c) {
+    float s00 = 0.0f, s10 = 0.0f, s01 = 0.0f, s20 = 0.0f, s11 = 0.0f, s02 = 0.0f;
+#pragma unroll
+    for (int b = 0; b <= P; ++b) {
+      s00 = fmaf(N[1][b], a[0][c][b], s00);
+      s10 = fmaf(N[1][b], a[1][c][b], s10);
+      s01 = fmaf(dN[1][b], a[0][c][b], s01);
+      s20 = fmaf(N[1][b], a[2][c][b], s20);
+      s11 = fmaf(dN[1][b], a[1][c][b], s11);
+      s02 = fmaf(ddN[1][b], a[0][c][b], s02);
+    }
+    y00[c] = s00;
+    y10[c] = s10;
+    y01[c] = s01;
+    y20[c] = s20;
+    y11[c] = s11;
+    y02[c] = s02;
+  }
+  float v = 0.0f, gx = 0.0f, gy = 0.0f, gz = 0.0f;
+  float hxx = 0.0f, hyy = 0.0f, hzz = 0.0f, hxy = 0.0f, hxz = 0.0f, hyz = 0.0f;
+#pragma unroll
+  for (int c = 0; c <= P; ++c) {
+    v = fmaf(N[2][c], y00[c], v);
+    gx = fmaf(N[2][c], y10[c], gx);
+    gy = fmaf(N[2][c], y01[c], gy);
+    gz = fmaf(dN[2][c], y00[c], gz);
+    hxx = fmaf(N[2][c], y20[c], hxx);
+    hyy = fmaf(N[2][c], y02[c], hyy);
+    hzz = fmaf(ddN[2][c], y00[c], hzz);
+    hxy = fmaf(N[2][c], y11[c], hxy);
+    hxz = fmaf(dN[2][c], y10[c], hxz);
+    hyz = fmaf(dN[2][c], y01[c], hyz);
+  }
+  f = v;
+  g[0] = gx;
+  g[1] = gy;
+  g[2] = gz;
+  h[0] = hxx;
+  h[1] = hyy;
+  h[2] = hzz;
+  h[3] = hxy;
+  h[4] = hxz;
+  h[5] = hyz;
 }
 
 // ---------------------------------------------------------------------------
@@ -1411,6 +1582,50 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgsDev a) {
   }
 }
 
+// Value, world gradient and world Hessian at points (non-rational models):
+// the parametric second derivative d2f/du_k du_l is scaled by the two
+// reciprocal box extents.
+template <int P, int STORE>
+__global__ __launch_bounds__(256) void eval_hess_kernel(EvalArgsDev a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.n) return;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.m.ctrl, a.m.ctrl_bytes);
+  float N[3][P + 1], dN[3][P + 1], ddN[3][P + 1];
+  int w[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const AxisDev& A = a.m.ax[k];
+    const double x = a.xyz[3 * i + k];
+    const double u = fmin(fmax((x - A.lo) * A.inv_ext, 0.0), 1.0);
+    const int s = span_search(A.knots, A.n, A.p, u);
+    const float d = (float)(u - A.knots[s]);
+    const float* row = A.tab + (size_t)(s - A.p) * (size_t)table_stride(A.p);
+    axis_basis2<P>(A.p, row, d, N[k], dN[k], ddN[k]);
+    w[k] = s - A.p;
+  }
+  const int e0 = w[0] + a.m.nx * w[1] + a.m.nxy * w[2];
+  const int nx = a.m.nx, nxy = a.m.nxy;
+  float f, g[3], h[6];
+  contract_hess<P>(
+      N, dN, ddN,
+      [&](int b, int c, float (&row)[P + 1]) { load_row<P, STORE>(rs, e0 + b * nx + c * nxy, row); },
+      f, g, h);
+  const float sx = a.m.ax[0].gscale, sy = a.m.ax[1].gscale, sz = a.m.ax[2].gscale;
+  a.value[i] = f;
+  if (a.grad != nullptr) {
+    a.grad[3 * i + 0] = g[0] * sx;
+    a.grad[3 * i + 1] = g[1] * sy;
+    a.grad[3 * i + 2] = g[2] * sz;
+  }
+  float* o = a.hess + 6 * i;
+  o[0] = h[0] * (sx * sx);
+  o[1] = h[1] * (sy * sy);
+  o[2] = h[2] * (sz * sz);
+  o[3] = h[3] * (sx * sy);
+  o[4] = h[4] * (sx * sz);
+  o[5] = h[5] * (sy * sz);
+}
+
 __global__ void zero_counter(unsigned long long* p) {
   if (threadIdx.x == 0) p[0] = 0ull;
 }
@@ -1510,7 +1725,10 @@ hipError_t launch_render_p(const RenderArgsDev& a, hipStream_t st, const KernelE
 template <int P, int STORE>
 hipError_t launch_eval_p(const EvalArgsDev& a, hipStream_t st) {
   const unsigned blocks = (unsigned)((a.n + 255) / 256);
-  if (a.grad)
+  if (a.hess) {
+    if (a.m.rational) return hipErrorInvalidValue;   // refused on the host first
+    eval_hess_kernel<P, STORE><<<blocks, 256, 0, st>>>(a);
+  } else if (a.grad)
     a.m.rational ? eval_kernel<P, STORE, true, true><<<blocks, 256, 0, st>>>(a)
                  : eval_kernel<P, STORE, true, false><<<blocks, 256, 0, st>>>(a);
   else

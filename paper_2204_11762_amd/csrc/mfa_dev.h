@@ -137,6 +137,7 @@ struct EvalArgsDev {
   const double* xyz;
   float* value;
   float* grad;          // nullable
+  float* hess;          // nullable: n*6 second derivatives (xx, yy, zz, xy, xz, yz)
   int64_t n;
 };
 
