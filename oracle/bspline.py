@@ -390,18 +390,32 @@ def derivative_model(model: Model, axis: int):
     return Model(tuple(deg), tuple(knots), np.moveaxis(Q, 0, ctrl_ax), model.lo, model.hi)
 
 
+def hessian_models(model: Model) -> list:
+    """The six second-derivative splines (pair order of ``HESS_PAIRS``):
+    the model differentiated along a, then along b; ``None`` where the
+    derivative is identically 0."""
+    out = []
+    for a, b in HESS_PAIRS:
+        da = derivative_model(model, a)
+        out.append(None if da is None else derivative_model(da, b))
+    return out
+
+
+def hessian_from_models(models: list, uvw: np.ndarray) -> np.ndarray:
+    """Parametric Hessian (m, 6): the values of the six derivative splines."""
+    uvw = np.atleast_2d(np.asarray(uvw, dtype=np.float64))
+    out = np.zeros((len(uvw), 6))
+    for h, dab in enumerate(models):
+        if dab is not None:
+            out[:, h], _ = eval_local(dab, uvw)
+    return out
+
+
 def hessian_hodograph(model: Model, uvw: np.ndarray) -> np.ndarray:
     """Parametric Hessian (m, 6) through derivative control points: for each
     pair (a, b) the model is differentiated along a, then along b, and the
     resulting spline's value is evaluated."""
-    uvw = np.atleast_2d(np.asarray(uvw, dtype=np.float64))
-    out = np.zeros((len(uvw), 6))
-    for h, (a, b) in enumerate(HESS_PAIRS):
-        da = derivative_model(model, a)
-        dab = None if da is None else derivative_model(da, b)
-        if dab is not None:
-            out[:, h], _ = eval_local(dab, uvw)
-    return out
+    return hessian_from_models(hessian_models(model), uvw)
 
 
 def eval_world_hessian(model: Model, xyz: np.ndarray):

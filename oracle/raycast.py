@@ -26,7 +26,19 @@ with its reason in the design notes of the repository):
   the light is the headlight ``l = -F`` (F the viewing axis) unless a light
   direction is given; ``v = -d``;
 * premultiplied output ``(C_r, C_g, C_b, A)``, transparent black for rays
-  that miss the box.
+  that miss the box;
+* curvature transfer function (optional; the use the model's analytic
+  second derivatives are for): the principal curvatures of the isosurface
+  through the sample, ``k1 >= k2``, are the two tangential eigenvalues of
+  ``G = P H P / |g|`` (``H`` the world Hessian, ``P = I - n n^T``,
+  ``n = g / |g|``), i.e. ``k1,2 = (T +- |k1 - k2|) / 2`` with
+  ``T = trace G`` and ``|k1 - k2| = sqrt(2) |G - (T/2) P|_F`` (the traceless
+  tangential part, whose entries carry no cancellation, unlike
+  ``2 |G|_F^2 - T^2``; a sphere around lower values has ``k1 = k2 = 1/r``;
+  both are 0 where ``|g|^2 < 1e-12``); an
+  ``m x m`` RGBA table over ``[k_lo, k_hi]^2`` (k1 along the first table
+  axis) interpolated bilinearly with clamping gives the sample's colour,
+  and its opacity multiplies the value table's.
 
 Pixel-level arithmetic of the camera and slab steps is written operation by
 operation (no library reductions) so that the ray parameters are the plain
@@ -40,7 +52,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .bspline import Model, eval_local
+from .bspline import HESS_PAIRS, Model, eval_local, hessian_from_models, hessian_models
 
 GRAD_EPS = 1e-6
 
@@ -63,6 +75,13 @@ class TransferFunction:
     table: np.ndarray             # (n, 4) RGBA, float32 values
     v_lo: float
     v_hi: float
+
+
+@dataclass
+class CurvatureTF:
+    table: np.ndarray             # (m, m, 4) RGBA, float32 values; [i2, i1]: k2 row, k1 column
+    k_lo: float
+    k_hi: float
 
 
 @dataclass
@@ -179,6 +198,45 @@ def tf_lookup(tf: TransferFunction, v: np.ndarray) -> np.ndarray:
     return T[i] + t * (T[i + 1] - T[i])
 
 
+def principal_curvatures(g: np.ndarray, h: np.ndarray):
+    """(k1, k2), k1 >= k2, of the isosurfaces at points with world gradient
+    ``g`` (m, 3) and world Hessian ``h`` (m, 6: xx yy zz xy xz yz)."""
+    m = len(g)
+    H = np.zeros((m, 3, 3))
+    for c, (a, b) in enumerate(HESS_PAIRS):
+        H[:, a, b] = h[:, c]
+        H[:, b, a] = h[:, c]
+    g2 = (g * g).sum(axis=1)
+    ok = g2 >= 1e-12
+    glen = np.sqrt(np.where(ok, g2, 1.0))
+    n = g / glen[:, None]
+    P = np.eye(3)[None, :, :] - n[:, :, None] * n[:, None, :]
+    G = P @ H @ P / glen[:, None, None]
+    T = np.trace(G, axis1=1, axis2=2)
+    D = G - 0.5 * T[:, None, None] * P
+    disc = np.sqrt(2.0 * (D * D).sum(axis=(1, 2)))
+    k1 = np.where(ok, 0.5 * (T + disc), 0.0)
+    k2 = np.where(ok, 0.5 * (T - disc), 0.0)
+    return k1, k2
+
+
+def curvature_lookup(ctf: CurvatureTF, k1: np.ndarray, k2: np.ndarray) -> np.ndarray:
+    """RGBA by bilinear interpolation of the table over [k_lo, k_hi]^2."""
+    T = np.asarray(ctf.table, dtype=np.float64)
+    m = T.shape[0]
+
+    def coord(k):
+        x = np.clip((k - ctf.k_lo) / (ctf.k_hi - ctf.k_lo), 0.0, 1.0) * (m - 1)
+        i = np.minimum(np.floor(x).astype(np.int64), m - 2)
+        return i, (x - i)[:, None]
+
+    i1, t1 = coord(k1)
+    i2, t2 = coord(k2)
+    low = T[i2, i1] + t1 * (T[i2, i1 + 1] - T[i2, i1])
+    high = T[i2 + 1, i1] + t1 * (T[i2 + 1, i1 + 1] - T[i2 + 1, i1])
+    return low + t2 * (high - low)
+
+
 def ipow(x: np.ndarray, k: int) -> np.ndarray:
     """x**k for an integer k >= 0 by plain repeated multiplication."""
     out = np.ones_like(x)
@@ -215,13 +273,16 @@ class RenderResult:
 
 def render_pixels(model: Model, cam: Camera, tf: TransferFunction, prm: RenderParams,
                   pix: np.ndarray, o_max: float | None = None,
-                  chunk: int = 4096, field=None) -> RenderResult:
+                  chunk: int = 4096, field=None, curvature: CurvatureTF | None = None
+                  ) -> RenderResult:
     """Render the pixels with flat indices ``pix`` (row-major, row 0 top).
 
     ``field``, if given, replaces the MFA by a closed-form field: a callable
     taking world points (k, 3) and returning the values (k,) and world
     gradients (k, 3); the model then only supplies the box.  Used to render
-    the ground truth of the closed-form test fields."""
+    the ground truth of the closed-form test fields.  ``curvature``, if
+    given, colours each sample by the curvature table (non-rational models,
+    no ``field``)."""
     pix = np.asarray(pix, dtype=np.int64)
     m = len(pix)
     rgba = np.zeros((m, 4))
@@ -231,12 +292,12 @@ def render_pixels(model: Model, cam: Camera, tf: TransferFunction, prm: RenderPa
     omax = prm.ert_alpha if o_max is None else o_max
     for c0 in range(0, m, chunk):
         sl = slice(c0, min(m, c0 + chunk))
-        res = _render_chunk(model, cam, tf, prm, pix[sl], omax, field)
+        res = _render_chunk(model, cam, tf, prm, pix[sl], omax, field, curvature)
         rgba[sl], used[sl], nom[sl], near[sl] = res
     return RenderResult(rgba, used, nom, near)
 
 
-def _render_chunk(model, cam, tf, prm, pix, omax, field=None):
+def _render_chunk(model, cam, tf, prm, pix, omax, field=None, curvature=None):
     W = cam.width
     rows = pix // W
     cols = pix % W
@@ -258,6 +319,11 @@ def _render_chunk(model, cam, tf, prm, pix, omax, field=None):
         lvec = np.asarray(prm.light_dir, dtype=np.float64)
         lvec = lvec / math.sqrt(float((lvec * lvec).sum()))
     ext = hi - lo
+    if curvature is not None:
+        if field is not None or model.weights is not None:
+            raise ValueError("curvature rendering: non-rational MFA models only")
+        hmodels = hessian_models(model)
+        hscale = np.array([1.0 / (ext[a] * ext[b]) for a, b in HESS_PAIRS])
     s = 0
     while alive.any():
         idx = np.nonzero(alive)[0]
@@ -271,6 +337,12 @@ def _render_chunk(model, cam, tf, prm, pix, omax, field=None):
             f, g = field(lo + uvw * ext)
         col = tf_lookup(tf, f)
         rgb, alpha = col[:, :3], col[:, 3]
+        if curvature is not None:
+            hw = hessian_from_models(hmodels, uvw) * hscale
+            k1, k2 = principal_curvatures(g, hw)
+            cc = curvature_lookup(curvature, k1, k2)
+            rgb = cc[:, :3]
+            alpha = alpha * cc[:, 3]
         if prm.shading:
             light = np.broadcast_to(lvec, g.shape)
             rgb = phong(rgb, g, light, -d[idx], prm)
