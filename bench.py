@@ -426,6 +426,36 @@ def eval_leg(b, ctx, wk, steps: int, log, n_points: int = 1 << 24):
     return out
 
 
+def curvature_leg(b, ctx, wk, steps: int, log):
+    """The render frame with a curvature transfer function (principal
+    curvatures from the analytic Hessian colour the samples): FP32 storage,
+    one lane per ray, timed around the whole call on the caller's stream."""
+    import torch
+    ctf = wl.curvature_tf(32, -60.0, 60.0)
+    h = b.mfa_model_upload(ctx, wk.model, 0)
+    try:
+        W, H = wk.camera.width, wk.camera.height
+        out = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        b.mfa_render_curvature(ctx, h, wk.camera, wk.tf, ctf, wk.params, out, cnt)
+        torch.cuda.synchronize()
+        samples = int(cnt.item())
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            b.mfa_render_curvature(ctx, h, wk.camera, wk.tf, ctf, wk.params, out, cnt)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+    finally:
+        b.mfa_model_free(ctx, h)
+    log(f"curvature: {samples} samples in {ms:.3f} ms, {samples / (ms * 1e-3):.3e} samples/s")
+    return {"store": "fp32", "samples_per_frame": samples, "ms_per_frame": ms,
+            "samples_per_s": samples / (ms * 1e-3),
+            "table": "32x32 over k1, k2 in [-60, 60]"}
+
+
 def fields_leg(b, ctx, log, n_points: int = 1 << 22):
     """Sect. 4 shaped measurements on the Gaussian beam (Eq. 1) sampled on a
     128^3 grid: (i) point-query time against the number of control points
@@ -518,6 +548,8 @@ def main():
                     help="skip the closed-form field measurements")
     ap.add_argument("--eval-steps", type=int, default=10,
                     help="timed repetitions of the point-query micro-benchmark (0 = skip it)")
+    ap.add_argument("--curvature-steps", type=int, default=5,
+                    help="timed frames with the curvature transfer function (0 = skip them)")
     args = ap.parse_args()
 
     def log(msg):
@@ -579,6 +611,9 @@ def main():
         evals = None
         if args.eval_steps > 0:
             evals = eval_leg(b, ctx, wk, args.eval_steps, log)
+        curvature = None
+        if args.curvature_steps > 0:
+            curvature = curvature_leg(b, ctx, wk, args.curvature_steps, log)
         fields = None if args.no_fields else fields_leg(b, ctx, log)
         batch = None
         if args.batch_steps > 0:
@@ -646,6 +681,8 @@ def main():
     }
     if value_only is not None:
         line["value_only"] = value_only
+    if curvature is not None:
+        line["curvature"] = curvature
     if evals is not None:
         line["eval"] = evals
     if fields is not None:

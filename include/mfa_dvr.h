@@ -55,6 +55,7 @@ typedef int32_t mfa_status;
 
 #define MFA_MAX_DEGREE 4
 #define MFA_MAX_TF 4096
+#define MFA_MAX_CURV_TF 64
 
 /* MFA model (Sect. 2.3): per axis a degree p in [1, MFA_MAX_DEGREE], n >= p+1
  * control points and a knot vector of n+p+1 FP64 values that is
@@ -184,6 +185,36 @@ mfa_status mfa_model_bytes(mfa_ctx* ctx, int64_t model, int64_t* bytes_out);
 mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* camera, const mfa_tf* tf,
                       const mfa_render_params* params, float* rgba_dev, int64_t* samples_dev,
                       void* stream);
+
+/* Curvature transfer function: an m x m RGBA table (2 <= m <=
+ * MFA_MAX_CURV_TF) over [k_lo, k_hi] x [k_lo, k_hi] of the two principal
+ * curvatures k1 >= k2, entry (i2, i1) at rgba[4 (i2 m + i1)] (k1 along a
+ * row), bilinearly interpolated with clamping.  Host memory, copied before
+ * the call returns; opacities in [0, 1]. */
+typedef struct mfa_curvature_tf {
+  int32_t m;
+  int32_t reserved;
+  const float* rgba; /* m*m*4 floats */
+  double k_lo;
+  double k_hi;
+} mfa_curvature_tf;
+
+/* Render with a curvature transfer function, the use the model's analytic
+ * second derivatives serve (Sect. 3.1: the representation gives all
+ * derivatives together).  As mfa_render, except per sample: the value
+ * table gives an opacity; the principal curvatures of the isosurface
+ * through the sample, the two tangential eigenvalues of P H P / |g| (H the
+ * world Hessian, g the world gradient, P = I - n n^T, n = g / |g|; 0 where
+ * |g|^2 < 1e-12; a sphere around lower values has k1 = k2 = 1/r), index
+ * the curvature table, whose colour becomes the sample's colour and whose
+ * opacity multiplies the value table's; then Phong shading if enabled.
+ * One lane per ray with global-memory gathers.  Errors: as mfa_render,
+ * plus MFA_ERR_INVALID for a malformed curvature table and MFA_ERR_MODEL
+ * for a rational model. */
+mfa_status mfa_render_curvature(mfa_ctx* ctx, int64_t model, const mfa_camera* camera,
+                                const mfa_tf* tf, const mfa_curvature_tf* curvature,
+                                const mfa_render_params* params, float* rgba_dev,
+                                int64_t* samples_dev, void* stream);
 
 /* One request of a render batch: the arguments of one mfa_render call. */
 typedef struct mfa_render_request {

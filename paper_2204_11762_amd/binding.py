@@ -34,7 +34,8 @@ MFA_CAMERA_ORTHO = 0
 MFA_CAMERA_PERSP = 1
 
 EXPORTED = ("mfa_create", "mfa_destroy", "mfa_set_memory_budget", "mfa_model_upload",
-            "mfa_model_free", "mfa_model_bytes", "mfa_render", "mfa_eval_points",
+            "mfa_model_free", "mfa_model_bytes", "mfa_render", "mfa_render_curvature",
+            "mfa_eval_points",
             "mfa_eval_hessian",
             "mfa_kernel_timing", "mfa_kernel_times", "mfa_autotune", "mfa_batch_create",
             "mfa_batch_render",
@@ -67,6 +68,11 @@ class Camera(C.Structure):
 class TF(C.Structure):
     _fields_ = [("n", C.c_int32), ("reserved", C.c_int32), ("rgba", C.POINTER(C.c_float)),
                 ("v_lo", C.c_double), ("v_hi", C.c_double)]
+
+
+class CurvatureTF(C.Structure):
+    _fields_ = [("m", C.c_int32), ("reserved", C.c_int32), ("rgba", C.POINTER(C.c_float)),
+                ("k_lo", C.c_double), ("k_hi", C.c_double)]
 
 
 class RenderParams(C.Structure):
@@ -113,6 +119,9 @@ def _load():
         "mfa_model_bytes": (st, [vp, i64, C.POINTER(i64)]),
         "mfa_render": (st, [vp, i64, C.POINTER(Camera), C.POINTER(TF), C.POINTER(RenderParams),
                             vp, vp, vp]),
+        "mfa_render_curvature": (st, [vp, i64, C.POINTER(Camera), C.POINTER(TF),
+                                      C.POINTER(CurvatureTF), C.POINTER(RenderParams),
+                                      vp, vp, vp]),
         "mfa_eval_points": (st, [vp, i64, i64, vp, vp, vp, vp]),
         "mfa_eval_hessian": (st, [vp, i64, i64, vp, vp, vp, vp, vp]),
         "mfa_kernel_timing": (st, [vp, C.c_int32]),
@@ -310,6 +319,34 @@ def mfa_render(ctx: int, model: int, camera, tf, params, rgba, samples=None, str
     t, keep = tf_struct(tf)
     _check(lib.mfa_render(ctx, int(model), C.byref(camera_struct(camera)), C.byref(t),
                           C.byref(params_struct(params)), out, sp, _stream_ptr(stream)))
+
+
+def curvature_struct(ctf, keep: _Keep | None = None) -> tuple:
+    """(CurvatureTF, keep) from an object with table (m, m, 4), k_lo, k_hi."""
+    keep = keep or _Keep()
+    table = np.asarray(ctf.table, dtype=np.float32)
+    c = CurvatureTF()
+    c.m = int(table.shape[0])
+    c.rgba = keep.f32(table.reshape(-1))
+    c.k_lo = float(ctf.k_lo)
+    c.k_hi = float(ctf.k_hi)
+    return c, keep
+
+
+def mfa_render_curvature(ctx: int, model: int, camera, tf, curvature, params, rgba,
+                         samples=None, stream=None) -> None:
+    """Render with a curvature transfer function (``curvature``: table
+    (m, m, 4), k_lo, k_hi) into ``rgba`` (H, W, 4) float32."""
+    import torch
+    out = _dev_tensor(rgba, torch.float32, (camera.height, camera.width, 4), "rgba")
+    sp = None
+    if samples is not None:
+        sp = _dev_tensor(samples, torch.int64, (1,), "samples")
+    t, keep = tf_struct(tf)
+    c, keep = curvature_struct(curvature, keep)
+    _check(lib.mfa_render_curvature(ctx, int(model), C.byref(camera_struct(camera)), C.byref(t),
+                                    C.byref(c), C.byref(params_struct(params)), out, sp,
+                                    _stream_ptr(stream)))
 
 
 def mfa_autotune(ctx: int, model: int, camera, tf, params, rgba, repeats: int = 5, stream=None):

@@ -1028,6 +1028,61 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const 
   return MFA_OK;
 }
 
+mfa_status mfa_render_curvature(mfa_ctx* ctx, int64_t model, const mfa_camera* cam,
+                                const mfa_tf* tf, const mfa_curvature_tf* ctf,
+                                const mfa_render_params* prm, float* rgba_dev,
+                                int64_t* samples_dev, void* stream) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  auto it = ctx->models.find(model);
+  if (it == ctx->models.end()) return fail(MFA_ERR_HANDLE, "unknown model handle");
+  const DeviceModel& dm = it->second;
+  mfa_status st = check_request(dm, cam, tf, prm, rgba_dev);
+  if (st != MFA_OK) return st;
+  if (ctf == nullptr || ctf->rgba == nullptr || ctf->m < 2 || ctf->m > MFA_MAX_CURV_TF)
+    return fail(MFA_ERR_INVALID, "curvature table needs 2..64 entries per axis");
+  if (!(std::isfinite(ctf->k_lo) && std::isfinite(ctf->k_hi) && ctf->k_lo < ctf->k_hi))
+    return fail(MFA_ERR_INVALID, "curvature range needs finite k_lo < k_hi");
+  const int nent = ctf->m * ctf->m;
+  for (int i = 0; i < 4 * nent; ++i) {
+    if (!std::isfinite(ctf->rgba[i]) ||
+        (i % 4 == 3 && !(ctf->rgba[i] >= 0.0f && ctf->rgba[i] <= 1.0f)))
+      return fail(MFA_ERR_INVALID, "curvature table entries must be finite, opacities in [0, 1]");
+  }
+  if (dm.md.rational) return fail(MFA_ERR_MODEL, "curvature rendering needs a non-rational model");
+
+  DeviceGuard g(ctx->device);
+  if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
+  // room for both tables first: a full cache is released on insertion
+  if (ctx->n_tf + 2 > kMaxCachedTF) {
+    const hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("hipDeviceSynchronize", e));
+    ctx->free_tfs();
+  }
+  float4* tf_dev = nullptr;
+  st = tf_device(ctx, tf, &tf_dev);
+  if (st != MFA_OK) return st;
+  mfa_tf flat{};
+  flat.n = nent;
+  flat.rgba = ctf->rgba;
+  flat.v_lo = ctf->k_lo;
+  flat.v_hi = ctf->k_hi;
+  float4* ctf_dev = nullptr;
+  st = tf_device(ctx, &flat, &ctf_dev);
+  if (st != MFA_OK) return st;
+
+  mfa::RenderArgsDev a;
+  build_render_args(dm, cam, tf, prm, rgba_dev, samples_dev, tf_dev, a);
+  a.lds_bytes = 0;   // one lane per ray, data from global memory
+  a.ctf = ctf_dev;
+  a.ctf_m = ctf->m;
+  a.ctf_lo = float(ctf->k_lo);
+  a.ctf_scale = float(1.0 / (ctf->k_hi - ctf->k_lo));
+  const hipError_t e = mfa::launch_render(a, static_cast<hipStream_t>(stream), mfa::KernelEvents{});
+  if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("render launch", e));
+  return MFA_OK;
+}
+
 mfa_status mfa_kernel_timing(mfa_ctx* ctx, int32_t enable) {
   g_last_error.clear();
   if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");

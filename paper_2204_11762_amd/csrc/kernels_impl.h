@@ -625,6 +625,45 @@ __device__ __forceinline__ void query(const ModelDev& m, __amdgpu_buffer_rsrc_t 
   }
 }
 
+// Value f, world gradient g and world Hessian h (xx, yy, zz, xy, xz, yz) at
+// parameters u of a non-rational model; span[] as in query().  The
+// parametric second derivative d2f/du_k du_l is scaled by the two
+// reciprocal box extents.
+template <int P, int STORE>
+__device__ __forceinline__ void query_hess(const ModelDev& m, __amdgpu_buffer_rsrc_t rs,
+                                           const double (&u)[3], int (&span)[3], bool first,
+                                           float& f, float (&g)[3], float (&h)[6]) {
+  float N[3][P + 1], dN[3][P + 1], ddN[3][P + 1];
+  int w[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const AxisDev& A = m.ax[k];
+    const int s = first ? span_search(A.knots, A.n, A.p, u[k])
+                        : span_walk(A.knots, A.n, A.p, u[k], span[k]);
+    span[k] = s;
+    const float d = (float)(u[k] - A.knots[s]);
+    const float* row = A.tab + (size_t)(s - A.p) * (size_t)table_stride(A.p);
+    axis_basis2<P>(A.p, row, d, N[k], dN[k], ddN[k]);
+    w[k] = s - A.p;
+  }
+  const int e0 = w[0] + m.nx * w[1] + m.nxy * w[2];
+  const int nx = m.nx, nxy = m.nxy;
+  contract_hess<P>(
+      N, dN, ddN,
+      [&](int b, int c, float (&row)[P + 1]) { load_row<P, STORE>(rs, e0 + b * nx + c * nxy, row); },
+      f, g, h);
+  const float sx = m.ax[0].gscale, sy = m.ax[1].gscale, sz = m.ax[2].gscale;
+  g[0] *= sx;
+  g[1] *= sy;
+  g[2] *= sz;
+  h[0] *= sx * sx;
+  h[1] *= sy * sy;
+  h[2] *= sz * sz;
+  h[3] *= sx * sy;
+  h[4] *= sx * sz;
+  h[5] *= sy * sz;
+}
+
 // ---------------------------------------------------------------------------
 // rays
 // ---------------------------------------------------------------------------
@@ -742,11 +781,11 @@ __device__ __forceinline__ EyeTerms eye_terms(const RenderArgsDev& a, float vx, 
 
 // Transfer function and Phong shading of a sample of value f and world
 // gradient g: shaded colour (sr, sg, sb) and opacity alpha.
-template <bool SHADE, class TfFetch>
-__device__ __forceinline__ void shade_sample(const RenderArgsDev& a, float tf_lo, float tf_scale,
-                                             float f, const float (&g)[3], const EyeTerms& eye,
-                                             TfFetch tf, float& sr, float& sg, float& sb,
-                                             float& alpha) {
+// Transfer function of a sample of value f: colour (sr, sg, sb) and alpha.
+template <class TfFetch>
+__device__ __forceinline__ void tf_sample(const RenderArgsDev& a, float tf_lo, float tf_scale,
+                                          float f, TfFetch tf, float& sr, float& sg, float& sb,
+                                          float& alpha) {
   float x = (f - tf_lo) * tf_scale;
   x = fminf(fmaxf(x, 0.0f), 1.0f) * (float)(a.ntf - 1);
   const int i = min((int)x, a.ntf - 2);
@@ -757,6 +796,13 @@ __device__ __forceinline__ void shade_sample(const RenderArgsDev& a, float tf_lo
   sg = fmaf(t, c1.y - c0.y, c0.y);
   sb = fmaf(t, c1.z - c0.z, c0.z);
   alpha = fmaf(t, c1.w - c0.w, c0.w);
+}
+
+// Phong lighting of the colour (sr, sg, sb) with world gradient g.
+template <bool SHADE>
+__device__ __forceinline__ void phong_sample(const RenderArgsDev& a, const float (&g)[3],
+                                             const EyeTerms& eye, float& sr, float& sg,
+                                             float& sb) {
   if (SHADE) {
     // n = g / |g|; diffuse |n.l|; specular max(0, r.v)^k
     const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
@@ -771,6 +817,84 @@ __device__ __forceinline__ void shade_sample(const RenderArgsDev& a, float tf_lo
     sg = fminf(1.0f, fmaf(kdiff, sg, spec));
     sb = fminf(1.0f, fmaf(kdiff, sb, spec));
   }
+}
+
+template <bool SHADE, class TfFetch>
+__device__ __forceinline__ void shade_sample(const RenderArgsDev& a, float tf_lo, float tf_scale,
+                                             float f, const float (&g)[3], const EyeTerms& eye,
+                                             TfFetch tf, float& sr, float& sg, float& sb,
+                                             float& alpha) {
+  tf_sample(a, tf_lo, tf_scale, f, tf, sr, sg, sb, alpha);
+  phong_sample<SHADE>(a, g, eye, sr, sg, sb);
+}
+
+// Principal curvatures k1 >= k2 of the isosurface through a point with
+// world gradient g and world Hessian h (xx, yy, zz, xy, xz, yz): the two
+// tangential eigenvalues of G = P H P / |g|, P = I - n n^T, n = g / |g|.
+// T = trace G = (trace H - n.Hn) / |g|; the split |k1 - k2| is
+// sqrt(2) times the Frobenius norm of the traceless tangential part
+// G - (T/2) P, a sum of squares without cancellation.  0 where
+// |g|^2 < 1e-12.
+__device__ __forceinline__ void principal_curvatures(const float (&g)[3], const float (&h)[6],
+                                                     float& k1, float& k2) {
+  const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+  if (!(g2 >= 1e-12f)) {
+    k1 = 0.0f;
+    k2 = 0.0f;
+    return;
+  }
+  const float il = rsqrtf(g2);
+  const float n[3] = {g[0] * il, g[1] * il, g[2] * il};
+  const float H[3][3] = {{h[0], h[3], h[4]}, {h[3], h[1], h[5]}, {h[4], h[5], h[2]}};
+  float Hn[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Hn[i] = H[i][0] * n[0] + H[i][1] * n[1] + H[i][2] * n[2];
+  const float nHn = n[0] * Hn[0] + n[1] * Hn[1] + n[2] * Hn[2];
+  const float T = (h[0] + h[1] + h[2] - nHn) * il;
+  float S = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      const float php = H[i][j] - n[i] * Hn[j] - Hn[i] * n[j] + nHn * n[i] * n[j];
+      const float p = (i == j ? 1.0f : 0.0f) - n[i] * n[j];
+      const float d = php * il - 0.5f * T * p;
+      S += (i == j ? 1.0f : 2.0f) * d * d;
+    }
+  }
+  const float disc = sqrtf(2.0f * S);
+  k1 = 0.5f * (T + disc);
+  k2 = 0.5f * (T - disc);
+}
+
+// Bilinear lookup of the curvature table at (k1, k2), clamped to its range.
+__device__ __forceinline__ float4 curvature_lookup(const RenderArgsDev& a, float k1, float k2) {
+  const int m = a.ctf_m;
+  auto coord = [&](float k, int& i, float& t) {
+    const float x = fminf(fmaxf((k - a.ctf_lo) * a.ctf_scale, 0.0f), 1.0f) * (float)(m - 1);
+    i = min((int)x, m - 2);
+    t = x - (float)i;
+  };
+  int i1, i2;
+  float t1, t2;
+  coord(k1, i1, t1);
+  coord(k2, i2, t2);
+  const float4 c00 = a.ctf[i2 * m + i1], c01 = a.ctf[i2 * m + i1 + 1];
+  const float4 c10 = a.ctf[(i2 + 1) * m + i1], c11 = a.ctf[(i2 + 1) * m + i1 + 1];
+  float4 lo, hi, o;
+  lo.x = fmaf(t1, c01.x - c00.x, c00.x);
+  lo.y = fmaf(t1, c01.y - c00.y, c00.y);
+  lo.z = fmaf(t1, c01.z - c00.z, c00.z);
+  lo.w = fmaf(t1, c01.w - c00.w, c00.w);
+  hi.x = fmaf(t1, c11.x - c10.x, c10.x);
+  hi.y = fmaf(t1, c11.y - c10.y, c10.y);
+  hi.z = fmaf(t1, c11.z - c10.z, c10.z);
+  hi.w = fmaf(t1, c11.w - c10.w, c10.w);
+  o.x = fmaf(t2, hi.x - lo.x, lo.x);
+  o.y = fmaf(t2, hi.y - lo.y, lo.y);
+  o.z = fmaf(t2, hi.z - lo.z, lo.z);
+  o.w = fmaf(t2, hi.w - lo.w, lo.w);
+  return o;
 }
 
 // One front-to-back compositing step; false once the accumulated opacity
@@ -799,7 +923,7 @@ __device__ __forceinline__ void count_samples(const RenderArgsDev& a, int count,
 
 // Used when the knots or transfer function of a request do not fit the LDS
 // budget of the brick kernel.
-template <int P, int STORE, bool SHADE, bool RAT>
+template <int P, int STORE, bool SHADE, bool RAT, bool CURV>
 __global__ __launch_bounds__(256) void render_global_kernel(RenderArgsDev a) {
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
@@ -822,10 +946,25 @@ __global__ __launch_bounds__(256) void render_global_kernel(RenderArgsDev a) {
       double u[3];
       sample_params(a.cam, ray, s, u);
       float f, g[3];
-      query<P, STORE, SHADE, RAT>(a.m, rs, rsw, u, span, s == 0, f, g);
-      ++count;
       float sr, sg, sb, alpha;
-      shade_sample<SHADE>(a, a.tf_lo, a.tf_scale, f, g, eye, tf, sr, sg, sb, alpha);
+      if constexpr (CURV) {
+        // curvature transfer function: the curvature table's colour, its
+        // opacity times the value table's
+        float h[6], k1, k2;
+        query_hess<P, STORE>(a.m, rs, u, span, s == 0, f, g, h);
+        tf_sample(a, a.tf_lo, a.tf_scale, f, tf, sr, sg, sb, alpha);
+        principal_curvatures(g, h, k1, k2);
+        const float4 cc = curvature_lookup(a, k1, k2);
+        sr = cc.x;
+        sg = cc.y;
+        sb = cc.z;
+        alpha *= cc.w;
+        phong_sample<SHADE>(a, g, eye, sr, sg, sb);
+      } else {
+        query<P, STORE, SHADE, RAT>(a.m, rs, rsw, u, span, s == 0, f, g);
+        shade_sample<SHADE>(a, a.tf_lo, a.tf_scale, f, g, eye, tf, sr, sg, sb, alpha);
+      }
+      ++count;
       if (!composite_one(a.ert, sr, sg, sb, alpha, cr, cg, cb, A)) break;
     }
     float4 o;
@@ -1582,48 +1721,30 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgsDev a) {
   }
 }
 
-// Value, world gradient and world Hessian at points (non-rational models):
-// the parametric second derivative d2f/du_k du_l is scaled by the two
-// reciprocal box extents.
+// Value, world gradient and world Hessian at points (non-rational models).
 template <int P, int STORE>
 __global__ __launch_bounds__(256) void eval_hess_kernel(EvalArgsDev a) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= a.n) return;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.m.ctrl, a.m.ctrl_bytes);
-  float N[3][P + 1], dN[3][P + 1], ddN[3][P + 1];
-  int w[3];
+  double u[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const AxisDev& A = a.m.ax[k];
     const double x = a.xyz[3 * i + k];
-    const double u = fmin(fmax((x - A.lo) * A.inv_ext, 0.0), 1.0);
-    const int s = span_search(A.knots, A.n, A.p, u);
-    const float d = (float)(u - A.knots[s]);
-    const float* row = A.tab + (size_t)(s - A.p) * (size_t)table_stride(A.p);
-    axis_basis2<P>(A.p, row, d, N[k], dN[k], ddN[k]);
-    w[k] = s - A.p;
+    u[k] = fmin(fmax((x - a.m.ax[k].lo) * a.m.ax[k].inv_ext, 0.0), 1.0);
   }
-  const int e0 = w[0] + a.m.nx * w[1] + a.m.nxy * w[2];
-  const int nx = a.m.nx, nxy = a.m.nxy;
+  int span[3];
   float f, g[3], h[6];
-  contract_hess<P>(
-      N, dN, ddN,
-      [&](int b, int c, float (&row)[P + 1]) { load_row<P, STORE>(rs, e0 + b * nx + c * nxy, row); },
-      f, g, h);
-  const float sx = a.m.ax[0].gscale, sy = a.m.ax[1].gscale, sz = a.m.ax[2].gscale;
+  query_hess<P, STORE>(a.m, rs, u, span, true, f, g, h);
   a.value[i] = f;
   if (a.grad != nullptr) {
-    a.grad[3 * i + 0] = g[0] * sx;
-    a.grad[3 * i + 1] = g[1] * sy;
-    a.grad[3 * i + 2] = g[2] * sz;
+    a.grad[3 * i + 0] = g[0];
+    a.grad[3 * i + 1] = g[1];
+    a.grad[3 * i + 2] = g[2];
   }
   float* o = a.hess + 6 * i;
-  o[0] = h[0] * (sx * sx);
-  o[1] = h[1] * (sy * sy);
-  o[2] = h[2] * (sz * sz);
-  o[3] = h[3] * (sx * sy);
-  o[4] = h[4] * (sx * sz);
-  o[5] = h[5] * (sy * sz);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) o[c] = h[c];
 }
 
 __global__ void zero_counter(unsigned long long* p) {
@@ -1669,10 +1790,14 @@ hipError_t launch_render_ps(const RenderArgsDev& a, hipStream_t st, const Kernel
   hipError_t e = mark(ev.begin, st);
   if (e != hipSuccess) return e;
   const dim3 grid((a.width + 15) / 16, (a.height + 15) / 16);
-  if (a.m.rational)
-    render_global_kernel<P, STORE, SHADE, true><<<grid, 256, 0, st>>>(a);
-  else
-    render_global_kernel<P, STORE, SHADE, false><<<grid, 256, 0, st>>>(a);
+  if (a.ctf != nullptr) {
+    if (a.m.rational) return hipErrorInvalidValue;   // refused on the host first
+    render_global_kernel<P, STORE, SHADE, false, true><<<grid, 256, 0, st>>>(a);
+  } else if (a.m.rational) {
+    render_global_kernel<P, STORE, SHADE, true, false><<<grid, 256, 0, st>>>(a);
+  } else {
+    render_global_kernel<P, STORE, SHADE, false, false><<<grid, 256, 0, st>>>(a);
+  }
   e = hipGetLastError();
   return e == hipSuccess ? mark(ev.end, st) : e;
 }

@@ -113,6 +113,12 @@ struct RenderArgsDev {
   int32_t eq;           // 1: every axis has degree pmax (degree fixed at compile time)
   float* out;           // width*height*4
   unsigned long long* samples;  // nullable
+  // curvature transfer function (nullptr: off): ctf_m x ctf_m RGBA entries,
+  // k1 along a row; k = clamp((kappa - ctf_lo) * ctf_scale, 0, 1) (ctf_m - 1)
+  const float4* ctf;
+  int32_t ctf_m;
+  float ctf_lo;
+  float ctf_scale;
   // LDS-brick ray marcher (render_brick_kernel); unused by the fallback
   int32_t spr;          // samples per round: each wave stages one brick per round
   int32_t brick_cap;    // floats of LDS per wave for its brick (multiple of 4)

@@ -77,6 +77,32 @@ class TFSpec:
 
 
 @dataclass
+class CurvatureTFSpec:
+    table: np.ndarray                  # float32 (m, m, 4) RGBA: [i2, i1], k2 row, k1 column
+    k_lo: float
+    k_hi: float
+
+
+def curvature_tf(m: int = 32, k_lo: float = -4.0, k_hi: float = 4.0) -> CurvatureTFSpec:
+    """A table over the principal curvatures (k1, k2) in the manner of
+    curvature-based transfer functions: red where both are positive (the
+    surface curves around lower values), blue where both are negative, green
+    on saddles, grey near flat; opacity grows with sqrt(k1^2 + k2^2) so that
+    flat regions stay faint."""
+    k = np.linspace(k_lo, k_hi, m)
+    k2, k1 = np.meshgrid(k, k, indexing="ij")
+    scale = max(abs(k_lo), abs(k_hi))
+    mag = np.sqrt(k1 ** 2 + k2 ** 2) / scale
+    conv = np.clip(np.minimum(k1, k2) / scale, 0, 1)
+    conc = np.clip(-np.maximum(k1, k2) / scale, 0, 1)
+    sadl = np.clip(np.minimum(k1, -k2) / scale, 0, 1) * (k1 * k2 < 0)
+    grey = 0.5 * (1.0 - np.clip(conv + conc + sadl, 0, 1))
+    table = np.stack([conv + grey, sadl + grey, conc + grey,
+                      0.15 + 0.85 * np.clip(mag, 0, 1)], axis=-1)
+    return CurvatureTFSpec(np.clip(table, 0, 1).astype(np.float32), float(k_lo), float(k_hi))
+
+
+@dataclass
 class ParamSpec:
     step: float
     ert_alpha: float = 0.99

@@ -68,32 +68,37 @@ class ImageReport:
     samples_slack: int
 
 
-def oracle_on_pixels(wk, pix, o_max=None, model=None, ert=None):
+def oracle_on_pixels(wk, pix, o_max=None, model=None, ert=None, curvature=None):
     M, cam, tf, prm = oracle_workload(wk)
     if model is not None:
         M = model
     if ert is not None:
         prm = copy.copy(prm)
         prm.ert_alpha = ert
-    return orc.render_pixels(M, cam, tf, prm, pix, o_max=o_max)
+    ctf = None if curvature is None else orc.CurvatureTF(
+        np.asarray(curvature.table, dtype=np.float32), curvature.k_lo, curvature.k_hi)
+    return orc.render_pixels(M, cam, tf, prm, pix, o_max=o_max, curvature=ctf)
 
 
-def compare_image(gpu_img, gpu_count, wk, pix, tau, px_tol, model=None, count_exact=True):
+def compare_image(gpu_img, gpu_count, wk, pix, tau, px_tol, model=None, count_exact=True,
+                  curvature=None):
     """Compare GPU pixels (flat indices ``pix``) with the oracle.  A pixel whose
     accumulated opacity comes within ``tau`` of the termination threshold may
     stop one or more samples earlier or later; it must then lie between the
     oracle renders with threshold O_max - tau and O_max + tau."""
     H, W = wk.camera.height, wk.camera.width
     flat = gpu_img.reshape(-1, 4)[pix]
-    nom = oracle_on_pixels(wk, pix, model=model)
+    nom = oracle_on_pixels(wk, pix, model=model, curvature=curvature)
     err = flat - nom.rgba
     amb = nom.near_threshold <= tau
     bad = np.abs(err).max(axis=1) > px_tol
     slack = 0
     if amb.any():
         ip = pix[amb]
-        early = oracle_on_pixels(wk, ip, o_max=wk.params.ert_alpha - tau, model=model)
-        late = oracle_on_pixels(wk, ip, o_max=wk.params.ert_alpha + tau, model=model)
+        early = oracle_on_pixels(wk, ip, o_max=wk.params.ert_alpha - tau, model=model,
+                                 curvature=curvature)
+        late = oracle_on_pixels(wk, ip, o_max=wk.params.ert_alpha + tau, model=model,
+                                curvature=curvature)
         lo = np.minimum(early.rgba, late.rgba) - px_tol
         hi = np.maximum(early.rgba, late.rgba) + px_tol
         inside = ((flat[amb] >= lo) & (flat[amb] <= hi)).all(axis=1)

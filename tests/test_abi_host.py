@@ -205,6 +205,8 @@ def test_null_context_and_handles(b):
     assert b.lib.mfa_model_free(None, 1) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_set_memory_budget(None, 0) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_render(None, 1, None, None, None, None, None, None) == b.MFA_ERR_HANDLE
+    assert b.lib.mfa_render_curvature(None, 1, None, None, None, None, None, None,
+                                      None) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_eval_points(None, 1, 0, None, None, None, None) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_eval_hessian(None, 1, 4, None, None, None, None, None) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_kernel_timing(None, 1) == b.MFA_ERR_HANDLE
