@@ -342,9 +342,9 @@ mfa_status mfa_server_wait(mfa_server* server, int64_t ticket, int64_t timeout_u
  * server.  Null is accepted and ignored. */
 mfa_status mfa_server_destroy(mfa_server* server);
 
-/* Kernel timing for measurement.  While enabled, every mfa_render call
- * records a pair of HIP events on its stream immediately around the
- * ray-casting kernel (after the per-frame tile planning), so that the
+/* Kernel timing for measurement.  While enabled, every mfa_render and
+ * mfa_render_curvature call records a pair of HIP events on its stream
+ * immediately around the ray-casting kernel (after the per-frame tile planning), so that the
  * kernel's own duration can be read back; at most 65536 launches are
  * recorded, later ones are not.  Enabling or disabling discards what was
  * recorded.  Errors: MFA_ERR_HANDLE. */

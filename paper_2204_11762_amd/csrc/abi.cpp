@@ -979,6 +979,33 @@ class BatchBuilder {
 
 }  // namespace
 
+namespace {
+
+// Launch one frame; while kernel timing is on, with a pair of HIP events
+// around the ray-casting kernel (at most kMaxTimedLaunches per record).
+mfa_status launch_timed(mfa_ctx* ctx, const mfa::RenderArgsDev& a, void* stream) {
+  mfa::KernelEvents ev;
+  if (ctx->timing && ctx->timed < kMaxTimedLaunches) {
+    if (ctx->timed == ctx->events.size()) {
+      mfa::KernelEvents fresh;
+      hipError_t e = hipEventCreate(&fresh.begin);
+      if (e == hipSuccess) {
+        e = hipEventCreate(&fresh.end);
+        if (e != hipSuccess) (void)hipEventDestroy(fresh.begin);
+      }
+      if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("hipEventCreate", e));
+      ctx->events.push_back(fresh);
+    }
+    ev = ctx->events[ctx->timed];
+  }
+  const hipError_t e = mfa::launch_render(a, static_cast<hipStream_t>(stream), ev);
+  if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("render launch", e));
+  if (ev.begin != nullptr) ctx->timed += 1;
+  return MFA_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const mfa_tf* tf,
@@ -1008,24 +1035,7 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const 
     a.tile_order = base + ctx->scratch_tiles;
     a.tile_hist = reinterpret_cast<unsigned*>(base + 2 * ctx->scratch_tiles);
   }
-  mfa::KernelEvents ev;
-  if (ctx->timing && ctx->timed < kMaxTimedLaunches) {
-    if (ctx->timed == ctx->events.size()) {
-      mfa::KernelEvents fresh;
-      hipError_t e = hipEventCreate(&fresh.begin);
-      if (e == hipSuccess) {
-        e = hipEventCreate(&fresh.end);
-        if (e != hipSuccess) (void)hipEventDestroy(fresh.begin);
-      }
-      if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("hipEventCreate", e));
-      ctx->events.push_back(fresh);
-    }
-    ev = ctx->events[ctx->timed];
-  }
-  const hipError_t e = mfa::launch_render(a, static_cast<hipStream_t>(stream), ev);
-  if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("render launch", e));
-  if (ev.begin != nullptr) ctx->timed += 1;
-  return MFA_OK;
+  return launch_timed(ctx, a, stream);
 }
 
 mfa_status mfa_render_curvature(mfa_ctx* ctx, int64_t model, const mfa_camera* cam,
@@ -1078,9 +1088,7 @@ mfa_status mfa_render_curvature(mfa_ctx* ctx, int64_t model, const mfa_camera* c
   a.ctf_m = ctf->m;
   a.ctf_lo = float(ctf->k_lo);
   a.ctf_scale = float(1.0 / (ctf->k_hi - ctf->k_lo));
-  const hipError_t e = mfa::launch_render(a, static_cast<hipStream_t>(stream), mfa::KernelEvents{});
-  if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("render launch", e));
-  return MFA_OK;
+  return launch_timed(ctx, a, stream);
 }
 
 mfa_status mfa_kernel_timing(mfa_ctx* ctx, int32_t enable) {

@@ -167,3 +167,29 @@ def test_curvature_errors(mfa):
         assert e.value.status == b.MFA_ERR_MODEL
     finally:
         b.mfa_model_free(ctx, hr)
+
+
+def test_curvature_frames_are_timed(mfa):
+    """Kernel timing records curvature frames like plain ones, without
+    changing the image."""
+    torch = torch_mod()
+    b, ctx = mfa
+    spec = _sphere_spec(57)
+    wk = _workload(spec, size=32)
+    ctf = wl.curvature_tf(16, 0.0, 2.5)
+    h = b.mfa_model_upload(ctx, spec)
+    try:
+        ref, _ = gpu_curvature_render(b, ctx, h, wk, ctf)
+        out = torch.zeros((32, 32, 4), dtype=torch.float32, device="cuda")
+        b.mfa_kernel_timing(ctx, True)
+        for _ in range(2):
+            b.mfa_render_curvature(ctx, h, wk.camera, wk.tf, ctf, wk.params, out)
+        b.mfa_render(ctx, h, wk.camera, wk.tf, wk.params, out)
+        ms = b.mfa_kernel_times(ctx)
+        b.mfa_kernel_timing(ctx, False)
+        assert ms.shape == (3,) and np.all(ms > 0)
+        b.mfa_render_curvature(ctx, h, wk.camera, wk.tf, ctf, wk.params, out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy().astype(np.float64), ref)
+    finally:
+        b.mfa_model_free(ctx, h)
