@@ -1091,6 +1091,42 @@ mfa_status mfa_render_curvature(mfa_ctx* ctx, int64_t model, const mfa_camera* c
   return launch_timed(ctx, a, stream);
 }
 
+mfa_status mfa_measure_fma_peak(mfa_ctx* ctx, double* tflops) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  if (tflops == nullptr) return fail(MFA_ERR_INVALID, "null tflops");
+  DeviceGuard g(ctx->device);
+  if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
+  int cus = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+  if (e != hipSuccess || cus <= 0) return fail(MFA_ERR_DEVICE, hip_msg("CU count", e));
+  const int blocks = 16 * cus;   // 16 workgroups of 4 waves per CU
+  const int iters = 20000;
+  float* out = nullptr;
+  e = hipMalloc(reinterpret_cast<void**>(&out), sizeof(float) * size_t(blocks));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MFA_ERR_NOMEM, hip_msg("hipMalloc (FMA probe)", e));
+  }
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  float ms = 0.0f;
+  e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  if (e == hipSuccess) e = mfa::launch_fma_peak(out, blocks, 100, nullptr);   // warm-up
+  if (e == hipSuccess) e = hipEventRecord(t0, nullptr);
+  if (e == hipSuccess) e = mfa::launch_fma_peak(out, blocks, iters, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(t1, nullptr);
+  if (e == hipSuccess) e = hipEventSynchronize(t1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+  if (t0 != nullptr) (void)hipEventDestroy(t0);
+  if (t1 != nullptr) (void)hipEventDestroy(t1);
+  (void)hipFree(out);
+  if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("FMA probe", e));
+  const double flops = double(blocks) * 256.0 * double(iters) * 8.0 * 2.0;
+  *tflops = flops / (double(ms) * 1e-3) / 1e12;
+  return MFA_OK;
+}
+
 mfa_status mfa_kernel_timing(mfa_ctx* ctx, int32_t enable) {
   g_last_error.clear();
   if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");

@@ -20,6 +20,11 @@ extern template hipError_t eval_for_store<0>(const EvalArgsDev&, hipStream_t);
 extern template hipError_t eval_for_store<1>(const EvalArgsDev&, hipStream_t);
 extern template hipError_t eval_for_store<2>(const EvalArgsDev&, hipStream_t);
 
+hipError_t launch_fma_peak(float* out, int blocks, int iters, hipStream_t st) {
+  fma_peak_kernel<<<blocks, 256, 0, st>>>(out, iters, 0.999999f, 1e-6f);
+  return hipGetLastError();
+}
+
 hipError_t launch_render(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
   if (a.samples != nullptr) {
     zero_counter<<<1, 64, 0, st>>>(a.samples);

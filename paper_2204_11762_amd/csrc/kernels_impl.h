@@ -1747,6 +1747,25 @@ __global__ __launch_bounds__(256) void eval_hess_kernel(EvalArgsDev a) {
   for (int c = 0; c < 6; ++c) o[c] = h[c];
 }
 
+// FP32 FMA issue ceiling: eight independent FMA chains per lane, so that
+// the issue rate, not the FMA latency, bounds the loop.  The values stay
+// finite (a contraction towards b / (1 - a)); a result is stored only if it
+// takes a value it cannot take, so the loop is not removed.
+__global__ __launch_bounds__(256) void fma_peak_kernel(float* out, int iters, float a, float b) {
+  float x[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = (float)(threadIdx.x + k);
+#pragma unroll 4
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = fmaf(x[k], a, b);
+  }
+  float s = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += x[k];
+  if (s == -1.0f) out[blockIdx.x] = s;
+}
+
 __global__ void zero_counter(unsigned long long* p) {
   if (threadIdx.x == 0) p[0] = 0ull;
 }

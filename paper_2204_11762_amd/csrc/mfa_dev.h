@@ -24,7 +24,7 @@ constexpr int kTileH = 64 / kLanesPerRay / kTileW;
 // kMaxRegion and small enough for about 64 regions, so that every group
 // has work on small frames too.
 constexpr int kXcdGroups = 8;
-constexpr int kMaxRegion = 4;
+constexpr int kMaxRegion = 2;
 // Counters of the tile sort (kXcdGroups x 512 buckets).
 constexpr int kPlanHistWords = kXcdGroups * 512;
 
@@ -180,5 +180,7 @@ struct KernelEvents {
 hipError_t launch_render(const RenderArgsDev& a, hipStream_t stream, const KernelEvents& ev);
 hipError_t launch_render_batch(const BatchDev& b, const BatchKey& k, hipStream_t stream);
 hipError_t launch_eval(const EvalArgsDev& a, hipStream_t stream);
+// FP32 FMA micro-loop: blocks x 256 threads, iters x 8 FMA each
+hipError_t launch_fma_peak(float* out, int blocks, int iters, hipStream_t stream);
 
 }  // namespace mfa
