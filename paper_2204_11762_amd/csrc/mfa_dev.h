@@ -24,7 +24,7 @@ constexpr int kTileH = 64 / kLanesPerRay / kTileW;
 // kMaxRegion and small enough for about 64 regions, so that every group
 // has work on small frames too.
 constexpr int kXcdGroups = 8;
-constexpr int kMaxRegion = 2;
+constexpr int kMaxRegion = 4;
 // Counters of the tile sort (kXcdGroups x 512 buckets).
 constexpr int kPlanHistWords = kXcdGroups * 512;
 
