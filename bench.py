@@ -608,6 +608,9 @@ def main():
                           "kernel_mean_ms": float(vleg["kern"].mean()),
                           "note": "value only (no gradient, no Phong); a different frame, since "
                                   "unshaded colours change where rays terminate"}
+        # the attainable FP32 vector rate without packed FP32 (micro-loop)
+        fma_tflops = b.mfa_measure_fma_peak(ctx)
+        log(f"FP32 FMA micro-loop: {fma_tflops:.1f} TFLOP/s")
         evals = None
         if args.eval_steps > 0:
             evals = eval_leg(b, ctx, wk, args.eval_steps, log)
@@ -676,7 +679,15 @@ def main():
                      "kernel": "render_brick_kernel<3,%d,shade,fast,eq,4>" % (
                          {"fp32": 0, "bf16": 1, "fp16": 2}[args.store]),
                      "kernel_ms": kern_ms, "flops_per_sample": flops_per_sample(p),
-                     "flops_per_launch": flops},
+                     "flops_per_launch": flops,
+                     "measured_fma_tflops": fma_tflops,
+                     "frac_of_measured_fma": achieved / (fma_tflops * 1e12),
+                     "ert_off": None if head["nominal"] is None else {
+                         "achieved": head["nominal"] * flops_per_sample(p)
+                         / (head["nominal_ms"] * 1e-3) / 1e12,
+                         "frac": head["nominal"] * flops_per_sample(p)
+                         / (head["nominal_ms"] * 1e-3) / PEAK_FP32_VALU,
+                         "note": "the same frame with termination off, whole call timed"}},
         "legs": {k: summary(v, k) for k, v in legs.items()},
     }
     if value_only is not None:

@@ -358,6 +358,15 @@ mfa_status mfa_kernel_timing(mfa_ctx* ctx, int32_t enable);
  * cap < 0, null ms_host with cap > 0), MFA_ERR_DEVICE. */
 mfa_status mfa_kernel_times(mfa_ctx* ctx, float* ms_host, int64_t cap, int64_t* count);
 
+/* Measured FP32 fused multiply-add rate of the context's device, the
+ * attainable ceiling of the FP32 vector roofline without packed FP32: a
+ * micro-loop of eight independent FMA chains per lane on 16 workgroups of
+ * 256 threads per compute unit, timed with HIP events on the null stream.
+ * Synchronous; writes TFLOP/s (2 flops per FMA) to *tflops.  Errors:
+ * MFA_ERR_HANDLE, MFA_ERR_INVALID (null tflops), MFA_ERR_NOMEM,
+ * MFA_ERR_DEVICE. */
+mfa_status mfa_measure_fma_peak(mfa_ctx* ctx, double* tflops);
+
 /* Value and world-space gradient queries (Algorithm 1: value query and
  * gradient query, all three derivatives at once) at n world points
  * xyz_dev (n*3 FP64, point-major).  Points outside the box are clamped to

@@ -35,13 +35,11 @@ MFA_CAMERA_PERSP = 1
 
 EXPORTED = ("mfa_create", "mfa_destroy", "mfa_set_memory_budget", "mfa_model_upload",
             "mfa_model_free", "mfa_model_bytes", "mfa_render", "mfa_render_curvature",
-            "mfa_eval_points",
-            "mfa_eval_hessian",
-            "mfa_kernel_timing", "mfa_kernel_times", "mfa_autotune", "mfa_batch_create",
-            "mfa_batch_render",
+            "mfa_eval_points", "mfa_eval_hessian", "mfa_kernel_timing", "mfa_kernel_times",
+            "mfa_measure_fma_peak", "mfa_autotune", "mfa_batch_create", "mfa_batch_render",
             "mfa_batch_free", "mfa_server_create", "mfa_server_submit", "mfa_server_wait",
-            "mfa_server_destroy", "mfa_validate_model",
-            "mfa_validate_render", "mfa_last_error", "mfa_version")
+            "mfa_server_destroy", "mfa_validate_model", "mfa_validate_render", "mfa_last_error",
+            "mfa_version")
 
 
 class MFAError(RuntimeError):
@@ -135,6 +133,7 @@ def _load():
         "mfa_server_wait": (st, [vp, i64, i64, C.POINTER(RequestInfo)]),
         "mfa_server_destroy": (st, [vp]),
         "mfa_kernel_times": (st, [vp, vp, i64, C.POINTER(i64)]),
+        "mfa_measure_fma_peak": (st, [vp, C.POINTER(C.c_double)]),
         "mfa_validate_model": (st, [C.POINTER(ModelDesc)]),
         "mfa_validate_render": (st, [C.POINTER(Camera), C.POINTER(TF), C.POINTER(RenderParams)]),
         "mfa_last_error": (C.c_char_p, []),
@@ -446,6 +445,13 @@ def mfa_kernel_timing(ctx: int, enable: bool) -> None:
     """Start (True) or stop (False) recording the ray-casting kernel's
     duration on every later mfa_render call; either discards the record."""
     _check(lib.mfa_kernel_timing(ctx, 1 if enable else 0))
+
+
+def mfa_measure_fma_peak(ctx: int) -> float:
+    """Measured FP32 FMA rate of the device (TFLOP/s), synchronous."""
+    out = C.c_double()
+    _check(lib.mfa_measure_fma_peak(ctx, C.byref(out)))
+    return out.value
 
 
 def mfa_kernel_times(ctx: int, cap: int = 1 << 16):

@@ -210,6 +210,7 @@ def test_null_context_and_handles(b):
     assert b.lib.mfa_eval_points(None, 1, 0, None, None, None, None) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_eval_hessian(None, 1, 4, None, None, None, None, None) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_kernel_timing(None, 1) == b.MFA_ERR_HANDLE
+    assert b.lib.mfa_measure_fma_peak(None, None) == b.MFA_ERR_HANDLE
     bh = C.c_int64()
     assert b.lib.mfa_batch_create(None, None, 1, C.byref(bh)) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_batch_render(None, 1, None) == b.MFA_ERR_HANDLE
