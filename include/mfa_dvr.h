@@ -24,7 +24,10 @@
  *    completed.
  *  - `stream` is a hipStream_t (NULL = the null stream).  Render and
  *    evaluation calls are asynchronous on that stream.
- *  - A context is used by one host thread at a time.
+ *  - A context is used by one host thread at a time.  Work it enqueues on
+ *    different streams may run concurrently: every stream has its own
+ *    planning space for mfa_render (a batch is the exception: see
+ *    mfa_batch_render).
  */
 #ifndef MFA_DVR_H
 #define MFA_DVR_H

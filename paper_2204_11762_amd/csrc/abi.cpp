@@ -432,6 +432,14 @@ struct RenderBatch {
   std::vector<int64_t> models;
 };
 
+// Planning scratch of one stream: cost and order arrays of `tiles` entries
+// each (launch slots), then kPlanHistWords bucket counters.
+struct PlanScratch {
+  void* mem = nullptr;
+  int64_t tiles = 0;
+};
+constexpr size_t kMaxPlanStreams = 16;
+
 struct mfa_ctx {
   int device = 0;
   int64_t budget = 0;
@@ -441,14 +449,18 @@ struct mfa_ctx {
   std::unordered_map<int64_t, RenderBatch> batches;
   std::unordered_map<uint64_t, std::vector<TFEntry>> tfs;
   size_t n_tf = 0;
-  // scratch of the tile sort: cost and order arrays of `scratch_tiles`
-  // entries each (launch slots), then kPlanHistWords bucket counters
-  void* scratch = nullptr;
-  int64_t scratch_tiles = 0;
+  // planning scratch by stream: renders on one stream are ordered by it,
+  // renders on different streams never share planning space
+  std::unordered_map<void*, PlanScratch> plans;
   // kernel timing: event pairs, the first `timed` of which are recorded
   bool timing = false;
   std::vector<mfa::KernelEvents> events;
   size_t timed = 0;
+
+  void free_plans() {
+    for (auto& kv : plans) (void)hipFree(kv.second.mem);
+    plans.clear();
+  }
 
   void free_tfs() {
     for (auto& kv : tfs)
@@ -498,26 +510,42 @@ mfa_status tf_device(mfa_ctx* ctx, const mfa_tf* tf, float4** out) {
   return MFA_OK;
 }
 
-// Grow the tile-queue scratch to `tiles` entries.  An older, smaller buffer
-// may still be read by enqueued kernels, so the device is synchronised
-// before it is released.
-mfa_status ensure_scratch(mfa_ctx* ctx, int64_t tiles) {
-  if (ctx->scratch != nullptr && ctx->scratch_tiles >= tiles) return MFA_OK;
-  if (ctx->scratch != nullptr) {
-    const hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("hipDeviceSynchronize", e));
-    (void)hipFree(ctx->scratch);
-    ctx->scratch = nullptr;
-    ctx->scratch_tiles = 0;
+// The planning scratch of `stream`, grown to at least `tiles` launch slots,
+// and its arrays attached to the records `a`.  A buffer that must grow, or
+// the whole set once it holds kMaxPlanStreams streams, may still be read by
+// enqueued kernels, so the device is synchronised before release.
+mfa_status attach_plan(mfa_ctx* ctx, void* stream, int64_t tiles, mfa::RenderArgsDev* a,
+                       int na) {
+  auto it = ctx->plans.find(stream);
+  if (it == ctx->plans.end() || it->second.tiles < tiles) {
+    const bool grow = it != ctx->plans.end();
+    if (grow || ctx->plans.size() >= kMaxPlanStreams) {
+      const hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("hipDeviceSynchronize", e));
+      if (grow) {
+        (void)hipFree(it->second.mem);
+        ctx->plans.erase(it);
+      } else {
+        ctx->free_plans();
+      }
+    }
+    PlanScratch ps;
+    const size_t bytes = size_t(tiles) * 8 + size_t(mfa::kPlanHistWords) * 4 + 256;
+    const hipError_t e = hipMalloc(&ps.mem, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MFA_ERR_NOMEM, hip_msg("hipMalloc (tile queue)", e));
+    }
+    ps.tiles = tiles;
+    it = ctx->plans.emplace(stream, ps).first;
   }
-  const size_t bytes = size_t(tiles) * 8 + size_t(mfa::kPlanHistWords) * 4 + 256;
-  const hipError_t e = hipMalloc(&ctx->scratch, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    ctx->scratch = nullptr;
-    return fail(MFA_ERR_NOMEM, hip_msg("hipMalloc (tile queue)", e));
+  int32_t* base = static_cast<int32_t*>(it->second.mem);
+  const int64_t n = it->second.tiles;
+  for (int i = 0; i < na; ++i) {
+    a[i].tile_cost = base;
+    a[i].tile_order = base + n;
+    a[i].tile_hist = reinterpret_cast<unsigned*>(base + 2 * n);
   }
-  ctx->scratch_tiles = tiles;
   return MFA_OK;
 }
 
@@ -574,8 +602,7 @@ mfa_status mfa_destroy(mfa_ctx* ctx) {
     for (auto& kv : ctx->models) (void)hipFree(kv.second.mem);
     ctx->models.clear();
     ctx->free_tfs();
-    if (ctx->scratch) (void)hipFree(ctx->scratch);
-    ctx->scratch = nullptr;
+    ctx->free_plans();
     for (auto& ev : ctx->events) {
       (void)hipEventDestroy(ev.begin);
       (void)hipEventDestroy(ev.end);
@@ -1028,12 +1055,8 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const 
   mfa::RenderArgsDev a;
   build_render_args(dm, cam, tf, prm, rgba_dev, samples_dev, tf_dev, a);
   if (a.ntiles > 0) {
-    st = ensure_scratch(ctx, a.nslots);
+    st = attach_plan(ctx, stream, a.nslots, &a, 1);
     if (st != MFA_OK) return st;
-    int32_t* base = static_cast<int32_t*>(ctx->scratch);
-    a.tile_cost = base;
-    a.tile_order = base + ctx->scratch_tiles;
-    a.tile_hist = reinterpret_cast<unsigned*>(base + 2 * ctx->scratch_tiles);
   }
   return launch_timed(ctx, a, stream);
 }
@@ -1189,14 +1212,8 @@ mfa_status mfa_autotune(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, cons
   }
   dm.round_spans = saved;
   if (args[0].ntiles > 0) {
-    st = ensure_scratch(ctx, slots);
+    st = attach_plan(ctx, stream, slots, args.data(), kCand);
     if (st != MFA_OK) return st;
-    int32_t* base = static_cast<int32_t*>(ctx->scratch);
-    for (auto& a : args) {
-      a.tile_cost = base;
-      a.tile_order = base + ctx->scratch_tiles;
-      a.tile_hist = reinterpret_cast<unsigned*>(base + 2 * ctx->scratch_tiles);
-    }
   }
   const int total = kCand * (repeats + 1);
   std::vector<mfa::KernelEvents> evs(total);

@@ -169,6 +169,43 @@ def test_determinism_and_stream(mfa):
         b.mfa_model_free(ctx, h)
 
 
+def test_concurrent_streams(mfa):
+    """Frames of different sizes and views enqueued on two streams without
+    synchronising in between (so their planning and ray casting can
+    overlap on the device) equal their solo renders bit for bit."""
+    import copy
+
+    import torch
+    b, ctx = mfa
+    wk = wl.c2()
+    views = []
+    for w, az in ((320, 30.0), (256, 75.0), (384, 150.0), (200, 250.0)):
+        v = copy.copy(wk)
+        v.camera = wl.orbit_camera(w, w, az, 20.0)
+        views.append(v)
+    h = b.mfa_model_upload(ctx, wk.model)
+    try:
+        ref = [gpu_render(b, ctx, h, v) for v in views]
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        outs = [torch.zeros((v.camera.height, v.camera.width, 4), dtype=torch.float32,
+                            device="cuda") for v in views]
+        cnts = [torch.zeros((1,), dtype=torch.int64, device="cuda") for _ in views]
+        torch.cuda.synchronize()
+        for rep in range(3):
+            for i, v in enumerate(views):
+                s = streams[i % 2]
+                with torch.cuda.stream(s):
+                    b.mfa_render(ctx, h, v.camera, v.tf, v.params, outs[i], cnts[i], stream=s)
+            torch.cuda.synchronize()
+            for i in range(len(views)):
+                assert np.array_equal(outs[i].cpu().numpy().astype(np.float64), ref[i][0]), \
+                    f"repeat {rep}, view {i}"
+                assert int(cnts[i].item()) == ref[i][1]
+                outs[i].fill_(-1.0)
+    finally:
+        b.mfa_model_free(ctx, h)
+
+
 def test_kernel_timing(mfa):
     """The optional kernel events time every render while enabled, leave the
     image unchanged, and record nothing once disabled."""
