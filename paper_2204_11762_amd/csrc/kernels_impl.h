@@ -18,10 +18,12 @@
 //      the accumulated opacity exceeds the limit.
 // The main ray caster (render_brick_kernel) gives each wave a 4x4 pixel
 // tile with four lanes per ray and stages the control points of a round of
-// samples in LDS; the fallback (render_global_kernel, used when the knots
-// or transfer function do not fit in LDS) gives each lane one ray of a
-// 16x16 tile and gathers from global memory.  In both, neighbouring rays
-// run in one wave, so their gathers share cache lines.
+// samples in LDS; the global-memory caster (render_global_kernel: when the
+// knots or transfer function do not fit in LDS, for rational models, and
+// for curvature transfer functions) gives each lane one ray of a 16x16
+// tile.  In both, neighbouring rays run in one wave, so their gathers share
+// cache lines.  Point queries (eval_kernel, eval_hess_kernel) give each
+// lane one point; the latter also returns the second derivatives.
 //
 // Mixed per-axis degrees run in the kernel of the largest degree P: an axis
 // of degree q < P uses the window of P+1 control points that starts at its
@@ -918,11 +920,13 @@ __device__ __forceinline__ void count_samples(const RenderArgsDev& a, int count,
 }
 
 // ---------------------------------------------------------------------------
-// fallback ray caster: all data from global memory
+// global-memory ray caster: one lane per ray, all data from global memory
 // ---------------------------------------------------------------------------
 
 // Used when the knots or transfer function of a request do not fit the LDS
-// budget of the brick kernel.
+// budget of the brick kernel, for rational models (RAT: the quotient of the
+// two contractions) and for curvature transfer functions (CURV: value,
+// gradient and Hessian per sample).
 template <int P, int STORE, bool SHADE, bool RAT, bool CURV>
 __global__ __launch_bounds__(256) void render_global_kernel(RenderArgsDev a) {
   const int tid = threadIdx.x;
@@ -1019,31 +1023,6 @@ __device__ __forceinline__ void span_step(const double* K, int n, int p, double 
   }
 }
 
-// Basis window of one axis for the current span.  Uniform knots on an
-// interior span use the cardinal pieces (derivatives in t = u m units);
-// otherwise the triangle with the span's reciprocal table (derivatives in
-// u units, rescaled to t units for uniform models so that one gradient
-// factor per axis applies).
-template <int P, bool UNIFORM>
-__device__ __forceinline__ void axis_weights(const AxisDev& A, const SpanState& st, double u,
-                                             float (&N)[P + 1], float (&dN)[P + 1]) {
-  const int q = A.p;
-  if constexpr (UNIFORM) {
-    if (st.s >= 2 * q - 1 && st.s <= A.n - q) {
-      const float t = (float)((u - st.lo) * A.m);
-      cardinal_window<P>(q, t, N, dN);
-      return;
-    }
-  }
-  const float d = (float)(u - st.lo);
-  const float* row = A.tab + (size_t)(st.s - q) * (size_t)table_stride(q);
-  axis_basis<P>(q, row, d, N, dN);
-  if constexpr (UNIFORM) {
-#pragma unroll
-    for (int i = 0; i <= P; ++i) dN[i] *= A.inv_m;
-  }
-}
-
 // Minimum (MAX = false) or maximum over the 64 lanes of a wave, returned as
 // a wave-uniform value.  Butterflies inside each row of 16 lanes by DPP
 // (pair swap, quad-half swap, half-row mirror, row mirror), then across
@@ -1109,11 +1088,12 @@ __device__ __forceinline__ int div_small(int a, int b, float inv_b) {
 // 2x2 tiles of entry b of a list of super-tiles sorted by decreasing
 // estimated work, and the hardware starts workgroups in index order, so the
 // longest rays start first while the four waves of a workgroup work on
-// neighbouring tiles.  LPR lanes share a ray (a tile has 64/LPR rays): lane e of a ray
-// evaluates samples e, e+LPR, e+2 LPR, ..., the group exchanges the shaded
-// samples through DPP and composites them in ray order, so a ray's serial
-// chain is LPR times shorter while the composited result is the same as
-// with one lane per ray.
+// neighbouring tiles.  LPR lanes share a ray (a tile has 64/LPR rays): lane
+// e of a ray evaluates samples e, e+LPR, e+2 LPR, ...; the lanes exchange
+// their samples' opacities through DPP and each runs the ray's opacity
+// chain in sample order, so a ray's serial chain is LPR times shorter while
+// the opacities and the termination sample are those of one lane per ray
+// (the colour sum is accumulated per lane and added at the end).
 //
 // A wave marches its rays in rounds of `spr` samples.  Before a round it
 // stages, into its own LDS brick, every control point that the windows of
