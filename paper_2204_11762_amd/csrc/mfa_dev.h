@@ -119,7 +119,7 @@ struct RenderArgsDev {
   int32_t ctf_m;
   float ctf_lo;
   float ctf_scale;
-  // LDS-brick ray marcher (render_brick_kernel); unused by the fallback
+  // LDS-brick ray marcher (render_brick_kernel); unused by the global caster
   int32_t spr;          // samples per round: each wave stages one brick per round
   int32_t brick_cap;    // floats of LDS per wave for its brick (multiple of 4)
   int32_t lds_knots;    // byte offset of the knot vectors in dynamic LDS (not with fast)
