@@ -284,6 +284,52 @@ def test_camera_inside_volume(mfa):
         b.mfa_model_free(ctx, h)
 
 
+OFF_IMAGE_CASES = {
+    # the box small in a wide view: most pixels miss it
+    "distant": wl.CameraSpec("persp", (3.5, 2.9, 6.2), (0.5, 0.5, 0.5), (0, 1, 0), 160, 120,
+                             fov_y_deg=40.0),
+    # the box across the image border
+    "edge": wl.CameraSpec("persp", (0.5, 0.6, 2.6), (1.25, 0.9, 0.5), (0, 1, 0), 144, 100,
+                          fov_y_deg=50.0),
+    # every corner in front of the eye, the box beside the view: every ray misses
+    "beside": wl.CameraSpec("persp", (0.5, 0.5, 4.0), (4.0, 0.5, 0.0), (0, 1, 0), 96, 64,
+                            fov_y_deg=30.0),
+    # orthographic window much wider than the box
+    "ortho": wl.CameraSpec("ortho", (0.5, 0.5, 3.0), (0.5, 0.5, 0.0), (0, 1, 0), 128, 96,
+                           ortho_half_w=1.6, ortho_half_h=1.2),
+}
+
+
+@pytest.mark.parametrize("name", sorted(OFF_IMAGE_CASES))
+def test_box_partly_or_wholly_off_image(mfa, name):
+    """Frames in which most rays, or all, miss the box: the full image and
+    the sample count equal the oracle's, and every missing ray gives
+    transparent black."""
+    b, ctx = mfa
+    wk = wl.c2()
+    wk.camera = OFF_IMAGE_CASES[name]
+    h = b.mfa_model_upload(ctx, wk.model)
+    try:
+        W, H = wk.camera.width, wk.camera.height
+        img, cnt = gpu_render(b, ctx, h, wk)
+        rep = compare_image(img, cnt, wk, np.arange(W * H), TAU32, PX32)
+        _report(f"off-image {name}", rep)
+        assert rep.rmse <= FP32_RMSE and rep.n_bad == 0
+        _check_counts(rep, True)
+        M, cam, _, p = oracle_workload(wk)
+        r, c = np.divmod(np.arange(W * H), W)
+        o, d = orc.camera_rays(cam, r, c)
+        t0, t1, hit = orc.slab(o, d, M.lo, M.hi)
+        nr = orc.sample_counts(t0, t1, hit, p.step)
+        assert (img.reshape(-1, 4)[nr == 0] == 0).all()
+        if name == "beside":
+            assert (nr == 0).all() and cnt == 0 and (img == 0).all()
+        else:
+            assert (nr > 0).sum() > 100
+    finally:
+        b.mfa_model_free(ctx, h)
+
+
 def test_c2_full_size_sampled_pixels(mfa):
     b, ctx = mfa
     wk = wl.c2()
