@@ -1063,6 +1063,30 @@ __device__ __forceinline__ float group_bcast(float v) {
   }
 }
 
+// Value of the lane D places earlier in each aligned group of L lanes (L = 2
+// or 4); a lane with fewer than D predecessors in its group gets the value
+// of the group's first lane (callers overwrite it).  DPP quad permutation.
+template <int L, int D>
+__device__ __forceinline__ float group_prev(float v) {
+  static_assert(D >= 1 && D < L, "distance");
+  static_assert(L == 2 || L == 4, "group size");
+  constexpr int b0 = 0, b1 = 1 >= D ? 1 - D : 0;
+  constexpr int b2 = L == 2 ? 2 : (2 >= D ? 2 - D : 0);
+  constexpr int b3 = L == 2 ? (3 - D >= 2 ? 3 - D : 2) : (3 >= D ? 3 - D : 0);
+  constexpr int ctrl = b0 | (b1 << 2) | (b2 << 4) | (b3 << 6);
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
+}
+
+// Value of the previous lane of each aligned group of L lanes (L = 2 or 4),
+// the group's first lane taking its last lane's: a rotation by one, DPP
+// quad permutation.
+template <int L>
+__device__ __forceinline__ float group_rotate(float v) {
+  static_assert(L == 2 || L == 4, "group size");
+  constexpr int ctrl = L == 4 ? (3 | (0 << 2) | (1 << 4) | (2 << 6)) : (1 | (0 << 2) | (3 << 4) | (2 << 6));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
+}
+
 // Sum over each aligned group of L lanes (L = 1, 2 or 4), returned to every
 // lane of the group: pair swap, then (L = 4) half-quad swap, by DPP.
 template <int L>
@@ -1215,7 +1239,12 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
       }
     }
   }
-  float cr = 0.0f, cg = 0.0f, cb = 0.0f, A = 0.0f;
+  // colour and opacity accumulated by this lane; transmittance of the ray
+  float cr = 0.0f, cg = 0.0f, cb = 0.0f, A = 0.0f, T = 1.0f;
+  // a sample is composited while the transmittance in front of it is at
+  // least this (opacities lie in [0, 1], checked on the host, so T >= 0
+  // and ert >= 1 never stops a ray)
+  const float t_stop = 1.0f - a.ert;
 
   for (int s0 = 0, sr = S;; s0 += sr) {
     if (!__any(alive)) break;
@@ -1262,18 +1291,24 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
         blo[k] = uniform_i(sl - q);
         bext[k] = uniform_i(sh - sl + P + 1);
       }
+      // x rows padded to whole groups of four; the z pitch is an odd
+      // multiple of four floats, so that the rows a wave gathers from
+      // neighbouring z slices spread over the LDS banks (a z pitch that is a
+      // multiple of 32 floats puts them in one bank)
       pitch_y = (bext[0] + 3) & ~3;
       pitch_z = pitch_y * bext[1];
-      nel = pitch_z * bext[2];
+      pitch_z += ((pitch_z >> 2) & 1) ? 0 : 4;
+      nel = pitch_z * (bext[2] - 1) + pitch_y * bext[1];
       fits = nel <= a.brick_cap;
       if (fits || sr <= 2 * LPR) break;
     }
 
     if (fits) {
       // Stage the brick: group gi = ix + gx (jy + bext1 kz) holds the four
-      // consecutive x values starting at x = 4 ix of row (jy, kz), at LDS
-      // offset 4 gi.  Lane L takes groups L, L + 64, ...; its (ix, jy, kz)
-      // and global element index advance by the mixed-radix digits of 64.
+      // consecutive x values starting at x = 4 ix of row (jy, kz), at brick
+      // offset 4 ix + pitch_y jy + pitch_z kz.  Lane L takes groups L,
+      // L + 64, ...; its (ix, jy, kz), global element index and brick
+      // offset advance by the mixed-radix digits of 64.
       const int gx = pitch_y >> 2;
       const int gxy = gx * bext[1];
       const int ngroups = gxy * bext[2];
@@ -1285,21 +1320,28 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
       const int dg = 4 * d_ix + nx * d_jy + nxy * d_kz;   // step without carries
       const int dg_c1 = nx - 4 * gx;                      // carry ix -> jy
       const int dg_c2 = nxy - nx * bext[1];               // carry jy -> kz
+      // brick offsets: the carry ix -> jy adds pitch_y - 4 gx = 0
+      const int dl = 4 * d_ix + pitch_y * d_jy + pitch_z * d_kz;
+      const int dl_c2 = pitch_z - pitch_y * bext[1];      // carry jy -> kz
       const int kz = div_small(lane, gxy, __builtin_amdgcn_rcpf((float)gxy));
       const int rem = lane - kz * gxy;
       int jy = div_small(rem, gx, inv_gx);
       int ix = rem - jy * gx;
       int g = (blo[0] + 4 * ix) + nx * (blo[1] + jy) + nxy * (blo[2] + kz);
+      int lo = 4 * ix + pitch_y * jy + pitch_z * kz;
       // four groups per lane in flight: loads past the last group read
       // element 0 (and are dropped), only the LDS stores are predicated
       for (int gi = lane; gi < ngroups; gi += 256) {
         float v[4][4];
+        int lu[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           load_row<3, STORE>(rs, gi + 64 * u < ngroups ? g : 0, v[u]);
+          lu[u] = lo;
           ix += d_ix;
           jy += d_jy;
           g += dg;
+          lo += dl;
           if (ix >= gx) {
             ix -= gx;
             jy += 1;
@@ -1308,6 +1350,7 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
           if (jy >= bext[1]) {
             jy -= bext[1];
             g += dg_c2;
+            lo += dl_c2;
           }
         }
 #pragma unroll
@@ -1318,7 +1361,7 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
             w.y = v[u][1];
             w.z = v[u][2];
             w.w = v[u][3];
-            *reinterpret_cast<float4*>(brick + 4 * (gi + 64 * u)) = w;
+            *reinterpret_cast<float4*>(brick + lu[u]) = w;
           }
         }
       }
@@ -1392,14 +1435,17 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
     };
 
     // shade(): transfer function and Phong shading of this lane's sample.
-    // composite(): the opacity chain of the group's samples j, j+1, ...,
-    // j+LPR-1 in order; false once the ray terminates.
-    // Every lane of a ray runs the same chain (each sample's alpha comes
-    // from its lane by a quad broadcast), keeps the compositing weight of
-    // its own sample and accumulates only its own colour; the partial
-    // colours of a ray are summed once at the end.  The phases run without
-    // branches: a sample past the round's end has alpha 0 and leaves the
-    // state unchanged, and after termination the weights are 0.
+    // composite(): front-to-back compositing of the group's samples j, j+1,
+    // ..., j+LPR-1 (one per lane); false once the ray terminates.
+    // T is the ray's transmittance (1 - accumulated opacity) before the
+    // group, the same in its LPR lanes.  The transmittance in front of lane
+    // e's sample is T times the product of (1 - alpha) over the group's
+    // earlier lanes, an exclusive product scan in two DPP steps.  The
+    // sample is composited while that transmittance is at least 1 - ert
+    // (the accumulated opacity has not passed ert), with weight
+    // transmittance x alpha; each lane accumulates its own weighted colour
+    // and weight (opacity), summed over the ray's lanes once at the end.  A
+    // sample past the round's end has alpha 0 and changes nothing.
     auto shade = [&](float f, const float (&g)[3], float& sr, float& sg, float& sb,
                      float& alpha) {
       float gw[3];
@@ -1408,30 +1454,28 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
       shade_sample<SHADE>(a, tf_lo, tf_scale, f, gw, eye, tf, sr, sg, sb, alpha);
     };
     auto composite = [&](int j, float sr, float sg, float sb, float alpha, bool valid) {
-      // Opacities lie in [0, 1] (checked on the host), so A <= 1 and a
-      // reached sample's weight (1 - A) alpha is +0 or positive; -0 marks
-      // a sample after the termination, which adds nothing and is not
-      // counted.
-      bool go = true;
-      float my_w = -0.0f;
-#define MFA_COMPOSITE_PHASE(Q)                          \
-  if constexpr ((Q) < LPR) {                            \
-    const float qa = group_bcast<LPR, (Q)>(alpha);      \
-    const float wq = go ? (1.0f - A) * qa : -0.0f;      \
-    if (e == (Q)) my_w = wq;                            \
-    A += wq;                                            \
-    go = go && !(A > a.ert);                            \
-  }
-      MFA_COMPOSITE_PHASE(0)
-      MFA_COMPOSITE_PHASE(1)
-      MFA_COMPOSITE_PHASE(2)
-      MFA_COMPOSITE_PHASE(3)
-#undef MFA_COMPOSITE_PHASE
-      cr = fmaf(my_w, sr, cr);
-      cg = fmaf(my_w, sg, cg);
-      cb = fmaf(my_w, sb, cb);
-      count += (valid && !signbit(my_w)) ? 1 : 0;
-      return go;
+      const float om = 1.0f - alpha;
+      float ex = 1.0f;   // product of (1 - alpha) over the earlier lanes of the group
+      if constexpr (LPR >= 2) {
+        // lane e takes (1 - alpha) of lane e-1, the first lane 1 (the
+        // selection is made on the source: every lane of the group takes
+        // part in each DPP move)
+        ex = group_rotate<LPR>(e == LPR - 1 ? 1.0f : om);
+        if constexpr (LPR == 4) {
+          ex *= group_prev<LPR, 1>(ex);   // lanes e-1, e-2
+          ex *= group_prev<LPR, 2>(ex);   // and e-3
+        }
+      }
+      const float tb = T * ex;
+      const bool reached = tb >= t_stop;
+      const float w = reached ? tb * alpha : 0.0f;
+      cr = fmaf(w, sr, cr);
+      cg = fmaf(w, sg, cg);
+      cb = fmaf(w, sb, cb);
+      A += w;
+      count += (valid && reached) ? 1 : 0;
+      T *= group_bcast<LPR, LPR - 1>(ex * om);
+      return T >= t_stop;
     };
 
     if (fits) {
@@ -1490,10 +1534,11 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
     }
     if (s1 >= nr) alive = false;
   }
-  // the colour of a ray is the sum of its lanes' partial colours
+  // the colour and opacity of a ray are the sums of its lanes' parts
   cr = group_sum<LPR>(cr);
   cg = group_sum<LPR>(cg);
   cb = group_sum<LPR>(cb);
+  A = group_sum<LPR>(A);
   if (inside && e == 0) {
     float4 o;
     o.x = cr;
