@@ -1048,6 +1048,40 @@ __device__ __forceinline__ unsigned wave_reduce_u32(unsigned v) {
 
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Brick z pitch.  A wave's lanes gather rows whose brick offsets differ by
+// dx + pitch_y dy + pitch_z dz for small cell offsets (dx, dy, dz); with
+// both pitches multiples of four floats, two such rows share an LDS bank
+// (of 32) when a dy + c dz = 0 mod 8, where a and c are the pitches in
+// groups of four.  pitch_conflicts(a, c) counts the offsets with |dy|,
+// |dz| <= 2 that do, the direct neighbours weighted 4; the z pitch is
+// raised by the fewest groups of four that reach the least count for a.
+constexpr int pitch_conflicts(int a, int c) {
+  int n = 0;
+  for (int dy = -2; dy <= 2; ++dy)
+    for (int dz = -2; dz <= 2; ++dz)
+      if ((dy != 0 || dz != 0) && ((a * dy + c * dz) % 8 + 8) % 8 == 0)
+        n += (dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) ? 4 : 1;
+  return n;
+}
+// Groups of four to add to a z pitch of residue c for a y pitch of residue
+// a (both mod 8).
+constexpr int pitch_z_step(int a, int c) {
+  int best = pitch_conflicts(a, 0);
+  for (int r = 1; r < 8; ++r) best = pitch_conflicts(a, r) < best ? pitch_conflicts(a, r) : best;
+  int k = 0;
+  while (pitch_conflicts(a, (c + k) % 8) != best) ++k;
+  return k;
+}
+// The steps packed two bits per (a, c), a in [4h, 4h + 4) for half h.
+constexpr unsigned long long pitch_z_steps(int h) {
+  unsigned long long w = 0;
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 8; ++c)
+      w |= (unsigned long long)pitch_z_step(4 * h + a, c) << (2 * (8 * a + c));
+  return w;
+}
+static_assert(pitch_z_step(3, 3) == 1 && pitch_z_step(3, 1) == 0, "pitch table");
+
 // Value of lane (group base + q) of each aligned group of L lanes (L = 1, 2
 // or 4, so a group never leaves its quad of lanes), by a DPP quad
 // permutation.
@@ -1291,13 +1325,17 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
         blo[k] = uniform_i(sl - q);
         bext[k] = uniform_i(sh - sl + P + 1);
       }
-      // x rows padded to whole groups of four; the z pitch is an odd
-      // multiple of four floats, so that the rows a wave gathers from
-      // neighbouring z slices spread over the LDS banks (a z pitch that is a
-      // multiple of 32 floats puts them in one bank)
+      // x rows padded to whole groups of four; the z pitch raised so that
+      // the rows a wave gathers from neighbouring cells spread over the LDS
+      // banks (pitch_z_step)
       pitch_y = (bext[0] + 3) & ~3;
       pitch_z = pitch_y * bext[1];
-      pitch_z += ((pitch_z >> 2) & 1) ? 0 : 4;
+      {
+        constexpr unsigned long long lo = pitch_z_steps(0), hi = pitch_z_steps(1);
+        const int ra = (pitch_y >> 2) & 7, rc = (pitch_z >> 2) & 7;
+        const unsigned long long w = ra < 4 ? lo : hi;
+        pitch_z += 4 * (int)((w >> (2 * (8 * (ra & 3) + rc))) & 3ull);
+      }
       nel = pitch_z * (bext[2] - 1) + pitch_y * bext[1];
       fits = nel <= a.brick_cap;
       if (fits || sr <= 2 * LPR) break;
