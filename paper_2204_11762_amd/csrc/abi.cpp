@@ -354,7 +354,7 @@ struct DeviceModel {
 // fallback kernel (lds_bytes = 0).
 constexpr int kMinBrick = 512;
 
-void plan_bricks(const DeviceModel& dm, int ntf, double step, mfa::RenderArgsDev& a) {
+void plan_bricks(const DeviceModel& dm, int ntf, double step, bool curv, mfa::RenderArgsDev& a) {
   const int tf_bytes = ntf * 16;
   int knot_doubles = 0;
   for (int k = 0; k < 3; ++k) {
@@ -363,8 +363,15 @@ void plan_bricks(const DeviceModel& dm, int ntf, double step, mfa::RenderArgsDev
     if (!a.fast) knot_doubles += int(dm.nknots[k]);
   }
   const int knot_bytes = (knot_doubles * 8 + 15) & ~15;
+  if (curv && dm.md.pmax > mfa::kCurvBrickMaxDegree) {
+    // curvature above this degree: the global-memory kernel
+    a.lds_bytes = 0;
+    a.spr = 0;
+    a.brick_cap = 0;
+    return;
+  }
   const int lds_budget =
-      mfa::brick_lds_per_group(mfa::brick_waves_per_simd(dm.md.pmax, a.fast != 0, a.eq != 0));
+      mfa::brick_lds_per_group(mfa::brick_waves_per_simd(dm.md.pmax, a.fast != 0, a.eq != 0, curv));
   const int rest = lds_budget - tf_bytes - knot_bytes;
   const int cap = (rest / (4 * 4)) & ~3;
   if (cap < kMinBrick) {
@@ -779,12 +786,13 @@ mfa_status check_request(const DeviceModel& dm, const mfa_camera* cam, const mfa
 }
 
 // Kernel record of one validated request (camera frame, transfer function
-// at tf_dev, shading, LDS plan).  The tile-plan scratch pointers are left
-// for the caller; ntiles receives the request's super-tiles (0 when the
-// request uses the global-memory kernel).
+// at tf_dev, shading, LDS plan; curv: planned for the curvature variants'
+// occupancy).  The tile-plan scratch pointers are left for the caller;
+// ntiles receives the request's super-tiles (0 when the request uses the
+// global-memory kernel).
 void build_render_args(const DeviceModel& dm, const mfa_camera* cam, const mfa_tf* tf,
                        const mfa_render_params* prm, float* rgba_dev, int64_t* samples_dev,
-                       float4* tf_dev, mfa::RenderArgsDev& a) {
+                       float4* tf_dev, mfa::RenderArgsDev& a, bool curv = false) {
   Frame fr;
   camera_frame(cam, fr);
   a = mfa::RenderArgsDev{};
@@ -835,7 +843,7 @@ void build_render_args(const DeviceModel& dm, const mfa_camera* cam, const mfa_t
   a.samples = reinterpret_cast<unsigned long long*>(samples_dev);
   a.fast = dm.md.uniform && dm.md.ax[0].p >= 2 && dm.md.ax[1].p >= 2 && dm.md.ax[2].p >= 2;
   a.eq = dm.md.ax[0].p == dm.md.pmax && dm.md.ax[1].p == dm.md.pmax && dm.md.ax[2].p == dm.md.pmax;
-  plan_bricks(dm, tf->n, prm->step, a);
+  plan_bricks(dm, tf->n, prm->step, curv, a);
   if (dm.md.rational) {
     // the brick kernels are non-rational: rational models use the global kernel
     a.lds_bytes = 0;
@@ -1104,13 +1112,18 @@ mfa_status mfa_render_curvature(mfa_ctx* ctx, int64_t model, const mfa_camera* c
   st = tf_device(ctx, &flat, &ctf_dev);
   if (st != MFA_OK) return st;
 
+  // the brick ray caster with second derivatives (the global-memory kernel
+  // when the transfer function leaves too little LDS for bricks)
   mfa::RenderArgsDev a;
-  build_render_args(dm, cam, tf, prm, rgba_dev, samples_dev, tf_dev, a);
-  a.lds_bytes = 0;   // one lane per ray, data from global memory
+  build_render_args(dm, cam, tf, prm, rgba_dev, samples_dev, tf_dev, a, true);
   a.ctf = ctf_dev;
   a.ctf_m = ctf->m;
   a.ctf_lo = float(ctf->k_lo);
   a.ctf_scale = float(1.0 / (ctf->k_hi - ctf->k_lo));
+  if (a.ntiles > 0) {
+    st = attach_plan(ctx, stream, a.nslots, &a, 1);
+    if (st != MFA_OK) return st;
+  }
   return launch_timed(ctx, a, stream);
 }
 

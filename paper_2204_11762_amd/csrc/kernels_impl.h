@@ -505,10 +505,13 @@ __device__ __forceinline__ void contract_hess(const float (&N)[3][P + 1],
                                               const float (&dN)[3][P + 1],
                                               const float (&ddN)[3][P + 1], Fetch fetch,
                                               float& f, float (&g)[3], float (&h)[6]) {
-  // a[o][c][b]: row (b, c) with the x factor differentiated o times
-  float a[3][P + 1][P + 1];
+  float v = 0.0f, gx = 0.0f, gy = 0.0f, gz = 0.0f;
+  float hxx = 0.0f, hyy = 0.0f, hzz = 0.0f, hxy = 0.0f, hxz = 0.0f, hyz = 0.0f;
+  // one z slice c at a time, so that only its rows' sums are live
 #pragma unroll
   for (int c = 0; c <= P; ++c) {
+    // x: row (b, c) contracted with N, dN and ddN
+    float a0[P + 1], a1[P + 1], a2[P + 1];
 #pragma unroll
     for (int b = 0; b <= P; ++b) {
       float row[P + 1];
@@ -520,46 +523,32 @@ __device__ __forceinline__ void contract_hess(const float (&N)[3][P + 1],
         s1 = fmaf(dN[0][i], row[i], s1);
         s2 = fmaf(ddN[0][i], row[i], s2);
       }
-      a[0][c][b] = s0;
-      a[1][c][b] = s1;
-      a[2][c][b] = s2;
+      a0[b] = s0;
+      a1[b] = s1;
+      a2[b] = s2;
     }
-  }
-  // y: (x order, y order) = (0,0) (1,0) (0,1) (2,0) (1,1) (0,2)
-  float y00[P + 1], y10[P + 1], y01[P + 1], y20[P + 1], y11[P + 1], y02[P + 1];
-#pragma unroll
-  for (int c = 0; c <= P; ++c) {
-    float s00 = 0.0f, s10 = 0.0f, s01 = 0.0f, s20 = 0.0f, s11 = 0.0f, s02 = 0.0f;
+    // y: (x order, y order) = (0,0) (1,0) (0,1) (2,0) (1,1) (0,2)
+    float y00 = 0.0f, y10 = 0.0f, y01 = 0.0f, y20 = 0.0f, y11 = 0.0f, y02 = 0.0f;
 #pragma unroll
     for (int b = 0; b <= P; ++b) {
-      s00 = fmaf(N[1][b], a[0][c][b], s00);
-      s10 = fmaf(N[1][b], a[1][c][b], s10);
-      s01 = fmaf(dN[1][b], a[0][c][b], s01);
-      s20 = fmaf(N[1][b], a[2][c][b], s20);
-      s11 = fmaf(dN[1][b], a[1][c][b], s11);
-      s02 = fmaf(ddN[1][b], a[0][c][b], s02);
+      y00 = fmaf(N[1][b], a0[b], y00);
+      y10 = fmaf(N[1][b], a1[b], y10);
+      y01 = fmaf(dN[1][b], a0[b], y01);
+      y20 = fmaf(N[1][b], a2[b], y20);
+      y11 = fmaf(dN[1][b], a1[b], y11);
+      y02 = fmaf(ddN[1][b], a0[b], y02);
     }
-    y00[c] = s00;
-    y10[c] = s10;
-    y01[c] = s01;
-    y20[c] = s20;
-    y11[c] = s11;
-    y02[c] = s02;
-  }
-  float v = 0.0f, gx = 0.0f, gy = 0.0f, gz = 0.0f;
-  float hxx = 0.0f, hyy = 0.0f, hzz = 0.0f, hxy = 0.0f, hxz = 0.0f, hyz = 0.0f;
-#pragma unroll
-  for (int c = 0; c <= P; ++c) {
-    v = fmaf(N[2][c], y00[c], v);
-    gx = fmaf(N[2][c], y10[c], gx);
-    gy = fmaf(N[2][c], y01[c], gy);
-    gz = fmaf(dN[2][c], y00[c], gz);
-    hxx = fmaf(N[2][c], y20[c], hxx);
-    hyy = fmaf(N[2][c], y02[c], hyy);
-    hzz = fmaf(ddN[2][c], y00[c], hzz);
-    hxy = fmaf(N[2][c], y11[c], hxy);
-    hxz = fmaf(dN[2][c], y10[c], hxz);
-    hyz = fmaf(dN[2][c], y01[c], hyz);
+    // z
+    v = fmaf(N[2][c], y00, v);
+    gx = fmaf(N[2][c], y10, gx);
+    gy = fmaf(N[2][c], y01, gy);
+    gz = fmaf(dN[2][c], y00, gz);
+    hxx = fmaf(N[2][c], y20, hxx);
+    hyy = fmaf(N[2][c], y02, hyy);
+    hzz = fmaf(ddN[2][c], y00, hzz);
+    hxy = fmaf(N[2][c], y11, hxy);
+    hxz = fmaf(dN[2][c], y10, hxz);
+    hyz = fmaf(dN[2][c], y01, hyz);
   }
   f = v;
   g[0] = gx;
@@ -1178,7 +1167,7 @@ __device__ __forceinline__ int div_small(int a, int b, float inv_b) {
 // box of control points it touches exceeds the brick, so that nearly every
 // round gathers from LDS; a round that still does not fit at two samples
 // per lane gathers from global memory.
-template <int P, int STORE, bool SHADE, bool FAST, bool EQ, int LPR>
+template <int P, int STORE, bool SHADE, bool FAST, bool EQ, int LPR, bool CURV = false>
 __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
   static_assert(LPR == 1 || LPR == 2 || LPR == 4, "lanes per ray");
   constexpr int TW = LPR == 4 ? 4 : 8;        // tile width in pixels
@@ -1211,12 +1200,15 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
   const int S = a.spr;
   const int ray_lane = lane / LPR;   // ray of this lane within the tile
   const int e = lane % LPR;          // this lane's sample phase
+  // world gradient factors: t-derivatives on the FAST path, u-derivatives
+  // on the GENERAL path and for curvature (whose bases come from the span
+  // tables on both paths)
   float gfac[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
-    gfac[k] = FAST ? a.m.ax[k].gscale * (float)a.m.ax[k].m : a.m.ax[k].gscale;
+    gfac[k] = FAST && !CURV ? a.m.ax[k].gscale * (float)a.m.ax[k].m : a.m.ax[k].gscale;
   // degree 3 on uniform knots: scaled cubic pieces (value x 216, gradient x 72)
-  constexpr bool kScaled = FAST && EQ && P == 3;
+  constexpr bool kScaled = FAST && EQ && P == 3 && !CURV;
   const float tf_lo = kScaled ? a.tf_lo * kCubicValueScale : a.tf_lo;
   const float tf_scale = kScaled ? a.tf_scale * (1.0f / kCubicValueScale) : a.tf_scale;
   if constexpr (kScaled) {
@@ -1472,6 +1464,57 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
       }
     };
 
+    // CURV: basis functions with first and second derivatives (in u) of
+    // this lane's sample from the span tables, on both paths
+    auto weights2 = [&](int s, int i, float (&N)[3][P + 1], float (&dN)[3][P + 1],
+                        float (&ddN)[3][P + 1], int (&w)[3]) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const AxisDev& Ax = a.m.ax[k];
+        const int q = EQ ? P : Ax.p;
+        int c;
+        float d;
+        if constexpr (FAST) {
+          // cell from the FP32 stepping (clamped to the spans) and the
+          // offset from its left knot, c / m
+          const int m = Ax.n - q;
+          const float t = fmaf((float)i, dt[k], ta[k]);
+          c = min(max(ca[k] + (int)floorf(t), 0), m - 1);
+          d = (t - (float)(c - ca[k])) * Ax.inv_m;
+        } else {
+          const double u = param(s, k);
+          span_step(K[k], Ax.n, q, u, st[k]);
+          d = (float)(u - st[k].lo);
+          c = st[k].s - q;
+        }
+        axis_basis2<P>(q, Ax.tab + (size_t)c * (size_t)table_stride(q), d, N[k], dN[k], ddN[k]);
+        w[k] = c;
+      }
+    };
+    // CURV: value table, principal curvatures of the isosurface, curvature
+    // table (its colour, its opacity times the value table's), then Phong
+    auto shade_curv = [&](float f, const float (&g)[3], const float (&h)[6], float& sr,
+                          float& sg, float& sb, float& alpha) {
+      float gw[3], hw[6];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gw[k] = g[k] * gfac[k];
+      hw[0] = h[0] * (gfac[0] * gfac[0]);
+      hw[1] = h[1] * (gfac[1] * gfac[1]);
+      hw[2] = h[2] * (gfac[2] * gfac[2]);
+      hw[3] = h[3] * (gfac[0] * gfac[1]);
+      hw[4] = h[4] * (gfac[0] * gfac[2]);
+      hw[5] = h[5] * (gfac[1] * gfac[2]);
+      tf_sample(a, tf_lo, tf_scale, f, tf, sr, sg, sb, alpha);
+      float k1, k2;
+      principal_curvatures(gw, hw, k1, k2);
+      const float4 cc = curvature_lookup(a, k1, k2);
+      sr = cc.x;
+      sg = cc.y;
+      sb = cc.z;
+      alpha *= cc.w;
+      phong_sample<SHADE>(a, gw, eye, sr, sg, sb);
+    };
+
     // shade(): transfer function and Phong shading of this lane's sample.
     // composite(): front-to-back compositing of the group's samples j, j+1,
     // ..., j+LPR-1 (one per lane); false once the ray terminates.
@@ -1522,23 +1565,42 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
         // a lane past the round's end adds alpha 0 and colour 0
         float sr = 0.0f, sg = 0.0f, sb = 0.0f, alpha = 0.0f;
         if (s < s1) {
-          float f, g[3];
-          float N[3][P + 1], dN[3][P + 1];
-          int w[3];
-          weights(s, i, N, dN, w);
-          // 24-bit products: pitches and in-box offsets are far below 2^23
-          int e0 = (w[0] - blo[0]) + __mul24(pitch_y, w[1] - blo[1]) +
-                   __mul24(pitch_z, w[2] - blo[2]);
-          e0 = min(max(e0, 0), emax);
-          contract<P, SHADE>(
-              N, dN,
-              [&](int b, int c, float (&row)[P + 1]) {
-                const float* r = brick + e0 + b * pitch_y + c * pitch_z;
+          if constexpr (CURV) {
+            float f, g[3], h[6];
+            float N[3][P + 1], dN[3][P + 1], ddN[3][P + 1];
+            int w[3];
+            weights2(s, i, N, dN, ddN, w);
+            int e0 = (w[0] - blo[0]) + __mul24(pitch_y, w[1] - blo[1]) +
+                     __mul24(pitch_z, w[2] - blo[2]);
+            e0 = min(max(e0, 0), emax);
+            contract_hess<P>(
+                N, dN, ddN,
+                [&](int b, int c, float (&row)[P + 1]) {
+                  const float* r = brick + e0 + b * pitch_y + c * pitch_z;
 #pragma unroll
-                for (int q = 0; q <= P; ++q) row[q] = r[q];
-              },
-              f, g);
-          shade(f, g, sr, sg, sb, alpha);
+                  for (int q = 0; q <= P; ++q) row[q] = r[q];
+                },
+                f, g, h);
+            shade_curv(f, g, h, sr, sg, sb, alpha);
+          } else {
+            float f, g[3];
+            float N[3][P + 1], dN[3][P + 1];
+            int w[3];
+            weights(s, i, N, dN, w);
+            // 24-bit products: pitches and in-box offsets are far below 2^23
+            int e0 = (w[0] - blo[0]) + __mul24(pitch_y, w[1] - blo[1]) +
+                     __mul24(pitch_z, w[2] - blo[2]);
+            e0 = min(max(e0, 0), emax);
+            contract<P, SHADE>(
+                N, dN,
+                [&](int b, int c, float (&row)[P + 1]) {
+                  const float* r = brick + e0 + b * pitch_y + c * pitch_z;
+#pragma unroll
+                  for (int q = 0; q <= P; ++q) row[q] = r[q];
+                },
+                f, g);
+            shade(f, g, sr, sg, sb, alpha);
+          }
         }
         if (!composite(j, sr, sg, sb, alpha, s < s1)) {
           alive = false;
@@ -1551,18 +1613,33 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
         // a lane past the round's end adds alpha 0 and colour 0
         float sr = 0.0f, sg = 0.0f, sb = 0.0f, alpha = 0.0f;
         if (s < s1) {
-          float f, g[3];
-          float N[3][P + 1], dN[3][P + 1];
-          int w[3];
-          weights(s, i, N, dN, w);
-          const int e0 = w[0] + nx * w[1] + nxy * w[2];
-          contract<P, SHADE>(
-              N, dN,
-              [&](int b, int c, float (&row)[P + 1]) {
-                load_row<P, STORE>(rs, e0 + b * nx + c * nxy, row);
-              },
-              f, g);
-          shade(f, g, sr, sg, sb, alpha);
+          if constexpr (CURV) {
+            float f, g[3], h[6];
+            float N[3][P + 1], dN[3][P + 1], ddN[3][P + 1];
+            int w[3];
+            weights2(s, i, N, dN, ddN, w);
+            const int e0 = w[0] + nx * w[1] + nxy * w[2];
+            contract_hess<P>(
+                N, dN, ddN,
+                [&](int b, int c, float (&row)[P + 1]) {
+                  load_row<P, STORE>(rs, e0 + b * nx + c * nxy, row);
+                },
+                f, g, h);
+            shade_curv(f, g, h, sr, sg, sb, alpha);
+          } else {
+            float f, g[3];
+            float N[3][P + 1], dN[3][P + 1];
+            int w[3];
+            weights(s, i, N, dN, w);
+            const int e0 = w[0] + nx * w[1] + nxy * w[2];
+            contract<P, SHADE>(
+                N, dN,
+                [&](int b, int c, float (&row)[P + 1]) {
+                  load_row<P, STORE>(rs, e0 + b * nx + c * nxy, row);
+                },
+                f, g);
+            shade(f, g, sr, sg, sb, alpha);
+          }
         }
         if (!composite(j, sr, sg, sb, alpha, s < s1)) {
           alive = false;
@@ -1588,12 +1665,12 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
   count_samples(a, count, lane);
 }
 
-template <int P, int STORE, bool SHADE, bool FAST, bool EQ, int LPR>
+template <int P, int STORE, bool SHADE, bool FAST, bool EQ, int LPR, bool CURV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    brick_waves_per_simd(P, FAST, EQ)))) void render_brick_kernel(RenderArgsDev a) {
+    brick_waves_per_simd(P, FAST, EQ, CURV)))) void render_brick_kernel(RenderArgsDev a) {
   const int sup = uniform_i(a.tile_order[blockIdx.x]);
   if (sup < 0) return;   // empty launch slot of a smaller XCD group
-  brick_render<P, STORE, SHADE, FAST, EQ, LPR>(a, sup);
+  brick_render<P, STORE, SHADE, FAST, EQ, LPR, CURV>(a, sup);
 }
 
 // Request of global super-tile t of a batch class: the largest r with
@@ -1838,7 +1915,7 @@ hipError_t mark(hipEvent_t ev, hipStream_t st) {
   return ev == nullptr ? hipSuccess : hipEventRecord(ev, st);
 }
 
-template <int P, int STORE, bool SHADE, bool FAST, bool EQ>
+template <int P, int STORE, bool SHADE, bool FAST, bool EQ, bool CURV = false>
 hipError_t launch_brick(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
   const unsigned blocks = (unsigned)((a.ntiles + 255) / 256);
   const int nhist = kXcdGroups * kBuckets;
@@ -1851,7 +1928,8 @@ hipError_t launch_brick(const RenderArgsDev& a, hipStream_t st, const KernelEven
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = mark(ev.begin, st);
   if (e != hipSuccess) return e;
-  render_brick_kernel<P, STORE, SHADE, FAST, EQ, kLanesPerRay><<<a.nslots, 256, a.lds_bytes, st>>>(a);
+  render_brick_kernel<P, STORE, SHADE, FAST, EQ, kLanesPerRay, CURV>
+      <<<a.nslots, 256, a.lds_bytes, st>>>(a);
   e = hipGetLastError();
   return e == hipSuccess ? mark(ev.end, st) : e;
 }
@@ -1861,6 +1939,21 @@ hipError_t launch_render_ps(const RenderArgsDev& a, hipStream_t st, const Kernel
   if (a.lds_bytes > 0) {
     // EQ: every axis has the kernel's degree P (degree known at compile time)
     const bool eq = a.eq != 0;
+    if (a.ctf != nullptr) {
+      // curvature transfer function (non-rational models, checked on the
+      // host, which plans no bricks above kCurvBrickMaxDegree)
+      if constexpr (P <= kCurvBrickMaxDegree) {
+        if constexpr (P >= 2) {
+          if (a.fast)
+            return eq ? launch_brick<P, STORE, SHADE, true, true, true>(a, st, ev)
+                      : launch_brick<P, STORE, SHADE, true, false, true>(a, st, ev);
+        }
+        return eq ? launch_brick<P, STORE, SHADE, false, true, true>(a, st, ev)
+                  : launch_brick<P, STORE, SHADE, false, false, true>(a, st, ev);
+      } else {
+        return hipErrorInvalidValue;
+      }
+    }
     if constexpr (P >= 2) {
       if (a.fast)
         return eq ? launch_brick<P, STORE, SHADE, true, true>(a, st, ev)

@@ -30,13 +30,19 @@ constexpr int kPlanHistWords = kXcdGroups * 512;
 
 // Waves per SIMD that the brick ray caster of kernel degree P is compiled
 // for (four workgroups of four waves per CU, or three for the variants
-// whose registers would otherwise spill), and the LDS one workgroup may use
-// at that occupancy (160 KB per CU).
-__host__ __device__ constexpr int brick_waves_per_simd(int P, bool fast, bool eq) {
-  return (P >= 4 || (P == 3 && !fast && !eq)) ? 3 : 4;
+// whose registers would otherwise spill; the curvature variants, which also
+// carry second derivatives, three at degree 2 on uniform knots and two
+// otherwise, up to kCurvBrickMaxDegree), and the LDS one
+// workgroup may use at that occupancy (160 KB per CU).
+__host__ __device__ constexpr int brick_waves_per_simd(int P, bool fast, bool eq,
+                                                      bool curv = false) {
+  return curv ? ((P >= 3 || !fast) ? 2 : 3) : (P >= 4 || (P == 3 && !fast)) ? 3 : 4;
 }
+// Largest degree whose curvature rendering uses the brick ray caster (its
+// registers would spill above; such models use the global-memory kernel).
+constexpr int kCurvBrickMaxDegree = 3;
 __host__ __device__ constexpr int brick_lds_per_group(int waves) {
-  return waves == 3 ? 52 * 1024 : 40 * 1024;
+  return waves == 2 ? 80 * 1024 : waves == 3 ? 52 * 1024 : 40 * 1024;
 }
 
 // Per-span FP32 table of one axis of degree p, for span s (stored at row

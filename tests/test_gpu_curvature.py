@@ -1,5 +1,7 @@
 """GPU parity of rendering with a curvature transfer function
-(mfa_render_curvature) against the FP64 oracle, through the C ABI.
+(mfa_render_curvature) against the FP64 oracle, through the C ABI.  Up to
+degree 3 the brick ray caster renders it (second derivatives from the span
+tables on both of its paths); degree 4 uses the global-memory kernel.
 
 Principal curvatures are well conditioned where the gradient is large
 against the Hessian and ill conditioned near critical points (the
@@ -26,11 +28,14 @@ TAU32 = 2e-5
 PX32 = 2e-4
 
 
-def _sphere_spec(seed, degree=(2, 3, 2), n=(10, 9, 11), centre=(-0.6, 0.45, 0.5), noise=2e-3):
-    """|x - c|^2 reproduced on Beta(2,5) knots (centre outside the box, so
-    1.2 <= |g| everywhere), plus small control-point noise."""
+def _sphere_spec(seed, degree=(2, 3, 2), n=(10, 9, 11), centre=(-0.6, 0.45, 0.5), noise=2e-3,
+                 uniform=False):
+    """|x - c|^2 reproduced on Beta(2,5) knots (uniform knots if asked;
+    centre outside the box, so 1.2 <= |g| everywhere), plus small
+    control-point noise."""
     rng = np.random.default_rng(seed)
-    knots = tuple(wl.clamped_beta_knots(n[k], degree[k], rng) for k in range(3))
+    knots = tuple(wl.clamped_uniform_knots(n[k], degree[k]) if uniform
+                  else wl.clamped_beta_knots(n[k], degree[k], rng) for k in range(3))
     ctrl = np.zeros((n[2], n[1], n[0]))
     for ax in range(3):
         c = centre[ax]
@@ -98,6 +103,28 @@ def test_quadric_storages_with_termination(mfa, store):
     _, rep = _run(mfa, spec, wk, ctf, store=store, deq=deq)
     print(f"\n  quadric store {store}: rmse {rep.rmse:.2e} ambiguous {rep.n_ambiguous} "
           f"samples {rep.samples_gpu}/{rep.samples_ref}")
+    assert rep.n_bad == 0 and rep.rmse <= FP32_RMSE
+    assert abs(rep.samples_gpu - rep.samples_ref) <= rep.samples_slack
+
+
+# (degree, uniform knots): the brick caster's uniform-knot path with equal
+# and mixed degrees, its general path with mixed degrees, and degree 4,
+# which renders curvature with the global-memory kernel
+VARIANTS = [((2, 2, 2), True), ((2, 3, 3), True), ((3, 2, 3), False), ((4, 4, 4), True),
+            ((4, 3, 4), False)]
+
+
+@pytest.mark.parametrize("variant", range(len(VARIANTS)))
+def test_quadric_kernel_variants(mfa, variant):
+    deg, uniform = VARIANTS[variant]
+    n = tuple(d + 8 for d in deg)
+    spec = _sphere_spec(60 + variant, degree=deg, n=n, uniform=uniform)
+    wk = _workload(spec, size=40, ert=0.99, shading=variant % 2 == 0)
+    ctf = wl.curvature_tf(24, 0.0, 2.5)
+    img, rep = _run(mfa, spec, wk, ctf)
+    print(f"\n  degree {deg} uniform={uniform}: rmse {rep.rmse:.2e} max {rep.max_abs:.2e} "
+          f"ambiguous {rep.n_ambiguous} samples {rep.samples_gpu}/{rep.samples_ref}")
+    assert np.isfinite(img).all()
     assert rep.n_bad == 0 and rep.rmse <= FP32_RMSE
     assert abs(rep.samples_gpu - rep.samples_ref) <= rep.samples_slack
 
