@@ -36,7 +36,7 @@ constexpr int kPlanHistWords = kXcdGroups * 512;
 // workgroup may use at that occupancy (160 KB per CU).
 __host__ __device__ constexpr int brick_waves_per_simd(int P, bool fast, bool eq,
                                                       bool curv = false) {
-  return curv ? ((P >= 3 || !fast) ? 2 : 3) : (P >= 4 || (P == 3 && !fast)) ? 3 : 4;
+  return curv ? ((P >= 3 || !fast) ? 2 : 3) : (P >= 4 || (P == 3 && !fast && !eq)) ? 3 : 4;
 }
 // Largest degree whose curvature rendering uses the brick ray caster (its
 // registers would spill above; such models use the global-memory kernel).
