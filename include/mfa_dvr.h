@@ -26,8 +26,8 @@
  *    evaluation calls are asynchronous on that stream.
  *  - A context is used by one host thread at a time.  Work it enqueues on
  *    different streams may run concurrently: every stream has its own
- *    planning space for mfa_render (a batch is the exception: see
- *    mfa_batch_render).
+ *    planning space for mfa_render and mfa_render_curvature (a batch is the
+ *    exception: see mfa_batch_render).
  */
 #ifndef MFA_DVR_H
 #define MFA_DVR_H
@@ -211,7 +211,11 @@ typedef struct mfa_curvature_tf {
  * |g|^2 < 1e-12; a sphere around lower values has k1 = k2 = 1/r), index
  * the curvature table, whose colour becomes the sample's colour and whose
  * opacity multiplies the value table's; then Phong shading if enabled.
- * One lane per ray with global-memory gathers.  Errors: as mfa_render,
+ * Up to degree 3 the LDS-brick ray caster renders it (like mfa_render,
+ * with second derivatives); degree-4 models, or transfer functions that
+ * leave too little LDS for bricks, use one lane per ray with global-memory
+ * gathers.  The curvature table is read from global memory (cached).
+ * Errors: as mfa_render,
  * plus MFA_ERR_INVALID for a malformed curvature table and MFA_ERR_MODEL
  * for a rational model. */
 mfa_status mfa_render_curvature(mfa_ctx* ctx, int64_t model, const mfa_camera* camera,

@@ -1136,11 +1136,11 @@ __device__ __forceinline__ int div_small(int a, int b, float inv_b) {
 // estimated work, and the hardware starts workgroups in index order, so the
 // longest rays start first while the four waves of a workgroup work on
 // neighbouring tiles.  LPR lanes share a ray (a tile has 64/LPR rays): lane
-// e of a ray evaluates samples e, e+LPR, e+2 LPR, ...; the lanes exchange
-// their samples' opacities through DPP and each runs the ray's opacity
-// chain in sample order, so a ray's serial chain is LPR times shorter while
-// the opacities and the termination sample are those of one lane per ray
-// (the colour sum is accumulated per lane and added at the end).
+// e of a ray evaluates samples e, e+LPR, e+2 LPR, ...; per step of LPR
+// samples the lanes form the transmittance in front of each sample by a
+// DPP product scan, so all of them agree on the ray's transmittance and on
+// where it stops, and each accumulates its own samples' weighted colour
+// (the sums are added at the end).
 //
 // A wave marches its rays in rounds of `spr` samples.  Before a round it
 // stages, into its own LDS brick, every control point that the windows of
