@@ -35,6 +35,9 @@ from paper_2204_11762_amd import workloads as wl  # noqa: E402
 
 METRIC = "MFA samples/s (value+grad) BF16 vs FP32 at stated err; p50/p99 frame latency"
 PEAK_FP32_VALU = 157.3e12     # MI355X FP32 vector peak (packed issue)
+PEAK_HBM = 8.0e12             # MI355X HBM3E bytes/s
+CLOCK_HZ = 2.4e9              # MI355X peak engine clock
+N_CU = 256                    # MI355X compute units
 CSRC = os.path.join(ROOT, "paper_2204_11762_amd", "csrc")
 # every source that the device code is compiled from
 KERNEL_SOURCES = ["mfa_dev.h", "kernels_impl.h", "kernels.hip", "kernels_f32.hip",
@@ -65,6 +68,28 @@ def measured_traffic(store: str):
         return None
     leg = rec.get("legs", {}).get(store)
     return None if leg is None else leg.get("hbm_bytes_per_launch")
+
+
+def hbm_rate(traffic, kern_ms):
+    """Measured HBM bytes per launch over the kernel's mean duration, against
+    the 8 TB/s peak (None without a matching counter summary)."""
+    if traffic is None or not kern_ms:
+        return None
+    gbps = traffic / (kern_ms * 1e-3) / 1e9
+    return {"gb_per_s": gbps, "frac": gbps / (PEAK_HBM / 1e9)}
+
+
+def lds_rate(p: int, samples: int, kern_ms):
+    """Algorithmic LDS read bytes of the brick kernel: each composited sample
+    gathers its (p+1)^3 control points (FP32 in LDS) and two transfer-function
+    entries (16 B each).  Reported per compute unit and clock against the
+    LDS's 128 bytes per clock."""
+    if not kern_ms:
+        return None
+    per_sample = 4 * (p + 1) ** 3 + 32
+    per_clk = samples * per_sample / (kern_ms * 1e-3 * CLOCK_HZ * N_CU)
+    return {"bytes_per_sample": per_sample, "bytes_per_clk_per_cu": per_clk,
+            "peak_bytes_per_clk_per_cu": 128, "frac": per_clk / 128}
 
 
 def flops_per_sample(p: int) -> int:
@@ -556,8 +581,8 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the ray caster shards "
-              "by image tiles across GPUs, which this build does not launch.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the ray caster would "
+              "shard by image tiles across GPUs, which is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     log(f"kernel source sha256 {kernel_source_hash()}")
@@ -682,6 +707,8 @@ def main():
                      "flops_per_launch": flops,
                      "measured_fma_tflops": fma_tflops,
                      "frac_of_measured_fma": achieved / (fma_tflops * 1e12),
+                     "hbm": hbm_rate(measured_traffic(args.store), kern_ms),
+                     "lds": lds_rate(p, head["samples"], kern_ms),
                      "ert_off": None if head["nominal"] is None else {
                          "achieved": head["nominal"] * flops_per_sample(p)
                          / (head["nominal_ms"] * 1e-3) / 1e12,
