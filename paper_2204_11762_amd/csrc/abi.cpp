@@ -354,7 +354,8 @@ struct DeviceModel {
 // fallback kernel (lds_bytes = 0).
 constexpr int kMinBrick = 512;
 
-void plan_bricks(const DeviceModel& dm, int ntf, double step, bool curv, mfa::RenderArgsDev& a) {
+void plan_bricks(const DeviceModel& dm, int ntf, double step, bool curv, bool batch,
+                 mfa::RenderArgsDev& a) {
   const int tf_bytes = ntf * 16;
   int knot_doubles = 0;
   for (int k = 0; k < 3; ++k) {
@@ -371,7 +372,8 @@ void plan_bricks(const DeviceModel& dm, int ntf, double step, bool curv, mfa::Re
     return;
   }
   const int lds_budget =
-      mfa::brick_lds_per_group(mfa::brick_waves_per_simd(dm.md.pmax, a.fast != 0, a.eq != 0, curv));
+      mfa::brick_lds_per_group(
+          mfa::brick_waves_per_simd(dm.md.pmax, a.fast != 0, a.eq != 0, curv, batch));
   const int rest = lds_budget - tf_bytes - knot_bytes;
   const int cap = (rest / (4 * 4)) & ~3;
   if (cap < kMinBrick) {
@@ -786,13 +788,14 @@ mfa_status check_request(const DeviceModel& dm, const mfa_camera* cam, const mfa
 }
 
 // Kernel record of one validated request (camera frame, transfer function
-// at tf_dev, shading, LDS plan; curv: planned for the curvature variants'
-// occupancy).  The tile-plan scratch pointers are left for the caller;
+// at tf_dev, shading, LDS plan; curv, batch: planned for the occupancy of
+// the curvature variants or of the batch kernel).  The tile-plan scratch pointers are left for the caller;
 // ntiles receives the request's super-tiles (0 when the request uses the
 // global-memory kernel).
 void build_render_args(const DeviceModel& dm, const mfa_camera* cam, const mfa_tf* tf,
                        const mfa_render_params* prm, float* rgba_dev, int64_t* samples_dev,
-                       float4* tf_dev, mfa::RenderArgsDev& a, bool curv = false) {
+                       float4* tf_dev, mfa::RenderArgsDev& a, bool curv = false,
+                       bool batch = false) {
   Frame fr;
   camera_frame(cam, fr);
   a = mfa::RenderArgsDev{};
@@ -843,7 +846,7 @@ void build_render_args(const DeviceModel& dm, const mfa_camera* cam, const mfa_t
   a.samples = reinterpret_cast<unsigned long long*>(samples_dev);
   a.fast = dm.md.uniform && dm.md.ax[0].p >= 2 && dm.md.ax[1].p >= 2 && dm.md.ax[2].p >= 2;
   a.eq = dm.md.ax[0].p == dm.md.pmax && dm.md.ax[1].p == dm.md.pmax && dm.md.ax[2].p == dm.md.pmax;
-  plan_bricks(dm, tf->n, prm->step, curv, a);
+  plan_bricks(dm, tf->n, prm->step, curv, batch, a);
   if (dm.md.rational) {
     // the brick kernels are non-rational: rational models use the global kernel
     a.lds_bytes = 0;
@@ -922,7 +925,7 @@ class BatchBuilder {
     for (int32_t i = 0; i < n; ++i) {
       const mfa_render_request& r = reqs[i];
       build_render_args(*dms[i], r.camera, r.tf, r.params, r.rgba_dev, r.samples_dev, nullptr,
-                        args_[i]);
+                        args_[i], false, true);
       tables_[i].assign(r.tf->rgba, r.tf->rgba + size_t(r.tf->n) * 4);
       tf_off_[i] = off;
       off = align256(off + size_t(r.tf->n) * 16);

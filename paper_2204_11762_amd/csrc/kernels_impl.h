@@ -1691,7 +1691,7 @@ __device__ __forceinline__ int batch_request(const int32_t* base, int nreq, int 
 // class; workgroup b renders entry b of the class's work-sorted list.
 template <int P, int STORE, bool SHADE, bool FAST, bool EQ, int LPR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    brick_waves_per_simd(P, FAST, EQ)))) void render_batch_kernel(BatchDev b) {
+    brick_waves_per_simd(P, FAST, EQ, false, true)))) void render_batch_kernel(BatchDev b) {
   const int t = uniform_i(b.tile_order[blockIdx.x]);
   const int r = uniform_i(batch_request(b.tile_base, b.nreq, t));
   brick_render<P, STORE, SHADE, FAST, EQ, LPR>(b.args[r], t - b.tile_base[r]);

@@ -32,11 +32,15 @@ constexpr int kPlanHistWords = kXcdGroups * 512;
 // for (four workgroups of four waves per CU, or three for the variants
 // whose registers would otherwise spill; the curvature variants, which also
 // carry second derivatives, three at degree 2 on uniform knots and two
-// otherwise, up to kCurvBrickMaxDegree), and the LDS one
-// workgroup may use at that occupancy (160 KB per CU).
+// otherwise, up to kCurvBrickMaxDegree), and the LDS one workgroup may use
+// at that occupancy (160 KB per CU).  The batch kernel (batch) fits
+// general-knot degree 3 with equal degrees in four waves, where the
+// single-frame kernel would spill.
 __host__ __device__ constexpr int brick_waves_per_simd(int P, bool fast, bool eq,
-                                                      bool curv = false) {
-  return curv ? ((P >= 3 || !fast) ? 2 : 3) : (P >= 4 || (P == 3 && !fast && !eq)) ? 3 : 4;
+                                                      bool curv = false, bool batch = false) {
+  return curv    ? ((P >= 3 || !fast) ? 2 : 3)
+         : batch ? ((P >= 4 || (P == 3 && !fast && !eq)) ? 3 : 4)
+                 : ((P >= 4 || (P == 3 && !fast)) ? 3 : 4);
 }
 // Largest degree whose curvature rendering uses the brick ray caster (its
 // registers would spill above; such models use the global-memory kernel).
