@@ -386,6 +386,48 @@ __device__ __forceinline__ void cardinal(float t, float* N, float* dN) {
   }
 }
 
+// Second t-derivatives of the cardinal pieces of degree Q on a cell: the
+// second differences of the degree Q-2 pieces M (M_{-1} = M_{Q-1} = 0),
+// N''_r = M_r - 2 M_{r-1} + M_{r-2}; (1, -2, 1) at degree 2 and
+// (1 - t, 3t - 2, 1 - 3t, t) at degree 3.
+template <int Q>
+__device__ __forceinline__ void cardinal_dd(float t, float* ddN) {
+  if constexpr (Q == 1) {
+    ddN[0] = 0.0f;
+    ddN[1] = 0.0f;
+  } else if constexpr (Q == 2) {
+    ddN[0] = 1.0f;
+    ddN[1] = -2.0f;
+    ddN[2] = 1.0f;
+  } else {
+    float M[Q - 1], dM[Q - 1];
+    cardinal<Q - 2>(t, M, dM);
+#pragma unroll
+    for (int r = 0; r <= Q; ++r) {
+      const float m0 = r <= Q - 2 ? M[r] : 0.0f;
+      const float m1 = (r >= 1 && r - 1 <= Q - 2) ? M[r - 1] : 0.0f;
+      const float m2 = r >= 2 ? M[r - 2] : 0.0f;
+      ddN[r] = fmaf(-2.0f, m1, m0 + m2);
+    }
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void cardinal_dd_window(int q, float t, float (&ddN)[P + 1]) {
+  if (q == P) {
+    cardinal_dd<P>(t, ddN);
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i <= P; ++i) ddN[i] = 0.0f;
+  if constexpr (P >= 3) {
+    if (q == 2) cardinal_dd<2>(t, ddN);
+  }
+  if constexpr (P >= 4) {
+    if (q == 3) cardinal_dd<3>(t, ddN);
+  }
+}
+
 // The cubic pieces scaled for the render kernel: 6 N and 2 dN/dt.  The
 // scaled derivatives are -s^2, t (3t - 4), 1 + t (2 - 3t) and t^2 with
 // s = 1 - t, so a sample's value and gradient come out of the contraction
@@ -1201,12 +1243,11 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
   const int ray_lane = lane / LPR;   // ray of this lane within the tile
   const int e = lane % LPR;          // this lane's sample phase
   // world gradient factors: t-derivatives on the FAST path, u-derivatives
-  // on the GENERAL path and for curvature (whose bases come from the span
-  // tables on both paths)
+  // on the GENERAL path
   float gfac[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
-    gfac[k] = FAST && !CURV ? a.m.ax[k].gscale * (float)a.m.ax[k].m : a.m.ax[k].gscale;
+    gfac[k] = FAST ? a.m.ax[k].gscale * (float)a.m.ax[k].m : a.m.ax[k].gscale;
   // degree 3 on uniform knots: scaled cubic pieces (value x 216, gradient x 72)
   constexpr bool kScaled = FAST && EQ && P == 3 && !CURV;
   const float tf_lo = kScaled ? a.tf_lo * kCubicValueScale : a.tf_lo;
@@ -1464,31 +1505,52 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
       }
     };
 
-    // CURV: basis functions with first and second derivatives (in u) of
-    // this lane's sample from the span tables, on both paths
+    // CURV: basis functions with first and second derivatives of this
+    // lane's sample: FAST, in t (cardinal pieces on interior cells, the span
+    // table's triangle scaled to t on the boundary spans); GENERAL, in u
+    // from the span tables
     auto weights2 = [&](int s, int i, float (&N)[3][P + 1], float (&dN)[3][P + 1],
                         float (&ddN)[3][P + 1], int (&w)[3]) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const AxisDev& Ax = a.m.ax[k];
         const int q = EQ ? P : Ax.p;
-        int c;
-        float d;
         if constexpr (FAST) {
-          // cell from the FP32 stepping (clamped to the spans) and the
-          // offset from its left knot, c / m
           const int m = Ax.n - q;
           const float t = fmaf((float)i, dt[k], ta[k]);
-          c = min(max(ca[k] + (int)floorf(t), 0), m - 1);
-          d = (t - (float)(c - ca[k])) * Ax.inv_m;
+          const float fl = floorf(t);
+          int c = ca[k] + (int)fl;
+          if (c >= q - 1 && c <= m - q) {
+            const float tl = t - fl;
+            if constexpr (EQ) {
+              cardinal<P>(tl, N[k], dN[k]);
+              cardinal_dd<P>(tl, ddN[k]);
+            } else {
+              cardinal_window<P>(q, tl, N[k], dN[k]);
+              cardinal_dd_window<P>(q, tl, ddN[k]);
+            }
+          } else {
+            c = min(max(c, 0), m - 1);
+            const float tl = t - (float)(c - ca[k]);
+            const float* row = Ax.tab + (size_t)c * (size_t)table_stride(q);
+            axis_basis2<P>(q, row, tl * Ax.inv_m, N[k], dN[k], ddN[k]);
+            const float i2 = Ax.inv_m * Ax.inv_m;
+#pragma unroll
+            for (int r = 0; r <= P; ++r) {
+              dN[k][r] *= Ax.inv_m;
+              ddN[k][r] *= i2;
+            }
+          }
+          w[k] = c;
         } else {
           const double u = param(s, k);
           span_step(K[k], Ax.n, q, u, st[k]);
-          d = (float)(u - st[k].lo);
-          c = st[k].s - q;
+          const float d = (float)(u - st[k].lo);
+          const int c = st[k].s - q;
+          axis_basis2<P>(q, Ax.tab + (size_t)c * (size_t)table_stride(q), d, N[k], dN[k],
+                         ddN[k]);
+          w[k] = c;
         }
-        axis_basis2<P>(q, Ax.tab + (size_t)c * (size_t)table_stride(q), d, N[k], dN[k], ddN[k]);
-        w[k] = c;
       }
     };
     // CURV: value table, principal curvatures of the isosurface, curvature
