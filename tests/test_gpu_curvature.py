@@ -16,7 +16,7 @@ import copy
 import numpy as np
 import pytest
 
-from gpu_helpers import FP32_RMSE, compare_image, torch_mod
+from gpu_helpers import FP32_RMSE, compare_image, gpu_render, torch_mod
 from helpers import oracle_model
 from oracle import bspline as ob
 from oracle import quant
@@ -194,6 +194,52 @@ def test_curvature_errors(mfa):
         assert e.value.status == b.MFA_ERR_MODEL
     finally:
         b.mfa_model_free(ctx, hr)
+
+
+def test_concurrent_with_plain_renders(mfa):
+    """Curvature frames and plain frames of another model enqueued
+    alternately on two streams without synchronising in between (each
+    stream has its own tile-planning space) equal their solo renders bit for
+    bit."""
+    torch = torch_mod()
+    b, ctx = mfa
+    spec = _sphere_spec(58, degree=(3, 3, 3), n=(11, 11, 11), uniform=True)
+    ctf = wl.curvature_tf(16, 0.0, 2.5)
+    curv = [_workload(spec, size=sz, seed=9) for sz in (40, 56)]
+    plain = wl.c2()
+    plain.camera = wl.orbit_camera(96, 80, 60.0, 25.0)
+    hc = b.mfa_model_upload(ctx, spec)
+    hp = b.mfa_model_upload(ctx, plain.model)
+    try:
+        ref_c = [gpu_curvature_render(b, ctx, hc, w, ctf) for w in curv]
+        ref_p = gpu_render(b, ctx, hp, plain)
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        outs = [torch.zeros((w.camera.height, w.camera.width, 4), dtype=torch.float32,
+                            device="cuda") for w in curv]
+        out_p = torch.zeros((80, 96, 4), dtype=torch.float32, device="cuda")
+        cnts = [torch.zeros((1,), dtype=torch.int64, device="cuda") for _ in range(3)]
+        torch.cuda.synchronize()
+        for rep in range(3):
+            for i, w in enumerate(curv):
+                s = streams[i % 2]
+                with torch.cuda.stream(s):
+                    b.mfa_render_curvature(ctx, hc, w.camera, w.tf, ctf, w.params, outs[i],
+                                           cnts[i], stream=s)
+                    if i == 0:
+                        b.mfa_render(ctx, hp, plain.camera, plain.tf, plain.params, out_p,
+                                     cnts[2], stream=s)
+            torch.cuda.synchronize()
+            for i in range(2):
+                assert np.array_equal(outs[i].cpu().numpy().astype(np.float64), ref_c[i][0]), \
+                    f"repeat {rep}, curvature frame {i}"
+                assert int(cnts[i].item()) == ref_c[i][1]
+            assert np.array_equal(out_p.cpu().numpy().astype(np.float64), ref_p[0])
+            assert int(cnts[2].item()) == ref_p[1]
+            for o in outs + [out_p]:
+                o.fill_(-1.0)
+    finally:
+        b.mfa_model_free(ctx, hc)
+        b.mfa_model_free(ctx, hp)
 
 
 def test_curvature_frames_are_timed(mfa):
