@@ -732,7 +732,9 @@ def main():
         line["serve_saturated"] = saturated
     if base is not None:
         line["cpu_baseline"] = {"value": base["samples"] / base["wall"], "unit": "samples/s",
-                                "cores": cores, "kind": "oracle",
+                                "cores": cores,
+                                "per_core": base["samples"] / base["wall"] / cores,
+                                "kind": "oracle",
                                 "sample": f"{len(base['pix'])} rays of the same frame that meet the "
                                           f"volume, {base['samples']} samples, "
                                           f"{base['wall']:.1f} s wall",
