@@ -26,8 +26,9 @@
  *    evaluation calls are asynchronous on that stream.
  *  - A context is used by one host thread at a time.  Work it enqueues on
  *    different streams may run concurrently: every stream has its own
- *    planning space for mfa_render and mfa_render_curvature (a batch is the
- *    exception: see mfa_batch_render).
+ *    planning space for mfa_render and mfa_render_curvature and its own
+ *    ordering space for point queries (a batch is the exception: see
+ *    mfa_batch_render).
  */
 #ifndef MFA_DVR_H
 #define MFA_DVR_H
@@ -378,8 +379,14 @@ mfa_status mfa_measure_fma_peak(mfa_ctx* ctx, double* tflops);
  * gradient query, all three derivatives at once) at n world points
  * xyz_dev (n*3 FP64, point-major).  Points outside the box are clamped to
  * it.  value_dev: n FP32; grad_dev: n*3 FP32 or null for value only.
- * n = 0 is a no-op.  Asynchronous on `stream`.  Errors: MFA_ERR_INVALID
- * (n < 0, null buffers with n > 0), MFA_ERR_HANDLE, MFA_ERR_DEVICE. */
+ * n = 0 is a no-op.  Asynchronous on `stream`.  From 2^16 points on, the
+ * points are binned on the device (an 8^3 grid over the box, in Morton
+ * order) and evaluated bin by bin unless a probe finds neighbouring points
+ * already in the same bins; results stay in the caller's order and equal
+ * those of a direct query bit for bit.  This uses 6 bytes of device memory
+ * per point in the stream's scratch, kept until the context is destroyed.
+ * Errors: MFA_ERR_INVALID (n < 0, null buffers with n > 0), MFA_ERR_HANDLE,
+ * MFA_ERR_NOMEM, MFA_ERR_DEVICE. */
 mfa_status mfa_eval_points(mfa_ctx* ctx, int64_t model, int64_t n, const double* xyz_dev,
                            float* value_dev, float* grad_dev, void* stream);
 

@@ -447,6 +447,14 @@ struct PlanScratch {
   void* mem = nullptr;
   int64_t tiles = 0;
 };
+// Point-query locality scratch of one stream: bins, order, counters.
+struct EvalScratch {
+  void* mem = nullptr;
+  int64_t points = 0;
+};
+// Point queries from this many points on are evaluated in locality order
+// (binned on the device; skipped there when the input is already local).
+constexpr int64_t kEvalOrderMin = int64_t(1) << 16;
 constexpr size_t kMaxPlanStreams = 16;
 
 struct mfa_ctx {
@@ -461,6 +469,8 @@ struct mfa_ctx {
   // planning scratch by stream: renders on one stream are ordered by it,
   // renders on different streams never share planning space
   std::unordered_map<void*, PlanScratch> plans;
+  // point-query ordering scratch by stream, for the same reason
+  std::unordered_map<void*, EvalScratch> evals;
   // kernel timing: event pairs, the first `timed` of which are recorded
   bool timing = false;
   std::vector<mfa::KernelEvents> events;
@@ -469,6 +479,11 @@ struct mfa_ctx {
   void free_plans() {
     for (auto& kv : plans) (void)hipFree(kv.second.mem);
     plans.clear();
+  }
+
+  void free_evals() {
+    for (auto& kv : evals) (void)hipFree(kv.second.mem);
+    evals.clear();
   }
 
   void free_tfs() {
@@ -558,6 +573,43 @@ mfa_status attach_plan(mfa_ctx* ctx, void* stream, int64_t tiles, mfa::RenderArg
   return MFA_OK;
 }
 
+// The ordering scratch of `stream`, grown to at least `points` points, laid
+// out in `o` (counters first, then the order, then the bins).  As for the
+// planning scratch, a buffer that must be released may still be read by
+// enqueued kernels, so the device is synchronised first.
+mfa_status attach_eval(mfa_ctx* ctx, void* stream, int64_t points, mfa::EvalOrderDev& o) {
+  auto it = ctx->evals.find(stream);
+  if (it == ctx->evals.end() || it->second.points < points) {
+    const bool grow = it != ctx->evals.end();
+    if (grow || ctx->evals.size() >= kMaxPlanStreams) {
+      const hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("hipDeviceSynchronize", e));
+      if (grow) {
+        (void)hipFree(it->second.mem);
+        ctx->evals.erase(it);
+      } else {
+        ctx->free_evals();
+      }
+    }
+    EvalScratch es;
+    const size_t bytes = size_t(2 * mfa::kEvalBins + 64) * 4 + size_t(points) * 6 + 256;
+    const hipError_t e = hipMalloc(&es.mem, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MFA_ERR_NOMEM, hip_msg("hipMalloc (point order)", e));
+    }
+    es.points = points;
+    it = ctx->evals.emplace(stream, es).first;
+  }
+  unsigned* base = static_cast<unsigned*>(it->second.mem);
+  o.counts = base;
+  o.cursor = base + mfa::kEvalBins;
+  o.flags = base + 2 * mfa::kEvalBins;
+  o.order = reinterpret_cast<int32_t*>(base + 2 * mfa::kEvalBins + 64);
+  o.bin = reinterpret_cast<uint16_t*>(o.order + it->second.points);
+  return MFA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -612,6 +664,7 @@ mfa_status mfa_destroy(mfa_ctx* ctx) {
     ctx->models.clear();
     ctx->free_tfs();
     ctx->free_plans();
+    ctx->free_evals();
     for (auto& ev : ctx->events) {
       (void)hipEventDestroy(ev.begin);
       (void)hipEventDestroy(ev.end);
@@ -1385,6 +1438,23 @@ mfa_status eval_common(mfa_ctx* ctx, int64_t model, int64_t n, const double* xyz
   a.grad = grad_dev;
   a.hess = hess_dev;
   a.n = n;
+  a.order = nullptr;
+  a.use_order = nullptr;
+  if (n >= kEvalOrderMin && n <= int64_t(INT32_MAX)) {
+    mfa::EvalOrderDev o{};
+    const mfa_status st = attach_eval(ctx, stream, n, o);
+    if (st != MFA_OK) return st;
+    o.xyz = xyz_dev;
+    o.n = n;
+    for (int k = 0; k < 3; ++k) {
+      o.lo[k] = dm.md.ax[k].lo;
+      o.inv_ext[k] = dm.md.ax[k].inv_ext;
+    }
+    const hipError_t eo = mfa::launch_eval_order(o, static_cast<hipStream_t>(stream));
+    if (eo != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("point order launch", eo));
+    a.order = o.order;
+    a.use_order = o.flags + 1;
+  }
   const hipError_t e = mfa::launch_eval(a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("eval launch", e));
   return MFA_OK;

@@ -49,6 +49,18 @@ hipError_t launch_render_batch(const BatchDev& b, const BatchKey& k, hipStream_t
   }
 }
 
+hipError_t launch_eval_order(const EvalOrderDev& o, hipStream_t st) {
+  if (o.n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((o.n + kEvalOrderChunk - 1) / kEvalOrderChunk);
+  if (o.n < int64_t(64) * kEvalProbeWaves) return hipErrorInvalidValue;
+  eval_order_zero<<<1, kEvalBins, 0, st>>>(o);
+  eval_order_probe<<<kEvalProbeWaves / 4, 256, 0, st>>>(o);
+  eval_order_bin<<<blocks, 256, 0, st>>>(o);
+  eval_order_scan<<<1, kEvalBins, 0, st>>>(o);
+  eval_order_scatter<<<blocks, 256, 0, st>>>(o);
+  return hipGetLastError();
+}
+
 hipError_t launch_eval(const EvalArgsDev& a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
   switch (a.m.store) {

@@ -1898,10 +1898,17 @@ __global__ __launch_bounds__(256) void batch_cost_kernel(BatchDev b) {
     if (h[i] != 0u) atomicAdd(&b.tile_hist[i], h[i]);
 }
 
+// Index of the point that thread t evaluates: the locality order's entry
+// when the binning pass chose it, else t.
+__device__ __forceinline__ int64_t eval_point(const EvalArgsDev& a, int64_t t) {
+  return (a.order != nullptr && *a.use_order != 0u) ? (int64_t)a.order[t] : t;
+}
+
 template <int P, int STORE, bool GRAD, bool RAT>
 __global__ __launch_bounds__(256) void eval_kernel(EvalArgsDev a) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= a.n) return;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.n) return;
+  const int64_t i = eval_point(a, t);
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.m.ctrl, a.m.ctrl_bytes);
   const __amdgpu_buffer_rsrc_t rsw = make_rsrc(RAT ? a.m.wctrl : a.m.ctrl,
                                                RAT ? a.m.wctrl_bytes : a.m.ctrl_bytes);
@@ -1926,8 +1933,9 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgsDev a) {
 // Value, world gradient and world Hessian at points (non-rational models).
 template <int P, int STORE>
 __global__ __launch_bounds__(256) void eval_hess_kernel(EvalArgsDev a) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= a.n) return;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.n) return;
+  const int64_t i = eval_point(a, t);
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.m.ctrl, a.m.ctrl_bytes);
   double u[3];
 #pragma unroll
@@ -1947,6 +1955,123 @@ __global__ __launch_bounds__(256) void eval_hess_kernel(EvalArgsDev a) {
   float* o = a.hess + 6 * i;
 #pragma unroll
   for (int c = 0; c < 6; ++c) o[c] = h[c];
+}
+
+// ---------------------------------------------------------------------------
+// locality order of point queries: a counting sort by bin
+// ---------------------------------------------------------------------------
+
+// Bin of a point: its cell on an 8^3 grid over the box, the three 3-bit
+// cell indices interleaved (Morton order, x lowest).
+__device__ __forceinline__ unsigned eval_bin(const EvalOrderDev& o, int64_t i) {
+  unsigned code = 0u;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double u = fmin(fmax((o.xyz[3 * i + k] - o.lo[k]) * o.inv_ext[k], 0.0), 1.0);
+    const unsigned c = (unsigned)min((int)(u * (double)(1 << kEvalBinBits)),
+                                     (1 << kEvalBinBits) - 1);
+#pragma unroll
+    for (int b = 0; b < kEvalBinBits; ++b) code |= ((c >> b) & 1u) << (3 * b + k);
+  }
+  return code;
+}
+
+__global__ __launch_bounds__(kEvalBins) void eval_order_zero(EvalOrderDev o) {
+  o.counts[threadIdx.x] = 0u;
+  if (threadIdx.x < 2) o.flags[threadIdx.x] = 0u;
+}
+
+// Whether to order: kEvalProbeWaves waves, spread evenly over the points,
+// each compare the bins of 64 consecutive points; the order is used when
+// more than one neighbouring pair in eight changes bin.  Every kernel of
+// the ordering takes the decision from the probe's count alone.
+constexpr int kEvalProbeWaves = 256;
+__device__ __forceinline__ bool eval_use_order(const EvalOrderDev& o) {
+  return (uint64_t)o.flags[0] * 8u > (uint64_t)kEvalProbeWaves * 63u;
+}
+
+// Needs n >= 64 kEvalProbeWaves (the host orders from 2^16 points on).
+__global__ __launch_bounds__(256) void eval_order_probe(EvalOrderDev o) {
+  const int lane = threadIdx.x & 63;
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t i = (int64_t)w * (o.n / kEvalProbeWaves) + lane;
+  const unsigned code = eval_bin(o, i);
+  const unsigned prev = (unsigned)__shfl_up((int)code, 1, 64);
+  const unsigned long long m = __ballot(lane > 0 && prev != code);
+  if (lane == 0 && m != 0ull) atomicAdd(&o.flags[0], (unsigned)__popcll(m));
+}
+
+// Workgroup g bins points [g C, g C + C) (C = kEvalOrderChunk; thread t
+// takes g C + t + 256 j): bin numbers and points per bin, counted in LDS
+// with one global atomic per bin and workgroup.
+__global__ __launch_bounds__(256) void eval_order_bin(EvalOrderDev o) {
+  if (!eval_use_order(o)) return;
+  __shared__ unsigned hist[kEvalBins];
+  const int tid = threadIdx.x;
+  for (int b = tid; b < kEvalBins; b += 256) hist[b] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kEvalOrderChunk;
+  for (int j = 0; j < kEvalOrderChunk / 256; ++j) {
+    const int64_t i = base + j * 256 + tid;
+    if (i < o.n) {
+      const unsigned code = eval_bin(o, i);
+      o.bin[i] = (uint16_t)code;
+      atomicAdd(&hist[code], 1u);
+    }
+  }
+  __syncthreads();
+  for (int b = tid; b < kEvalBins; b += 256)
+    if (hist[b] != 0u) atomicAdd(&o.counts[b], hist[b]);
+}
+
+// Exclusive prefix sum of the bin counts into the cursors, and the
+// decision for the evaluation kernel.
+__global__ __launch_bounds__(kEvalBins) void eval_order_scan(EvalOrderDev o) {
+  const bool use = eval_use_order(o);
+  if (threadIdx.x == 0) o.flags[1] = use ? 1u : 0u;
+  if (!use) return;
+  __shared__ unsigned part[kEvalBins];
+  const int tid = threadIdx.x;
+  const unsigned v = o.counts[tid];
+  part[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < kEvalBins; off <<= 1) {
+    const unsigned x = tid >= off ? part[tid - off] : 0u;
+    __syncthreads();
+    part[tid] += x;
+    __syncthreads();
+  }
+  o.cursor[tid] = part[tid] - v;
+}
+
+// Point indices bin by bin: workgroup g takes the points it binned, ranks
+// them within their bins in LDS, reserves one range per bin with a global
+// atomic, and writes them there (the order within a bin is arbitrary: every
+// point's result is independent of it).
+__global__ __launch_bounds__(256) void eval_order_scatter(EvalOrderDev o) {
+  if (!eval_use_order(o)) return;
+  __shared__ unsigned cnt[kEvalBins];
+  const int tid = threadIdx.x;
+  for (int b = tid; b < kEvalBins; b += 256) cnt[b] = 0u;
+  __syncthreads();
+  constexpr int J = kEvalOrderChunk / 256;
+  const int64_t base = (int64_t)blockIdx.x * kEvalOrderChunk;
+  unsigned code[J], rank[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int64_t i = base + j * 256 + tid;
+    code[j] = i < o.n ? (unsigned)o.bin[i] : 0u;
+    rank[j] = i < o.n ? atomicAdd(&cnt[code[j]], 1u) : 0u;
+  }
+  __syncthreads();
+  for (int b = tid; b < kEvalBins; b += 256)
+    if (cnt[b] != 0u) cnt[b] = atomicAdd(&o.cursor[b], cnt[b]);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int64_t i = base + j * 256 + tid;
+    if (i < o.n) o.order[cnt[code[j]] + rank[j]] = (int32_t)i;
+  }
 }
 
 // FP32 FMA issue ceiling: eight independent FMA chains per lane, so that

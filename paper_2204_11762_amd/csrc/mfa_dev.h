@@ -155,6 +155,29 @@ struct EvalArgsDev {
   float* grad;          // nullable
   float* hess;          // nullable: n*6 second derivatives (xx, yy, zz, xy, xz, yz)
   int64_t n;
+  // locality order (nullable): thread i evaluates point order[i] when
+  // *use_order is non-zero (set on the device by the binning pass)
+  const int32_t* order;
+  const unsigned* use_order;
+};
+
+// Locality ordering of large point queries: the points are binned on an
+// 8^3 grid over the box, the bins numbered in Morton order, and evaluated
+// bin by bin, unless consecutive points already share bins.  A workgroup
+// bins kEvalOrderChunk points with LDS counters.
+constexpr int kEvalBinBits = 3;
+constexpr int kEvalBins = 1 << (3 * kEvalBinBits);
+constexpr int kEvalOrderChunk = 4096;
+struct EvalOrderDev {
+  const double* xyz;
+  int64_t n;              // <= INT32_MAX
+  double lo[3];
+  double inv_ext[3];
+  uint16_t* bin;          // n bin numbers
+  unsigned* counts;       // kEvalBins points per bin
+  unsigned* cursor;       // kEvalBins next free slot per bin
+  unsigned* flags;        // [0] bin changes among the probed neighbours, [1] use the order
+  int32_t* order;         // n point indices, bin by bin
 };
 
 // The requests of a render batch that share one kernel variant (a class):
@@ -190,6 +213,7 @@ struct KernelEvents {
 hipError_t launch_render(const RenderArgsDev& a, hipStream_t stream, const KernelEvents& ev);
 hipError_t launch_render_batch(const BatchDev& b, const BatchKey& k, hipStream_t stream);
 hipError_t launch_eval(const EvalArgsDev& a, hipStream_t stream);
+hipError_t launch_eval_order(const EvalOrderDev& o, hipStream_t stream);
 // FP32 FMA micro-loop: blocks x 256 threads, iters x 8 FMA each
 hipError_t launch_fma_peak(float* out, int blocks, int iters, hipStream_t stream);
 

@@ -178,3 +178,49 @@ def test_eval_zero_points_is_noop(mfa):
         torch.cuda.synchronize()
     finally:
         b.mfa_model_free(ctx, h)
+
+
+def _morton_sorted(xyz, bits=10):
+    q = np.clip((xyz * (1 << bits)).astype(np.int64), 0, (1 << bits) - 1)
+    code = np.zeros(len(xyz), dtype=np.int64)
+    for bit in range(bits):
+        for k in range(3):
+            code |= ((q[:, k] >> bit) & 1) << (3 * bit + k)
+    return xyz[np.argsort(code, kind="stable")]
+
+
+def test_locality_order_equals_direct(mfa):
+    """From 2^16 points on, queries are binned on the device and evaluated
+    bin by bin (unless neighbouring points already share bins).  Each
+    point's value, gradient and second derivatives are those of the same
+    point queried directly, bit for bit: scattered points (reordered),
+    points sorted along a Morton curve (left in place), and points outside
+    the box; the oracle checks a sample."""
+    torch = __import__("torch")
+    b, ctx = mfa
+    rng = np.random.default_rng(77)
+    spec = wl.random_model(rng, n=(40, 36, 44), degree=(3, 3, 3), beta_knots=True)
+    h = b.mfa_model_upload(ctx, spec)
+    n, chunk = 200_003, 50_000            # above and below the ordering threshold
+    scattered = wl.uniform_points(rng, n, np.full(3, -0.05), np.full(3, 1.05))
+    try:
+        for name, xyz in (("scattered", scattered), ("morton", _morton_sorted(scattered))):
+            f, g = gpu_eval(b, ctx, h, xyz)
+            parts = [gpu_eval(b, ctx, h, xyz[s:s + chunk]) for s in range(0, n, chunk)]
+            np.testing.assert_array_equal(f, np.concatenate([p[0] for p in parts]), err_msg=name)
+            np.testing.assert_array_equal(g, np.concatenate([p[1] for p in parts]), err_msg=name)
+            x = torch.from_numpy(np.ascontiguousarray(xyz)).cuda()
+            outs = []
+            for lo_i, hi_i in ((0, n),) + tuple((s, min(s + chunk, n)) for s in range(0, n, chunk)):
+                m = hi_i - lo_i
+                v = torch.full((m,), np.nan, dtype=torch.float32, device="cuda")
+                hs = torch.full((m, 6), np.nan, dtype=torch.float32, device="cuda")
+                b.mfa_eval_hessian(ctx, h, x[lo_i:hi_i].contiguous(), v, hs)
+                torch.cuda.synchronize()
+                outs.append(hs.cpu().numpy())
+            np.testing.assert_array_equal(outs[0], np.concatenate(outs[1:]), err_msg=name)
+            pick = rng.choice(n, 2000, replace=False)
+            F, G = ob.eval_world(oracle_model(spec), xyz[pick])
+            assert normwise(f[pick], F) <= FP32_REL and normwise(g[pick], G) <= FP32_REL
+    finally:
+        b.mfa_model_free(ctx, h)
