@@ -190,8 +190,9 @@ def _morton_sorted(xyz, bits=10):
 
 
 def test_locality_order_equals_direct(mfa):
-    """From 2^16 points on, queries are binned on the device and evaluated
-    bin by bin (unless neighbouring points already share bins).  Each
+    """From 2^16 points on, queries of a model whose gathers miss the
+    caches are binned on the device and evaluated bin by bin (unless
+    neighbouring points already share bins).  Each
     point's value, gradient and second derivatives are those of the same
     point queried directly, bit for bit: scattered points (reordered),
     points sorted along a Morton curve (left in place), and points outside
@@ -199,7 +200,9 @@ def test_locality_order_equals_direct(mfa):
     torch = __import__("torch")
     b, ctx = mfa
     rng = np.random.default_rng(77)
-    spec = wl.random_model(rng, n=(40, 36, 44), degree=(3, 3, 3), beta_knots=True)
+    # 1.07 MB of FP32 control points at degree 3: large enough for the
+    # ordering (sqrt(bytes) * (p+1)^3 = 6.6e4 >= 4e4)
+    spec = wl.random_model(rng, n=(64, 60, 70), degree=(3, 3, 3), beta_knots=True)
     h = b.mfa_model_upload(ctx, spec)
     n, chunk = 200_003, 50_000            # above and below the ordering threshold
     scattered = wl.uniform_points(rng, n, np.full(3, -0.05), np.full(3, 1.05))
