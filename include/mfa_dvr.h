@@ -384,9 +384,10 @@ mfa_status mfa_measure_fma_peak(mfa_ctx* ctx, double* tflops);
  * order) and evaluated bin by bin unless a probe finds neighbouring points
  * already in the same bins; results stay in the caller's order and equal
  * those of a direct query bit for bit.  This uses 6 bytes of device memory
- * per point in the stream's scratch, kept until the context is destroyed.
+ * per point in the stream's scratch, kept until the context is destroyed;
+ * if it cannot be allocated, the points are evaluated in the given order.
  * Errors: MFA_ERR_INVALID (n < 0, null buffers with n > 0), MFA_ERR_HANDLE,
- * MFA_ERR_NOMEM, MFA_ERR_DEVICE. */
+ * MFA_ERR_DEVICE. */
 mfa_status mfa_eval_points(mfa_ctx* ctx, int64_t model, int64_t n, const double* xyz_dev,
                            float* value_dev, float* grad_dev, void* stream);
 

@@ -1451,6 +1451,14 @@ mfa_status eval_common(mfa_ctx* ctx, int64_t model, int64_t n, const double* xyz
   if (n >= kEvalOrderMin && n <= int64_t(INT32_MAX) && score >= kEvalOrderScore) {
     mfa::EvalOrderDev o{};
     const mfa_status st = attach_eval(ctx, stream, n, o);
+    if (st == MFA_ERR_NOMEM) {
+      // the order is an optimisation: without its scratch, evaluate the
+      // points as given
+      g_last_error.clear();
+      const hipError_t e = mfa::launch_eval(a, static_cast<hipStream_t>(stream));
+      if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("eval launch", e));
+      return MFA_OK;
+    }
     if (st != MFA_OK) return st;
     o.xyz = xyz_dev;
     o.n = n;
