@@ -442,10 +442,16 @@ struct RenderBatch {
 };
 
 // Planning scratch of one stream: cost and order arrays of `tiles` entries
-// each (launch slots), then kPlanHistWords bucket counters.
+// each (launch slots), then two sets of bucket counters (kPlanWords).
+// Frames alternate between the sets (`parity` names the next frame's), and
+// each frame clears the set of the frame before it, so the next frame's set
+// is zero.  An init launch clears both on a fresh buffer (ready = false); a
+// frame whose launches fail part-way clears `ready`.
 struct PlanScratch {
   void* mem = nullptr;
   int64_t tiles = 0;
+  bool ready = false;
+  int parity = 0;
 };
 // Point-query locality scratch of one stream: bins, order, counters.
 struct EvalScratch {
@@ -541,11 +547,12 @@ mfa_status tf_device(mfa_ctx* ctx, const mfa_tf* tf, float4** out) {
 }
 
 // The planning scratch of `stream`, grown to at least `tiles` launch slots,
-// and its arrays attached to the records `a`.  A buffer that must grow, or
-// the whole set once it holds kMaxPlanStreams streams, may still be read by
-// enqueued kernels, so the device is synchronised before release.
-mfa_status attach_plan(mfa_ctx* ctx, void* stream, int64_t tiles, mfa::RenderArgsDev* a,
-                       int na) {
+// and its arrays attached to the records `a` (the counters are attached
+// per launch, by plan_counters).  A buffer that must grow, or the whole set
+// once it holds kMaxPlanStreams streams, may still be read by enqueued
+// kernels, so the device is synchronised before release.
+mfa_status attach_plan(mfa_ctx* ctx, void* stream, int64_t tiles, mfa::RenderArgsDev* a, int na,
+                       PlanScratch** out) {
   auto it = ctx->plans.find(stream);
   if (it == ctx->plans.end() || it->second.tiles < tiles) {
     const bool grow = it != ctx->plans.end();
@@ -560,23 +567,47 @@ mfa_status attach_plan(mfa_ctx* ctx, void* stream, int64_t tiles, mfa::RenderArg
       }
     }
     PlanScratch ps;
-    const size_t bytes = size_t(tiles) * 8 + size_t(mfa::kPlanHistWords) * 4 + 256;
+    // whole groups of 64 slots keep the counters 256-byte aligned
+    const int64_t slots = (tiles + 63) & ~int64_t(63);
+    const size_t bytes = size_t(slots) * 8 + size_t(mfa::kPlanWords) * 4;
     const hipError_t e = hipMalloc(&ps.mem, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(MFA_ERR_NOMEM, hip_msg("hipMalloc (tile queue)", e));
     }
-    ps.tiles = tiles;
+    ps.tiles = slots;
     it = ctx->plans.emplace(stream, ps).first;
   }
   int32_t* base = static_cast<int32_t*>(it->second.mem);
   const int64_t n = it->second.tiles;
+  if (!it->second.ready) {
+    const hipError_t e = mfa::launch_plan_init(reinterpret_cast<unsigned*>(base + 2 * n),
+                                               static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("tile queue init", e));
+    it->second.ready = true;
+    it->second.parity = 0;
+  }
   for (int i = 0; i < na; ++i) {
     a[i].tile_cost = base;
     a[i].tile_order = base + n;
-    a[i].tile_hist = reinterpret_cast<unsigned*>(base + 2 * n);
   }
+  *out = &it->second;
   return MFA_OK;
+}
+
+// The counter sets of the next frame planned in `ps`, attached to `a`.
+void plan_counters(PlanScratch& ps, mfa::RenderArgsDev& a) {
+  unsigned* c = reinterpret_cast<unsigned*>(static_cast<int32_t*>(ps.mem) + 2 * ps.tiles);
+  a.tile_hist = c + ps.parity * 2 * mfa::kPlanHistWords;
+  a.tile_clear = c + (1 - ps.parity) * 2 * mfa::kPlanHistWords;
+  ps.parity ^= 1;
+}
+
+// After a failed launch the planning scratch of `stream` may be left part-way
+// through a frame: the next frame initialises it again.
+void plan_unready(mfa_ctx* ctx, void* stream) {
+  auto it = ctx->plans.find(stream);
+  if (it != ctx->plans.end()) it->second.ready = false;
 }
 
 // The ordering scratch of `stream`, grown to at least `points` points, laid
@@ -1080,7 +1111,8 @@ namespace {
 
 // Launch one frame; while kernel timing is on, with a pair of HIP events
 // around the ray-casting kernel (at most kMaxTimedLaunches per record).
-mfa_status launch_timed(mfa_ctx* ctx, const mfa::RenderArgsDev& a, void* stream) {
+mfa_status launch_timed(mfa_ctx* ctx, mfa::RenderArgsDev& a, PlanScratch* ps, void* stream) {
+  if (ps != nullptr) plan_counters(*ps, a);
   mfa::KernelEvents ev;
   if (ctx->timing && ctx->timed < kMaxTimedLaunches) {
     if (ctx->timed == ctx->events.size()) {
@@ -1090,13 +1122,19 @@ mfa_status launch_timed(mfa_ctx* ctx, const mfa::RenderArgsDev& a, void* stream)
         e = hipEventCreate(&fresh.end);
         if (e != hipSuccess) (void)hipEventDestroy(fresh.begin);
       }
-      if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("hipEventCreate", e));
+      if (e != hipSuccess) {
+        plan_unready(ctx, stream);
+        return fail(MFA_ERR_DEVICE, hip_msg("hipEventCreate", e));
+      }
       ctx->events.push_back(fresh);
     }
     ev = ctx->events[ctx->timed];
   }
   const hipError_t e = mfa::launch_render(a, static_cast<hipStream_t>(stream), ev);
-  if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("render launch", e));
+  if (e != hipSuccess) {
+    plan_unready(ctx, stream);
+    return fail(MFA_ERR_DEVICE, hip_msg("render launch", e));
+  }
   if (ev.begin != nullptr) ctx->timed += 1;
   return MFA_OK;
 }
@@ -1124,11 +1162,12 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const 
 
   mfa::RenderArgsDev a;
   build_render_args(dm, cam, tf, prm, rgba_dev, samples_dev, tf_dev, a);
+  PlanScratch* ps = nullptr;
   if (a.ntiles > 0) {
-    st = attach_plan(ctx, stream, a.nslots, &a, 1);
+    st = attach_plan(ctx, stream, a.nslots, &a, 1, &ps);
     if (st != MFA_OK) return st;
   }
-  return launch_timed(ctx, a, stream);
+  return launch_timed(ctx, a, ps, stream);
 }
 
 mfa_status mfa_render_curvature(mfa_ctx* ctx, int64_t model, const mfa_camera* cam,
@@ -1182,11 +1221,12 @@ mfa_status mfa_render_curvature(mfa_ctx* ctx, int64_t model, const mfa_camera* c
   a.ctf_m = ctf->m;
   a.ctf_lo = float(ctf->k_lo);
   a.ctf_scale = float(1.0 / (ctf->k_hi - ctf->k_lo));
+  PlanScratch* ps = nullptr;
   if (a.ntiles > 0) {
-    st = attach_plan(ctx, stream, a.nslots, &a, 1);
+    st = attach_plan(ctx, stream, a.nslots, &a, 1, &ps);
     if (st != MFA_OK) return st;
   }
-  return launch_timed(ctx, a, stream);
+  return launch_timed(ctx, a, ps, stream);
 }
 
 mfa_status mfa_measure_fma_peak(mfa_ctx* ctx, double* tflops) {
@@ -1286,8 +1326,9 @@ mfa_status mfa_autotune(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, cons
     slots = std::max<int64_t>(slots, args[c].nslots);
   }
   dm.round_spans = saved;
+  PlanScratch* ps = nullptr;
   if (args[0].ntiles > 0) {
-    st = attach_plan(ctx, stream, slots, args.data(), kCand);
+    st = attach_plan(ctx, stream, slots, args.data(), kCand, &ps);
     if (st != MFA_OK) return st;
   }
   const int total = kCand * (repeats + 1);
@@ -1303,7 +1344,11 @@ mfa_status mfa_autotune(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, cons
   }
   if (e != hipSuccess) --made;
   for (int r = 0, k = 0; r <= repeats && e == hipSuccess; ++r)   // round 0: warm-up
-    for (int c = 0; c < kCand && e == hipSuccess; ++c, ++k) e = mfa::launch_render(args[c], hs, evs[k]);
+    for (int c = 0; c < kCand && e == hipSuccess; ++c, ++k) {
+      if (ps != nullptr) plan_counters(*ps, args[c]);
+      e = mfa::launch_render(args[c], hs, evs[k]);
+    }
+  if (e != hipSuccess) plan_unready(ctx, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(hs);
   double best = saved, best_ms = 1e30, default_ms = 0.0;
   for (int c = 0; c < kCand && e == hipSuccess; ++c) {

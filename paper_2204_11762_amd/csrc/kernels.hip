@@ -25,6 +25,11 @@ hipError_t launch_fma_peak(float* out, int blocks, int iters, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_plan_init(unsigned* hist, hipStream_t st) {
+  plan_init_kernel<<<(kPlanWords + 255) / 256, 256, 0, st>>>(hist, kPlanWords);
+  return hipGetLastError();
+}
+
 hipError_t launch_render(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
   if (a.samples != nullptr) {
     zero_counter<<<1, 64, 0, st>>>(a.samples);

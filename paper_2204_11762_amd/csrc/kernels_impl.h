@@ -1776,46 +1776,57 @@ __device__ __forceinline__ int xcd_group(int t, int nsx, int region) {
   return ((sx / region) + 3 * (sy / region)) & (kXcdGroups - 1);
 }
 
-// Clear G x kBuckets counters and mark every launch slot empty.
-__global__ __launch_bounds__(256) void plan_zero_kernel(unsigned* hist, int nhist, int* order,
-                                                        int nslots) {
+// Clear nhist counters: the state in which a frame's planning finds its
+// scratch (set up once per buffer, then kept by plan_cost_kernel).
+__global__ __launch_bounds__(256) void plan_init_kernel(unsigned* hist, int nhist) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < nhist) hist[i] = 0u;
-  if (i < nslots) order[i] = -1;
 }
 
 // Work estimate of every super-tile (2x2 tiles of tile_w x tile_h pixels):
 // the largest sample count among nine rays (corners, edge midpoints and
-// centre of its pixel rectangle).
-__device__ __forceinline__ int supertile_cost(const RenderArgsDev& a, int t) {
+// centre of its pixel rectangle).  Part r (0..3) takes rays r, r + 4 and
+// r + 8 of the nine (row-major over the 3x3 points).
+__device__ __forceinline__ int supertile_cost_part(const RenderArgsDev& a, int t, int r) {
   const int ntx = (a.width + a.tile_w - 1) / a.tile_w;
   const int nsx = (ntx + 1) >> 1;
   const int x0 = (t % nsx) * 2 * a.tile_w, y0 = (t / nsx) * 2 * a.tile_h;
   const int x1 = min(x0 + 2 * a.tile_w - 1, a.width - 1);
   const int y1 = min(y0 + 2 * a.tile_h - 1, a.height - 1);
-  const int xm = (x0 + x1) >> 1, ym = (y0 + y1) >> 1;
   int c = 0;
-  c = max(c, make_ray(a.cam, y0, x0).nr);
-  c = max(c, make_ray(a.cam, y0, xm).nr);
-  c = max(c, make_ray(a.cam, y0, x1).nr);
-  c = max(c, make_ray(a.cam, ym, x0).nr);
-  c = max(c, make_ray(a.cam, ym, xm).nr);
-  c = max(c, make_ray(a.cam, ym, x1).nr);
-  c = max(c, make_ray(a.cam, y1, x0).nr);
-  c = max(c, make_ray(a.cam, y1, xm).nr);
-  c = max(c, make_ray(a.cam, y1, x1).nr);
+  for (int j = r; j < 9; j += 4) {
+    const int jy = j / 3, jx = j - 3 * jy;
+    const int y = jy == 0 ? y0 : jy == 1 ? (y0 + y1) >> 1 : y1;
+    const int x = jx == 0 ? x0 : jx == 1 ? (x0 + x1) >> 1 : x1;
+    c = max(c, make_ray(a.cam, y, x).nr);
+  }
   return c;
 }
 
-// Single frame: work estimates and the per-group bucket histogram.
+__device__ __forceinline__ int supertile_cost(const RenderArgsDev& a, int t) {
+  int c = 0;
+  for (int r = 0; r < 4; ++r) c = max(c, supertile_cost_part(a, t, r));
+  return c;
+}
+
+// Single frame: work estimates and the per-group bucket histogram.  Four
+// lanes share a super-tile's nine rays; the histogram is gathered in LDS
+// and added to the frame's counters.  Frames on a stream alternate between
+// two sets of counters (histogram and cursors); the grid clears the set of
+// the previous frame, whose planning is complete, for the next one.
 __global__ __launch_bounds__(256) void plan_cost_kernel(RenderArgsDev a) {
   __shared__ unsigned h[kXcdGroups * kBuckets];
   const int tid = threadIdx.x;
+  for (int i = blockIdx.x * 256 + tid; i < 2 * kPlanHistWords; i += gridDim.x * 256)
+    a.tile_clear[i] = 0u;
   for (int i = tid; i < kXcdGroups * kBuckets; i += 256) h[i] = 0u;
   __syncthreads();
-  const int t = blockIdx.x * 256 + tid;
-  if (t < a.ntiles) {
-    const int c = supertile_cost(a, t);
+  const int t = blockIdx.x * 64 + (tid >> 2);
+  const int r = tid & 3;
+  int c = t < a.ntiles ? supertile_cost_part(a, t, r) : 0;
+  c = max(c, __shfl_xor(c, 1));
+  c = max(c, __shfl_xor(c, 2));
+  if (t < a.ntiles && r == 0) {
     a.tile_cost[t] = c;
     atomicAdd(&h[xcd_group(t, a.nsx, a.region) * kBuckets + cost_rank(c)], 1u);
   }
@@ -1869,6 +1880,71 @@ __global__ __launch_bounds__(256) void plan_scatter_kernel(const int* cost, int 
     if (cnt[i] != 0u) off[i] = atomicAdd(&base[i], cnt[i]);
   __syncthreads();
   if (t < n) order[(int)(off[key] + local) * G + g] = t;
+}
+
+// Single frame: the launch order above with G = kXcdGroups, where every
+// workgroup does the scan for itself.  A workgroup forms the
+// exclusive prefix sums of each group's bucket histogram in LDS (thread i
+// holds 16 consecutive buckets, 32 threads a group), and reserves the
+// ranges of its own tiles through the bucket cursors, which start at zero.
+// The grid also marks the launch slots past each group's tiles empty (-1).
+__global__ __launch_bounds__(256) void plan_place_kernel(const int* cost, int n, int nsx,
+                                                         int region, const unsigned* hist,
+                                                         unsigned* cursor, int* order,
+                                                         int nslots) {
+  constexpr int kWords = kXcdGroups * kBuckets;
+  constexpr int kPer = kWords / 256;       // buckets per thread
+  constexpr int kSeg = kBuckets / kPer;    // threads per group
+  static_assert(kWords % (4 * 256) == 0 && kSeg <= 64 && (kSeg & (kSeg - 1)) == 0,
+                "bucket layout of the per-workgroup scan");
+  __shared__ unsigned pre[kWords];
+  __shared__ unsigned cnt[kWords];
+  __shared__ unsigned total[kXcdGroups];
+  const int tid = threadIdx.x;
+  unsigned v[kPer];
+  unsigned sum = 0u;
+#pragma unroll
+  for (int q = 0; q < kPer; q += 4) {
+    const uint4 w = *reinterpret_cast<const uint4*>(hist + tid * kPer + q);
+    v[q] = w.x;
+    v[q + 1] = w.y;
+    v[q + 2] = w.z;
+    v[q + 3] = w.w;
+  }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) sum += v[q];
+  // inclusive scan of the thread sums within each segment of kSeg lanes
+  const int seg_lane = __lane_id() & (kSeg - 1);
+  unsigned incl = sum;
+#pragma unroll
+  for (int d = 1; d < kSeg; d <<= 1) {
+    const unsigned o = __shfl_up(incl, d, kSeg);
+    if (seg_lane >= d) incl += o;
+  }
+  unsigned run = incl - sum;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    pre[tid * kPer + q] = run;
+    cnt[tid * kPer + q] = 0u;
+    run += v[q];
+  }
+  if (seg_lane == kSeg - 1) total[tid / kSeg] = run;
+  __syncthreads();
+  for (int i = blockIdx.x * 256 + tid; i < nslots; i += gridDim.x * 256)
+    if ((unsigned)(i / kXcdGroups) >= total[i % kXcdGroups]) order[i] = -1;
+  const int t = blockIdx.x * 256 + tid;
+  int key = 0, g = 0;
+  unsigned local = 0u;
+  if (t < n) {
+    g = xcd_group(t, nsx, region);
+    key = g * kBuckets + cost_rank(cost[t]);
+    local = atomicAdd(&cnt[key], 1u);
+  }
+  __syncthreads();
+  for (int i = tid; i < kWords; i += 256)
+    if (cnt[i] != 0u) pre[i] += atomicAdd(&cursor[i], cnt[i]);
+  __syncthreads();
+  if (t < n) order[(int)(pre[key] + local) * kXcdGroups + g] = t;
 }
 
 // Batch class: clear the bucket counters and every request's sample
@@ -2104,14 +2180,12 @@ hipError_t mark(hipEvent_t ev, hipStream_t st) {
 
 template <int P, int STORE, bool SHADE, bool FAST, bool EQ, bool CURV = false>
 hipError_t launch_brick(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
+  // the frame's counters are zero (plan_init_kernel, then the cost pass of
+  // the frame before the previous one)
   const unsigned blocks = (unsigned)((a.ntiles + 255) / 256);
-  const int nhist = kXcdGroups * kBuckets;
-  const unsigned zblocks = (unsigned)((max(a.nslots, nhist) + 255) / 256);
-  plan_zero_kernel<<<zblocks, 256, 0, st>>>(a.tile_hist, nhist, a.tile_order, a.nslots);
-  plan_cost_kernel<<<blocks, 256, 0, st>>>(a);
-  plan_scan_kernel<<<kXcdGroups, kBuckets, 0, st>>>(a.tile_hist);
-  plan_scatter_kernel<kXcdGroups>
-      <<<blocks, 256, 0, st>>>(a.tile_cost, a.ntiles, a.nsx, a.region, a.tile_hist, a.tile_order);
+  plan_cost_kernel<<<(unsigned)((a.ntiles + 63) / 64), 256, 0, st>>>(a);
+  plan_place_kernel<<<blocks, 256, 0, st>>>(a.tile_cost, a.ntiles, a.nsx, a.region, a.tile_hist,
+                                            a.tile_hist + kPlanHistWords, a.tile_order, a.nslots);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = mark(ev.begin, st);
   if (e != hipSuccess) return e;

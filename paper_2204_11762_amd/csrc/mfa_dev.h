@@ -25,8 +25,11 @@ constexpr int kTileH = 64 / kLanesPerRay / kTileW;
 // has work on small frames too.
 constexpr int kXcdGroups = 8;
 constexpr int kMaxRegion = 4;
-// Counters of the tile sort (kXcdGroups x 512 buckets).
+// Counters of the tile sort (kXcdGroups x 512 buckets).  A frame uses two
+// such arrays, the bucket histogram and the bucket cursors; the planning
+// scratch of a stream holds two sets, for alternate frames (kPlanWords).
 constexpr int kPlanHistWords = kXcdGroups * 512;
+constexpr int kPlanWords = 4 * kPlanHistWords;
 
 // Waves per SIMD that the brick ray caster of kernel degree P is compiled
 // for (four workgroups of four waves per CU, or three for the variants
@@ -144,7 +147,9 @@ struct RenderArgsDev {
   int32_t tile_h;
   int32_t* tile_cost;   // ntiles work estimates (scratch)
   int32_t* tile_order;  // nslots super-tile indices, -1 for empty slots (scratch)
-  unsigned* tile_hist;  // kPlanHistWords bucket counters of the tile sort (scratch)
+  unsigned* tile_hist;  // this frame's counters of the tile sort (scratch): histogram,
+                        // then cursors (2 x kPlanHistWords, zero before the frame)
+  unsigned* tile_clear; // the previous frame's counters, cleared by this frame's planning
 };
 
 struct EvalArgsDev {
@@ -214,6 +219,9 @@ hipError_t launch_render(const RenderArgsDev& a, hipStream_t stream, const Kerne
 hipError_t launch_render_batch(const BatchDev& b, const BatchKey& k, hipStream_t stream);
 hipError_t launch_eval(const EvalArgsDev& a, hipStream_t stream);
 hipError_t launch_eval_order(const EvalOrderDev& o, hipStream_t stream);
+// Initial state of a single frame's planning scratch: kPlanWords zero
+// counters at hist.
+hipError_t launch_plan_init(unsigned* hist, hipStream_t stream);
 // FP32 FMA micro-loop: blocks x 256 threads, iters x 8 FMA each
 hipError_t launch_fma_peak(float* out, int blocks, int iters, hipStream_t stream);
 

@@ -206,6 +206,47 @@ def test_concurrent_streams(mfa):
         b.mfa_model_free(ctx, h)
 
 
+def test_frame_sequence_one_stream(mfa):
+    """Frames of changing size enqueued back to back on one fresh stream
+    (the planning scratch grows between them, and consecutive frames plan
+    with alternating counter sets) equal the same frames rendered each as
+    the first frame of a fresh context, bit for bit, and write every pixel."""
+    import torch
+    b, ctx = mfa
+    wk = wl.c2()
+    sizes = (96, 96, 300, 64, 300, 300, 130, 96, 417)
+    views = []
+    for k, w in enumerate(sizes):
+        v = copy.copy(wk)
+        v.camera = wl.orbit_camera(w, w - 7 * (k % 3), 40.0 * k, 15.0)
+        views.append(v)
+    ref = []
+    for v in views:
+        c2 = b.mfa_create(0)
+        try:
+            h2 = b.mfa_model_upload(c2, wk.model)
+            ref.append(gpu_render(b, c2, h2, v))
+        finally:
+            b.mfa_destroy(c2)
+        assert (ref[-1][0] >= 0.0).all()
+    h = b.mfa_model_upload(ctx, wk.model)
+    try:
+        s = torch.cuda.Stream()
+        outs = [torch.full((v.camera.height, v.camera.width, 4), -1.0, dtype=torch.float32,
+                           device="cuda") for v in views]
+        cnts = [torch.zeros((1,), dtype=torch.int64, device="cuda") for _ in views]
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            for i, v in enumerate(views):
+                b.mfa_render(ctx, h, v.camera, v.tf, v.params, outs[i], cnts[i], stream=s)
+        s.synchronize()
+        for i in range(len(views)):
+            assert np.array_equal(outs[i].cpu().numpy().astype(np.float64), ref[i][0]), f"frame {i}"
+            assert int(cnts[i].item()) == ref[i][1], f"frame {i}"
+    finally:
+        b.mfa_model_free(ctx, h)
+
+
 def test_kernel_timing(mfa):
     """The optional kernel events time every render while enabled, leave the
     image unchanged, and record nothing once disabled."""
