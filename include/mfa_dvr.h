@@ -183,9 +183,12 @@ mfa_status mfa_model_bytes(mfa_ctx* ctx, int64_t model, int64_t* bytes_out);
  * that misses the box yields (0,0,0,0).  If samples_dev is not null it
  * receives (overwritten, one int64) the number of samples composited over
  * the whole image, early-terminated rays counting up to and including
- * their last sample.  Asynchronous on `stream`.  Errors: MFA_ERR_INVALID
- * (camera, TF or parameters, null rgba_dev), MFA_ERR_HANDLE,
- * MFA_ERR_DEVICE. */
+ * their last sample.  Asynchronous on `stream`.  Not for HIP graph
+ * capture: a call may allocate and copy (planning space, a new transfer
+ * function), and consecutive frames on a stream share planning state that a
+ * replayed graph would not advance; capture batches (mfa_batch_render)
+ * instead.  Errors: MFA_ERR_INVALID (camera, TF or parameters, null
+ * rgba_dev), MFA_ERR_HANDLE, MFA_ERR_DEVICE. */
 mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* camera, const mfa_tf* tf,
                       const mfa_render_params* params, float* rgba_dev, int64_t* samples_dev,
                       void* stream);

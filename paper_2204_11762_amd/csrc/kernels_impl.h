@@ -1944,7 +1944,10 @@ __global__ __launch_bounds__(256) void plan_place_kernel(const int* cost, int n,
   for (int i = tid; i < kWords; i += 256)
     if (cnt[i] != 0u) pre[i] += atomicAdd(&cursor[i], cnt[i]);
   __syncthreads();
-  if (t < n) order[(int)(pre[key] + local) * kXcdGroups + g] = t;
+  // with counters that started at zero every position is below nslots; the
+  // test keeps counters left over from an interrupted frame in bounds
+  const unsigned pos = (pre[key] + local) * kXcdGroups + g;
+  if (t < n && pos < (unsigned)nslots) order[pos] = t;
 }
 
 // Batch class: clear the bucket counters and every request's sample
