@@ -157,6 +157,13 @@ def cpu_baseline(wk, n_rays: int, seed: int, workers: int):
     return {"pix": pix, "rgba": rgba, "samples": samples, "wall": wall}
 
 
+FRAME_NAMES = {
+    "c1": "16^3 p2 random control points, 128^2 orthographic, step 1/256 (every ray)",
+    "c2": "64^3 p3 least-squares fit, 512^2 perspective, step 1/512 (every ray that meets "
+          "the volume)",
+}
+
+
 def host_cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -320,10 +327,12 @@ def batch_leg(b, ctx, steps: int, warmup: int, log):
             b.mfa_model_free(ctx, h)
 
 
-def serve_leg(b, ctx, log, rate: float, duration: float):
+def serve_leg(b, ctx, log, rate: float, duration: float, max_bytes: int):
     """The serving workload: requests submitted to the library's render
     server at their Poisson arrival times; throughput over the whole run and
-    per-request latency (submission to completion)."""
+    per-request latency (submission to completion).  The server admits
+    requests within a device-byte budget (max_bytes); the requests it held
+    back for it while a launch slot was free are counted."""
     import torch
     models, reqs, arrivals = wl.serve_config(rate=rate, duration_s=duration)
     p_of = [int(max(spec.degree)) for spec, _ in models]
@@ -333,7 +342,7 @@ def serve_leg(b, ctx, log, rate: float, duration: float):
                             device="cuda") for r in reqs]
         cnt = torch.zeros((len(reqs),), dtype=torch.int64, device="cuda")
         torch.cuda.synchronize()
-        server = b.mfa_server_create(ctx, streams=2, max_batch=64)
+        server = b.mfa_server_create(ctx, streams=2, max_batch=64, max_bytes=max_bytes)
         infos = []
         try:
             # a few requests first, so that the slots' buffers are sized
@@ -360,9 +369,11 @@ def serve_leg(b, ctx, log, rate: float, duration: float):
         span = (done.max() - sub.min()) * 1e-9
         lat = (done - sub) * 1e-6
         bsz = np.array([inf.batch_size for inf in infos])
+        deferred = int(sum(inf.deferred for inf in infos))
         log(f"serve: {len(reqs)} requests in {span:.2f} s, {samples} samples, "
             f"p50 {np.percentile(lat, 50):.2f} ms, p99 {np.percentile(lat, 99):.2f} ms, "
-            f"mean batch {bsz.mean():.1f}")
+            f"mean batch {bsz.mean():.1f}, {deferred} held back by the "
+            f"{max_bytes / 2**20:.0f} MiB budget")
         return {"workload": f"Poisson {rate:g} req/s for {duration:g} s over 16 resident models "
                             "(p 2-4, 32^3-256^3, FP32/BF16, uniform/Beta(2,5) knots); images "
                             "128^2-1920x1080, 128-1024 samples per unit length, per-request table",
@@ -372,7 +383,8 @@ def serve_leg(b, ctx, log, rate: float, duration: float):
                 "latency_p50_ms": float(np.percentile(lat, 50)),
                 "latency_p99_ms": float(np.percentile(lat, 99)),
                 "latency_max_ms": float(lat.max()), "mean_batch": float(bsz.mean()),
-                "server": {"streams": 2, "max_batch": 64}}
+                "deferred_by_budget": deferred,
+                "server": {"streams": 2, "max_batch": 64, "max_bytes": max_bytes}}
     finally:
         for h in handles:
             b.mfa_model_free(ctx, h)
@@ -556,7 +568,12 @@ def main():
     ap.add_argument("--no-nominal", action="store_true",
                     help="skip the frames without early termination (so that every render "
                          "launch of a profiled run is a timed-type frame)")
-    ap.add_argument("--cpu-workers", type=int, default=0, help="0 = host cores, at most 16")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle processes: 0 = the host CPUs this process may run on, at most "
+                         "16 (the CPU share of one GPU on the measurement hosts)")
+    ap.add_argument("--no-cpu-frames", action="store_true",
+                    help="skip the oracle's full-frame timings of the small (128^2) and "
+                         "production (512^2) frames")
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (a plain copy "
@@ -598,6 +615,15 @@ def main():
             f"with {cores} processes")
         base = cpu_baseline(wk, args.cpu_rays, args.seed, cores)
         log(f"CPU oracle: {base['samples']} samples in {base['wall']:.2f} s")
+        if not args.no_cpu_frames:
+            frames = {}
+            for name, fw in (("c1", wl.c1()), ("c2", wl.c2())):
+                r = cpu_baseline(fw, -1, args.seed, cores)
+                frames[name] = {"workload": FRAME_NAMES[name], "rays": int(len(r["pix"])),
+                                "samples": r["samples"], "wall_s": r["wall"],
+                                "samples_per_s": r["samples"] / r["wall"]}
+                log(f"CPU oracle, {name} frame: {r['samples']} samples in {r['wall']:.2f} s")
+            base["frames"] = frames
 
     import torch
 
@@ -648,9 +674,14 @@ def main():
             batch = batch_leg(b, ctx, args.batch_steps, 2, log)
         serve = saturated = None
         if args.serve_seconds > 0:
-            serve = serve_leg(b, ctx, log, args.serve_rate, args.serve_seconds)
-            # the same request mix offered 20 times faster: the server's capacity
-            saturated = serve_leg(b, ctx, log, 20 * args.serve_rate, args.serve_seconds / 8)
+            # a budget of 48 MiB in flight: one full-HD request (33 MB of
+            # image) leaves room for smaller ones but not for a second one
+            serve = serve_leg(b, ctx, log, args.serve_rate, args.serve_seconds, 48 << 20)
+            # the same request mix offered 20 times faster: the server's
+            # capacity, with a budget that still binds (a 64-request batch of
+            # this mix holds about 1.1 GB of images)
+            saturated = serve_leg(b, ctx, log, 20 * args.serve_rate, args.serve_seconds / 8,
+                                  512 << 20)
     finally:
         b.mfa_destroy(ctx)
     if args.store not in legs:
@@ -733,12 +764,15 @@ def main():
     if base is not None:
         line["cpu_baseline"] = {"value": base["samples"] / base["wall"], "unit": "samples/s",
                                 "cores": cores,
-                                "per_core": base["samples"] / base["wall"] / cores,
+                                "processes": cores,
+                                "host_cpus_visible": len(os.sched_getaffinity(0)),
+                                "per_process": base["samples"] / base["wall"] / cores,
                                 "kind": "oracle",
                                 "sample": f"{len(base['pix'])} rays of the same frame that meet the "
                                           f"volume, {base['samples']} samples, "
                                           f"{base['wall']:.1f} s wall",
-                                "host_cpu": host_cpu_model()}
+                                "host_cpu": host_cpu_model(),
+                                "full_frames": base.get("frames")}
     print(json.dumps(line), flush=True)
 
 

@@ -325,6 +325,8 @@ typedef struct mfa_request_info {
   int64_t submit_ns;  /* host steady-clock times: submission, */
   int64_t launch_ns;  /* admission into a launched batch, */
   int64_t done_ns;    /* completion seen by the worker */
+  int32_t deferred;   /* 1 if max_bytes held it back while a launch slot was free */
+  int32_t reserved;
 } mfa_request_info;
 
 typedef struct mfa_server mfa_server;

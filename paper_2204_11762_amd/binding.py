@@ -97,7 +97,8 @@ class ServerConfig(C.Structure):
 
 class RequestInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("batch_size", C.c_int32), ("submit_ns", C.c_int64),
-                ("launch_ns", C.c_int64), ("done_ns", C.c_int64)]
+                ("launch_ns", C.c_int64), ("done_ns", C.c_int64), ("deferred", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 def _load():

@@ -1570,6 +1570,7 @@ struct Pending {
   int64_t* samples = nullptr;
   int64_t footprint = 0;       // output bytes plus an estimate of its share of a batch block
   int64_t submit_ns = 0;
+  bool deferred = false;       // held back by the byte budget while a slot was free
 };
 
 struct TicketState {
@@ -1709,8 +1710,10 @@ void server_loop(mfa_server* sv) {
       while (!sv->queue.empty() && int32_t(free_slot->reqs.size()) < sv->cfg.max_batch) {
         Pending& p = sv->queue.front();
         if (budget > 0 && sv->in_flight_bytes + free_slot->bytes + p.footprint > budget &&
-            !(free_slot->reqs.empty() && sv->in_flight_bytes == 0))
+            !(free_slot->reqs.empty() && sv->in_flight_bytes == 0)) {
+          p.deferred = true;
           break;
+        }
         free_slot->bytes += p.footprint;
         free_slot->reqs.push_back(std::move(p));
         sv->queue.pop_front();
@@ -1724,6 +1727,7 @@ void server_loop(mfa_server* sv) {
           TicketState& ts = sv->tickets[r.ticket];
           ts.info.launch_ns = t;
           ts.info.batch_size = nb;
+          ts.info.deferred = r.deferred ? 1 : 0;
         }
         lk.unlock();
         const mfa_status st = slot_launch(*free_slot);

@@ -4,6 +4,7 @@ compare with the FP64 oracle."""
 from __future__ import annotations
 
 import copy
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -68,6 +69,26 @@ class ImageReport:
     samples_slack: int
 
 
+# Pixel sets at least this large are rendered by the oracle in a pool of
+# processes (spawned, so that no child inherits the parent's GPU state).
+POOL_MIN_PIXELS = 16384
+_POOL_ARGS = {}
+
+
+def _pool_init(args):
+    _POOL_ARGS["args"] = args
+
+
+def _pool_job(pix):
+    M, cam, tf, prm, o_max, ctf = _POOL_ARGS["args"]
+    r = orc.render_pixels(M, cam, tf, prm, pix, o_max=o_max, curvature=ctf)
+    return r.rgba, r.samples, r.n_nominal, r.near_threshold
+
+
+def pool_workers() -> int:
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
 def oracle_on_pixels(wk, pix, o_max=None, model=None, ert=None, curvature=None):
     M, cam, tf, prm = oracle_workload(wk)
     if model is not None:
@@ -77,7 +98,19 @@ def oracle_on_pixels(wk, pix, o_max=None, model=None, ert=None, curvature=None):
         prm.ert_alpha = ert
     ctf = None if curvature is None else orc.CurvatureTF(
         np.asarray(curvature.table, dtype=np.float32), curvature.k_lo, curvature.k_hi)
-    return orc.render_pixels(M, cam, tf, prm, pix, o_max=o_max, curvature=ctf)
+    pix = np.asarray(pix, dtype=np.int64)
+    workers = pool_workers()
+    if len(pix) < POOL_MIN_PIXELS or workers == 1:
+        return orc.render_pixels(M, cam, tf, prm, pix, o_max=o_max, curvature=ctf)
+    import multiprocessing as mp
+    chunks = np.array_split(pix, 4 * workers)
+    with mp.get_context("spawn").Pool(workers, initializer=_pool_init,
+                                      initargs=((M, cam, tf, prm, o_max, ctf),)) as pool:
+        parts = pool.map(_pool_job, chunks)
+    return orc.RenderResult(np.concatenate([q[0] for q in parts]),
+                            np.concatenate([q[1] for q in parts]),
+                            np.concatenate([q[2] for q in parts]),
+                            np.concatenate([q[3] for q in parts]))
 
 
 def compare_image(gpu_img, gpu_count, wk, pix, tau, px_tol, model=None, count_exact=True,

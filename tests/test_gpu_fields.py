@@ -4,8 +4,8 @@ MFAs least-squares fitted to the Gaussian beam (Eq. 1) and Marschner-Lobb
 of the analytic field itself (value and gradient exact), by MSE, PSNR and
 SSIM on 8-bit images.
 
-Checked: the GPU images equal the oracle's images of the same MFA to 8-bit
-rounding (so the study measures the MFA, not the renderer), and the quality
+Checked: the GPU images equal the oracle's images of the same MFA to the
+FP32 image bar (so the study measures the MFA, not the renderer), and the quality
 ordering the paper reports holds: degree > 1 beats degree 1, and more
 control points beat fewer."""
 
@@ -14,7 +14,7 @@ from __future__ import annotations
 import numpy as np
 import pytest
 
-from gpu_helpers import gpu_render
+from gpu_helpers import FP32_RMSE, compare_image, gpu_render
 from helpers import oracle_camera, oracle_model, oracle_params, oracle_tf
 from image_metrics import psnr, ssim, to_8bit
 from oracle import raycast as orc
@@ -23,6 +23,8 @@ from paper_2204_11762_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 W = 96
+TAU32 = 2e-5      # band around the termination threshold for FP32 opacity
+PX32 = 2e-4       # per-pixel bound outside that band
 
 
 def _camera():
@@ -61,18 +63,18 @@ def _study(mfa, field, N, configs, tf, prm):
             truth = _ground_truth(field, spec, wk)
         h = b.mfa_model_upload(ctx, spec)
         try:
-            img, _ = gpu_render(b, ctx, h, wk)
+            img, cnt = gpu_render(b, ctx, h, wk)
         finally:
             b.mfa_model_free(ctx, h)
+        # GPU vs oracle on the same MFA, on the float images: the FP32 bar
+        # (pixels whose termination is ambiguous in FP32 lie between the
+        # oracle renders with the threshold moved by the band)
+        rep = compare_image(img, cnt, wk, np.arange(W * W), TAU32, PX32)
+        print(f"\n  {field.__name__} {n}^3 p{p}: GPU vs oracle rmse {rep.rmse:.3e} "
+              f"max {rep.max_abs:.3e} ambiguous {rep.n_ambiguous}")
+        assert rep.rmse <= FP32_RMSE and rep.n_bad == 0
+        assert abs(rep.samples_gpu - rep.samples_ref) <= rep.samples_slack
         gpu8 = to_8bit(img)
-        M = oracle_model(spec)
-        ref = orc.render_pixels(M, oracle_camera(wk.camera), oracle_tf(tf), oracle_params(prm),
-                                np.arange(W * W))
-        ref8 = to_8bit(ref.rgba.reshape(W, W, 4))
-        # GPU vs oracle on the same MFA: 8-bit rounding, and a pixel whose
-        # termination is ambiguous in FP32 differs by one sample's colour
-        diff = np.abs(gpu8.astype(int) - ref8.astype(int))
-        assert diff.max() <= 3 and diff.mean() < 0.05
         rows.append((n, p, psnr(truth, gpu8), ssim(truth, gpu8)))
     print()
     for n, p, ps, ss in rows:

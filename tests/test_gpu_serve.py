@@ -150,3 +150,92 @@ def test_server_errors(mfa):
     finally:
         for h in handles:
             b.mfa_model_free(ctx, h)
+
+
+# Requests shaped like the serving workload: (model of the serving set, image
+# size, samples per unit length).  Models 9, 10, 11 and 15 are the 256^3 ones
+# (p 2 FP32 Beta, p 3 BF16 uniform, p 4 BF16 Beta, p 2 BF16 Beta).
+SERVE_MIX = [(10, (1920, 1080), 1024), (11, (1920, 1080), 1024), (9, (1280, 720), 512),
+             (15, (1024, 768), 256), (7, (512, 512), 1024), (4, (128, 128), 128),
+             (8, (256, 256), 512), (1, (1920, 1080), 128)]
+
+
+def test_server_serving_mix_against_oracle(mfa):
+    """Requests of the serving workload's shape (256^3 models in FP32 and
+    BF16, uniform and Beta knots, degrees 2-4, images up to 1920x1080, up to
+    1024 samples per unit length) served under a byte budget that holds the
+    second full-HD request back while the first is in flight.  Each served
+    image equals its solo render bit for bit, and sampled pixels match the
+    FP64 oracle: FP32 models at the FP32 bar; BF16 models at the FP32 bar
+    against the de-quantised model and at the BF16 bar against FP64."""
+    import torch
+
+    from gpu_helpers import BF16_RMSE, FP32_RMSE, compare_image
+    from helpers import oracle_model, oracle_workload
+    from oracle import quant
+    from oracle import raycast as orc
+    b, ctx = mfa
+    models, _, _ = wl.serve_config()
+    rng = np.random.default_rng(81)
+    reqs = []
+    for mi, (W, H), N in SERVE_MIX:
+        P = models[mi][0].ctrl
+        tf = wl.pwl_tf(int(rng.integers(1 << 30)), float(P.min()), float(P.max()))
+        reqs.append(wl.BatchRequest(mi, wl.random_orbit_camera(rng, W, H), tf,
+                                    wl.ParamSpec(step=1.0 / N)))
+    used = sorted({r.model for r in reqs})
+    handles = {mi: b.mfa_model_upload(ctx, *models[mi]) for mi in used}
+    try:
+        refs = [gpu_render(b, ctx, handles[r.model],
+                           wl.Workload("serve", models[r.model][0], r.camera, r.tf, r.params))
+                for r in reqs]
+        outs = [torch.full((r.camera.height, r.camera.width, 4), -1.0, dtype=torch.float32,
+                           device="cuda") for r in reqs]
+        cnts = [torch.full((1,), -7, dtype=torch.int64, device="cuda") for _ in reqs]
+        torch.cuda.synchronize()
+        fhd = 1920 * 1080 * 16
+        server = b.mfa_server_create(ctx, streams=2, max_batch=4, max_bytes=fhd * 3 // 2)
+        try:
+            tickets = [b.mfa_server_submit(server, handles[r.model], r.camera, r.tf, r.params,
+                                           outs[i], cnts[i]) for i, r in enumerate(reqs)]
+            infos = [b.mfa_server_wait(server, t, -1) for t in tickets]
+        finally:
+            b.mfa_server_destroy(server)
+        torch.cuda.synchronize()
+        assert sum(inf.deferred for inf in infos) >= 1, "the byte budget never held a request"
+        for i, r in enumerate(reqs):
+            spec, store = models[r.model]
+            got = outs[i].cpu().numpy().astype(np.float64)
+            cnt = int(cnts[i].item())
+            assert np.array_equal(got, refs[i][0]), f"request {i}: served image differs"
+            assert cnt == refs[i][1], f"request {i}: count"
+            wk = wl.Workload("serve", spec, r.camera, r.tf, r.params)
+            M, cam, _, prm = oracle_workload(wk)
+            W, H = r.camera.width, r.camera.height
+            rr, cc = np.divmod(np.arange(W * H), W)
+            o, d = orc.camera_rays(cam, rr, cc)
+            t0, t1, hit = orc.slab(o, d, M.lo, M.hi)
+            nr = orc.sample_counts(t0, t1, hit, prm.step)
+            assert (got.reshape(-1, 4)[nr == 0] == 0).all()
+            prng = np.random.default_rng(90 + i)
+            hits, misses = np.nonzero(nr > 0)[0], np.nonzero(nr == 0)[0]
+            pix = np.sort(np.concatenate([
+                prng.choice(hits, min(150, len(hits)), replace=False),
+                prng.choice(misses, min(20, len(misses)), replace=False)]))
+            if store == 0:
+                rep = compare_image(got, cnt, wk, pix, 2e-5, 2e-4)
+                msg = f"fp32 rmse {rep.rmse:.2e}"
+                assert rep.rmse <= FP32_RMSE and rep.n_bad == 0, f"request {i}: {rep}"
+            else:
+                Mq = oracle_model(spec, ctrl=quant.dequant_bf16(spec.ctrl))
+                rep = compare_image(got, cnt, wk, pix, 2e-5, 2e-4, model=Mq)
+                assert rep.rmse <= FP32_RMSE and rep.n_bad == 0, f"request {i}: {rep}"
+                rep64 = compare_image(got, cnt, wk, pix, 3e-3, 5e-2)
+                assert rep64.rmse <= BF16_RMSE, f"request {i}: {rep64}"
+                msg = f"bf16 rmse {rep.rmse:.2e} (de-quantised), {rep64.rmse:.2e} (FP64)"
+            print(f"\n  request {i}: model {r.model} p{spec.degree[0]} {W}x{H} step 1/"
+                  f"{round(1 / r.params.step)}, batch {infos[i].batch_size}, deferred "
+                  f"{infos[i].deferred}: {msg}")
+    finally:
+        for h in handles.values():
+            b.mfa_model_free(ctx, h)

@@ -211,6 +211,85 @@ def test_linear_field_image_exact_table():
                                rtol=0, atol=1e-14)
 
 
+@pytest.mark.parametrize("light, diff, spec", [
+    # l = (0, 3, 4)/5 (given unnormalised): n.l = 0.8, r = 2(n.l)n - l =
+    # (0, -0.6, 0.8), r.v = 0.8
+    ((0.0, 3.0, 4.0), 0.8, 0.8 ** 10),
+    # the opposite light: two-sided diffuse |n.l| = 0.8, r = (0, 0.6, -0.8)
+    # points away from the eye, r.v = -0.8, no specular
+    ((0.0, -3.0, -4.0), 0.8, 0.0),
+    # tilted in x: l = (12, 0, 5)/13, n.l = 5/13, r = (-12, 0, 5)/13, r.v = 5/13
+    ((12.0, 0.0, 5.0), 5 / 13, (5 / 13) ** 10),
+])
+def test_linear_field_explicit_light(light, diff, spec):
+    """The explicit-light branch (headlight off): f = w reproduced exactly,
+    the c1 camera (v = +z, world gradient +z, so n = +z), and a light
+    direction given unnormalised.  Diffuse and specular terms follow from
+    the hand-normalised light, so every pixel is one closed-form sum; a
+    missing normalisation or a one-sided diffuse fails."""
+    n, p = 10, 3
+    U = wl.clamped_uniform_knots(n, p)
+    cz = ob.marsden_coeffs(p, U, 1)
+    ctrl = np.broadcast_to(cz[:, None, None], (n, n, n)).copy()
+    M = ob.Model((p, p, p), (U, U, U), ctrl, np.zeros(3), np.ones(3))
+    cam = _c1_camera(4, 4)
+    e = np.arange(5) / 4.0
+    tf = orc.TransferFunction(np.repeat(e[:, None], 4, 1).astype(np.float32), 0.0, 1.0)
+    prm = orc.RenderParams(step=1 / 32, headlight=False, light_dir=light)
+    res = orc.render(M, cam, tf, prm)
+    C = A = 0.0
+    for s in range(32):
+        w = 1 - (s + 0.5) / 32
+        cs = min(1.0, (0.1 + 0.7 * diff) * w + 0.2 * spec)
+        C += (1 - A) * w * cs
+        A += (1 - A) * w
+        if A > 0.99:
+            break
+    np.testing.assert_allclose(res.rgba.reshape(-1, 4), np.broadcast_to([C, C, C, A], (16, 4)),
+                               rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("light, diff, spec", [
+    # n = +x, v = +z (n.v = 0): r = 2 (n.l) n - l = (0.6, 0, 0.8), r.v = 0.8
+    ((3.0, 0.0, -4.0), 0.6, 0.8 ** 10),
+    # mirrored light: r = (-0.6, 0, -0.8) faces away from the eye
+    ((-3.0, 0.0, 4.0), 0.6, 0.0),
+])
+def test_linear_field_x_explicit_light(light, diff, spec):
+    """Headlight off with the normal across the view: f = u reproduced
+    exactly (Marsden along x), so n = +x while v = +z.  Every sample of the
+    ray through column c has f = (c + 1/2)/W (u is constant along a z ray),
+    so the pixel is the constant-colour closed form with opacity f and the
+    shaded colour min(1, (k_a + k_d |n.l|) f + k_s max(0, r.v)^k).  Here r.v
+    comes only from the reflected light (n.v = 0): a sign or term slip in
+    r = 2 (n.l) n - l shows."""
+    n, p = 10, 3
+    U = wl.clamped_uniform_knots(n, p)
+    cx = ob.marsden_coeffs(p, U, 1)
+    ctrl = np.broadcast_to(cx[None, None, :], (n, n, n)).copy()
+    M = ob.Model((p, p, p), (U, U, U), ctrl, np.zeros(3), np.ones(3))
+    W, H = 8, 3
+    cam = _c1_camera(W, H)
+    e = np.arange(5) / 4.0
+    tf = orc.TransferFunction(np.repeat(e[:, None], 4, 1).astype(np.float32), 0.0, 1.0)
+    prm = orc.RenderParams(step=1 / 32, headlight=False, light_dir=light)
+    res = orc.render(M, cam, tf, prm)
+    for c in range(W):
+        a = (c + 0.5) / W
+        cs = min(1.0, (0.1 + 0.7 * diff) * a + 0.2 * spec)
+        k = 0
+        A = 0.0
+        while k < 32:
+            k += 1
+            A = 1 - (1 - a) ** k
+            if A > 0.99:
+                break
+        want = np.array([cs * A, cs * A, cs * A, A])
+        np.testing.assert_allclose(res.rgba[:, c, :], np.broadcast_to(want, (H, 4)),
+                                   rtol=0, atol=1e-14)
+        assert (res.samples.reshape(H, W)[:, c] == k).all()
+
+
 def test_mirror_symmetry():
     """A model symmetric under x <-> y seen from a camera in the plane x = y
     with up = +z renders a left-right mirror-symmetric image."""
