@@ -193,6 +193,26 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* camera, con
                       const mfa_render_params* params, float* rgba_dev, int64_t* samples_dev,
                       void* stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Renders
+ * exactly as mfa_render (same kernels, bit-identical image and count) but
+ * calls no hipMalloc/hipFree and no allocating routine: the transfer
+ * function copy and the tile-planning space live in one fixed device array
+ * of 4 MiB per GPU, reserved by the library until the process ends (its
+ * address is looked up by mfa_create).  The transfer function is copied
+ * from host memory on `stream` before the call returns.  Limits: at most
+ * 507,904 launch slots (one per 8x8-pixel super-tile, grouped per XCD);
+ * images up to about 5600 x 5600 pixels fit, larger ones are refused with
+ * MFA_ERR_INVALID and a message naming the limit.  Every call on a GPU
+ * shares that GPU's array and each call clears what must start at zero:
+ * calls that overlap on one GPU (another stream, another context or host
+ * thread) race and may corrupt each other's images; order them on one
+ * stream.  No kernel timing is recorded.  Errors: as mfa_render, plus
+ * MFA_ERR_INVALID for an image beyond the limit. */
+mfa_status mfa_render_noalloc(mfa_ctx* ctx, int64_t model, const mfa_camera* camera,
+                              const mfa_tf* tf, const mfa_render_params* params, float* rgba_dev,
+                              int64_t* samples_dev, void* stream);
+
 /* Curvature transfer function: an m x m RGBA table (2 <= m <=
  * MFA_MAX_CURV_TF) over [k_lo, k_hi] x [k_lo, k_hi] of the two principal
  * curvatures k1 >= k2, entry (i2, i1) at rgba[4 (i2 m + i1)] (k1 along a

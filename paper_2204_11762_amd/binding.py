@@ -39,7 +39,7 @@ EXPORTED = ("mfa_create", "mfa_destroy", "mfa_set_memory_budget", "mfa_model_upl
             "mfa_measure_fma_peak", "mfa_autotune", "mfa_batch_create", "mfa_batch_render",
             "mfa_batch_free", "mfa_server_create", "mfa_server_submit", "mfa_server_wait",
             "mfa_server_destroy", "mfa_validate_model", "mfa_validate_render", "mfa_last_error",
-            "mfa_version")
+            "mfa_version", "mfa_render_noalloc")
 
 
 class MFAError(RuntimeError):
@@ -118,6 +118,8 @@ def _load():
         "mfa_model_bytes": (st, [vp, i64, C.POINTER(i64)]),
         "mfa_render": (st, [vp, i64, C.POINTER(Camera), C.POINTER(TF), C.POINTER(RenderParams),
                             vp, vp, vp]),
+        "mfa_render_noalloc": (st, [vp, i64, C.POINTER(Camera), C.POINTER(TF),
+                                    C.POINTER(RenderParams), vp, vp, vp]),
         "mfa_render_curvature": (st, [vp, i64, C.POINTER(Camera), C.POINTER(TF),
                                       C.POINTER(CurvatureTF), C.POINTER(RenderParams),
                                       vp, vp, vp]),
@@ -319,6 +321,20 @@ def mfa_render(ctx: int, model: int, camera, tf, params, rgba, samples=None, str
     t, keep = tf_struct(tf)
     _check(lib.mfa_render(ctx, int(model), C.byref(camera_struct(camera)), C.byref(t),
                           C.byref(params_struct(params)), out, sp, _stream_ptr(stream)))
+
+
+def mfa_render_noalloc(ctx: int, model: int, camera, tf, params, rgba, samples=None,
+                       stream=None) -> None:
+    """As mfa_render, without device allocation (the library's fixed
+    scratch array; overlapping calls on one GPU race)."""
+    import torch
+    out = _dev_tensor(rgba, torch.float32, (camera.height, camera.width, 4), "rgba")
+    sp = None
+    if samples is not None:
+        sp = _dev_tensor(samples, torch.int64, (1,), "samples")
+    t, keep = tf_struct(tf)
+    _check(lib.mfa_render_noalloc(ctx, int(model), C.byref(camera_struct(camera)), C.byref(t),
+                                  C.byref(params_struct(params)), out, sp, _stream_ptr(stream)))
 
 
 def curvature_struct(ctf, keep: _Keep | None = None) -> tuple:

@@ -474,6 +474,9 @@ struct mfa_ctx {
   int64_t budget = 0;
   int64_t used = 0;
   int64_t next_id = 1;
+  // device address of the allocation-free entry point's fixed array on
+  // this context's GPU (looked up when the context is created)
+  void* scratch = nullptr;
   std::unordered_map<int64_t, DeviceModel> models;
   std::unordered_map<int64_t, RenderBatch> batches;
   std::unordered_map<uint64_t, std::vector<TFEntry>> tfs;
@@ -681,8 +684,14 @@ mfa_status mfa_create(int32_t device, mfa_ctx** ctx_out) {
   if (device < 0 || device >= count) return fail(MFA_ERR_DEVICE, "no such HIP device");
   DeviceGuard g(device);
   if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
+  // set-up of the allocation-free entry point: its array's address on this
+  // device, with the device current
+  void* scratch = nullptr;
+  const hipError_t es = mfa::noalloc_scratch(device, &scratch);
+  if (es != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("scratch address", es));
   mfa_ctx* ctx = new mfa_ctx();
   ctx->device = device;
+  ctx->scratch = scratch;
   *ctx_out = ctx;
   return MFA_OK;
 }
@@ -1168,6 +1177,51 @@ mfa_status mfa_render(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, const 
     if (st != MFA_OK) return st;
   }
   return launch_timed(ctx, a, ps, stream);
+}
+
+mfa_status mfa_render_noalloc(mfa_ctx* ctx, int64_t model, const mfa_camera* cam,
+                              const mfa_tf* tf, const mfa_render_params* prm, float* rgba_dev,
+                              int64_t* samples_dev, void* stream) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  auto it = ctx->models.find(model);
+  if (it == ctx->models.end()) return fail(MFA_ERR_HANDLE, "unknown model handle");
+  const DeviceModel& dm = it->second;
+  mfa_status st = check_request(dm, cam, tf, prm, rgba_dev);
+  if (st != MFA_OK) return st;
+  if (ctx->scratch == nullptr) return fail(MFA_ERR_DEVICE, "no scratch address for this device");
+  if (size_t(tf->n) * sizeof(float4) > mfa::kNoAllocTfBytes)
+    return fail(MFA_ERR_INVALID, "transfer function larger than the fixed scratch holds");
+
+  char* base = static_cast<char*>(ctx->scratch);
+  float4* tf_dev = reinterpret_cast<float4*>(base + mfa::kNoAllocTfOff);
+  mfa::RenderArgsDev a;
+  build_render_args(dm, cam, tf, prm, rgba_dev, samples_dev, tf_dev, a);
+  if (int64_t(a.nslots) > mfa::kNoAllocMaxSlots)
+    return fail(MFA_ERR_INVALID, "image too large for the fixed scratch: " +
+                                     std::to_string(a.nslots) + " launch slots, at most " +
+                                     std::to_string(mfa::kNoAllocMaxSlots));
+
+  DeviceGuard g(ctx->device);
+  if (!g.ok()) return fail(MFA_ERR_DEVICE, "hipSetDevice failed");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(tf_dev, tf->rgba, size_t(tf->n) * sizeof(float4),
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("transfer function copy", e));
+  if (a.ntiles > 0) {
+    // the tile sort's counters start at zero: cleared by a fill kernel on
+    // every call, since the last call on this GPU left its counts there
+    unsigned* counters = reinterpret_cast<unsigned*>(base + mfa::kNoAllocCountersOff);
+    e = mfa::launch_plan_init(counters, s);
+    if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("scratch clear", e));
+    a.tile_cost = reinterpret_cast<int32_t*>(base + mfa::kNoAllocSlotsOff);
+    a.tile_order = a.tile_cost + mfa::kNoAllocMaxSlots;
+    a.tile_hist = counters;
+    a.tile_clear = counters + 2 * mfa::kPlanHistWords;
+  }
+  e = mfa::launch_render(a, s, mfa::KernelEvents{});
+  if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("render launch", e));
+  return MFA_OK;
 }
 
 mfa_status mfa_render_curvature(mfa_ctx* ctx, int64_t model, const mfa_camera* cam,

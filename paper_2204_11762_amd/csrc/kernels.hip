@@ -3,9 +3,39 @@
 // are instantiated in their own translation unit (kernels_f32.hip,
 // kernels_bf16.hip, kernels_f16.hip).
 
+#include <mutex>
+
 #include "kernels_impl.h"
 
 namespace mfa {
+
+// The allocation-free render entry point's device memory (layout in
+// mfa_dev.h).  Each GPU holds its own copy, at its own address, until the
+// process ends.  In host code this name is not a device address: kernels
+// get the address that noalloc_scratch() looks up.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kScratchDevices] = {};
+
+}  // namespace
+
+hipError_t noalloc_scratch(int device, void** out) {
+  if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_addr[device] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    g_scratch_addr[device] = p;
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
 
 extern template hipError_t render_for_store<0>(const RenderArgsDev&, hipStream_t,
                                                const KernelEvents&);

@@ -214,6 +214,25 @@ struct KernelEvents {
   hipEvent_t end = nullptr;
 };
 
+// Device memory of the allocation-free render entry point
+// (mfa_render_noalloc): a fixed array per GPU, laid out as the transfer
+// function (up to 4096 RGBA entries), the two counter sets of the tile
+// sort, then the cost and order arrays of at most kNoAllocMaxSlots launch
+// slots.  Every call on a GPU uses the same array.
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+constexpr size_t kNoAllocTfOff = 0;
+constexpr size_t kNoAllocTfBytes = size_t(4096) * 16;
+constexpr size_t kNoAllocCountersOff = kNoAllocTfOff + kNoAllocTfBytes;
+constexpr size_t kNoAllocSlotsOff = kNoAllocCountersOff + size_t(kPlanWords) * 4;
+constexpr int64_t kNoAllocMaxSlots =
+    int64_t((kNoAllocScratchBytes - kNoAllocSlotsOff) / 8) & ~int64_t(63);
+static_assert(kNoAllocSlotsOff % 256 == 0, "scratch parts stay 256-byte aligned");
+
+// Device address of that array on the current device (kernels.hip, where
+// the array is defined): looked up once per device through the runtime and
+// kept; the caller makes `device` current first.
+hipError_t noalloc_scratch(int device, void** out);
+
 // Kernel launchers (kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_render(const RenderArgsDev& a, hipStream_t stream, const KernelEvents& ev);
 hipError_t launch_render_batch(const BatchDev& b, const BatchKey& k, hipStream_t stream);
