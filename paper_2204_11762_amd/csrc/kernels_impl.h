@@ -428,11 +428,12 @@ __device__ __forceinline__ void cardinal_dd_window(int q, float t, float (&ddN)[
   }
 }
 
-// The cubic pieces scaled for the render kernel: 6 N and 2 dN/dt.  The
-// scaled derivatives are -s^2, t (3t - 4), 1 + t (2 - 3t) and t^2 with
-// s = 1 - t, so a sample's value and gradient come out of the contraction
-// multiplied by 6^3 and 2 * 6^2; the caller folds both factors into its
-// transfer-function and gradient constants.
+// The cubic pieces scaled for the render kernel: 6 N and 2 dN/dt.  With
+// s = 1 - t the pieces are s^3, 3t^3 - 6t^2 + 4, 3s^3 - 6s^2 + 4 (the
+// mirror image of the second) and t^3, and the scaled derivatives -s^2,
+// t (3t - 4), 1 + t (2 - 3t) and t^2, so a sample's value and gradient
+// come out of the contraction multiplied by 6^3 and 2 * 6^2; the caller
+// folds both factors into its transfer-function and gradient constants.
 constexpr float kCubicValueScale = 216.0f;
 constexpr float kCubicGradScale = 72.0f;
 
@@ -442,7 +443,7 @@ __device__ __forceinline__ void cardinal3_scaled(float t, float* N, float* dN) {
   const float s2 = s * s;
   N[0] = s2 * s;
   N[1] = fmaf(t2, fmaf(t, 3.0f, -6.0f), 4.0f);
-  N[2] = fmaf(t, fmaf(t, fmaf(t, -3.0f, 3.0f), 3.0f), 1.0f);
+  N[2] = fmaf(s2, fmaf(s, 3.0f, -6.0f), 4.0f);
   N[3] = t2 * t;
   dN[0] = -s2;
   dN[1] = t * fmaf(t, 3.0f, -4.0f);
@@ -819,7 +820,7 @@ template <class TfFetch>
 __device__ __forceinline__ void tf_sample(const RenderArgsDev& a, float tf_lo, float tf_scale,
                                           float f, TfFetch tf, float& sr, float& sg, float& sb,
                                           float& alpha) {
-  float x = (f - tf_lo) * tf_scale;
+  float x = fmaf(f, tf_scale, -tf_lo * tf_scale);
   x = fminf(fmaxf(x, 0.0f), 1.0f) * (float)(a.ntf - 1);
   const int i = min((int)x, a.ntf - 2);
   const float t = x - (float)i;
@@ -839,7 +840,8 @@ __device__ __forceinline__ void phong_sample(const RenderArgsDev& a, const float
   if (SHADE) {
     // n = g / |g|; diffuse |n.l|; specular max(0, r.v)^k
     const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
-    const float inv = (g2 >= 1e-12f) ? rsqrtf(g2) : 1e6f;
+    // 1 / max(|g|, 1e-6)
+    const float inv = rsqrtf(fmaxf(g2, 1e-12f));
     const float gl = g[0] * a.light[0] + g[1] * a.light[1] + g[2] * a.light[2];
     const float gv2 = g[0] * eye.v2x + g[1] * eye.v2y + g[2] * eye.v2z;
     const float ndl = gl * inv;
@@ -1457,6 +1459,29 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
       }
     }
 
+    // Interior rounds (uniform knots, every axis of degree P): when every
+    // cell of the round's box is interior on all three axes (cardinal
+    // pieces apply), so is every sample's cell, since the box holds the
+    // cells of all the round's samples with a margin far above the FP32
+    // stepping error.  The samples then skip the per-axis range test, and
+    // their brick offset is formed in FP32 from the cells' floor values
+    // (small integers, exact) on top of a per-lane base.
+    constexpr bool kInteriorPath = FAST && EQ && !CURV;
+    bool interior = false;
+    float basef = 0.0f;
+    const float pitch_yf = (float)pitch_y, pitch_zf = (float)pitch_z;
+    if constexpr (kInteriorPath) {
+      interior = fits;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int m = a.m.ax[k].n - P;
+        // the box's cells are blo .. blo + bext - P - 1
+        interior = interior && blo[k] >= P - 1 && blo[k] + bext[k] - P - 1 <= m - P;
+      }
+      basef = (float)(ca[0] - blo[0]) + pitch_yf * (float)(ca[1] - blo[1]) +
+              pitch_zf * (float)(ca[2] - blo[2]);
+    }
+
     // one lane's sample: basis weights and window start of each axis
     auto weights = [&](int s, int i, float (&N)[3][P + 1], float (&dN)[3][P + 1], int (&w)[3]) {
 #pragma unroll
@@ -1621,7 +1646,52 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
       return T >= t_stop;
     };
 
-    if (fits) {
+    // row (b, c) of a sample's window in the brick, e0 its first element
+    auto brick_row = [&](int e0) {
+      return [=](int b, int c, float (&row)[P + 1]) {
+        const float* r = brick + e0 + b * pitch_y + c * pitch_z;
+#pragma unroll
+        for (int q = 0; q <= P; ++q) row[q] = r[q];
+      };
+    };
+
+    bool interior_done = false;
+    if constexpr (kInteriorPath) {
+      if (interior) {
+        interior_done = true;
+        for (int j = s0, i = 0; j < s1; j += LPR, ++i) {
+          // A lane past the round's end evaluates a sample anyway (its
+          // window is clamped into the staged brick, so every value is
+          // finite) and adds it with alpha 0.
+          const bool valid = j + e < s1;
+          float sr, sg, sb, alpha, f, g[3];
+          float N[3][P + 1], dN[3][P + 1], fl[3];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const float t = fmaf((float)i, dt[k], ta[k]);
+            fl[k] = floorf(t);
+            const float tl = t - fl[k];
+            if constexpr (kScaled)
+              cardinal3_scaled(tl, N[k], dN[k]);
+            else
+              cardinal<P>(tl, N[k], dN[k]);
+          }
+          const float ef = fmaf(fl[2], pitch_zf, fmaf(fl[1], pitch_yf, fl[0] + basef));
+          const int e0 = min(max((int)ef, 0), emax);
+          contract<P, SHADE>(N, dN, brick_row(e0), f, g);
+          shade(f, g, sr, sg, sb, alpha);
+          alpha = valid ? alpha : 0.0f;
+          if (!composite(j, sr, sg, sb, alpha, valid)) {
+            alive = false;
+            break;
+          }
+        }
+      }
+    }
+
+    if (interior_done) {
+      // the round was rendered by the interior loop
+    } else if (fits) {
       for (int j = s0, i = 0; j < s1; j += LPR, ++i) {
         const int s = j + e;
         // a lane past the round's end adds alpha 0 and colour 0
@@ -1635,14 +1705,7 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
             int e0 = (w[0] - blo[0]) + __mul24(pitch_y, w[1] - blo[1]) +
                      __mul24(pitch_z, w[2] - blo[2]);
             e0 = min(max(e0, 0), emax);
-            contract_hess<P>(
-                N, dN, ddN,
-                [&](int b, int c, float (&row)[P + 1]) {
-                  const float* r = brick + e0 + b * pitch_y + c * pitch_z;
-#pragma unroll
-                  for (int q = 0; q <= P; ++q) row[q] = r[q];
-                },
-                f, g, h);
+            contract_hess<P>(N, dN, ddN, brick_row(e0), f, g, h);
             shade_curv(f, g, h, sr, sg, sb, alpha);
           } else {
             float f, g[3];
@@ -1653,14 +1716,7 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
             int e0 = (w[0] - blo[0]) + __mul24(pitch_y, w[1] - blo[1]) +
                      __mul24(pitch_z, w[2] - blo[2]);
             e0 = min(max(e0, 0), emax);
-            contract<P, SHADE>(
-                N, dN,
-                [&](int b, int c, float (&row)[P + 1]) {
-                  const float* r = brick + e0 + b * pitch_y + c * pitch_z;
-#pragma unroll
-                  for (int q = 0; q <= P; ++q) row[q] = r[q];
-                },
-                f, g);
+            contract<P, SHADE>(N, dN, brick_row(e0), f, g);
             shade(f, g, sr, sg, sb, alpha);
           }
         }
