@@ -390,16 +390,6 @@ def serve_leg(b, ctx, log, rate: float, duration: float, max_bytes: int):
             b.mfa_model_free(ctx, h)
 
 
-def morton_order(xyz: np.ndarray, bits: int = 10) -> np.ndarray:
-    """Permutation that sorts points in [0,1]^3 along a Morton (Z-order) curve."""
-    q = np.clip((xyz * (1 << bits)).astype(np.int64), 0, (1 << bits) - 1)
-    code = np.zeros(len(xyz), dtype=np.int64)
-    for bit in range(bits):
-        for k in range(3):
-            code |= ((q[:, k] >> bit) & 1) << (3 * bit + k)
-    return np.argsort(code, kind="stable")
-
-
 def eval_leg(b, ctx, wk, steps: int, log, n_points: int = 1 << 24):
     """Value + gradient queries at n_points points of the 256^3 model
     (uniformly random, then sorted along a Morton curve), against the HBM
@@ -410,7 +400,7 @@ def eval_leg(b, ctx, wk, steps: int, log, n_points: int = 1 << 24):
     import torch
     p = int(max(wk.model.degree))
     xyz = wl.uniform_points(np.random.default_rng(9), n_points)
-    orders = {"random": np.arange(n_points), "morton": morton_order(xyz)}
+    orders = {"random": np.arange(n_points), "morton": wl.morton_order(xyz)}
     out = {}
     for store, name in ((0, "fp32"), (1, "bf16")):
         h = b.mfa_model_upload(ctx, wk.model, store)

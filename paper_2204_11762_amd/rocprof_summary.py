@@ -15,7 +15,14 @@ Two subcommands:
              result is keyed by the SHA-256 of the kernel source that the
              profiled bench printed, so that a stale summary is recognised.
 
-Both write the full profiling command into the summary.
+``counters`` turns the ``<prefix>_counter_collection.csv`` files of one or
+             more ``rocprofv3 --pmc ...`` passes into the median value per
+             dispatch of each counter for the kernels matching a pattern,
+             and that value per unit of work (composited samples or
+             points per dispatch, given); counts of wave instructions
+             (``SQ_INSTS_*``) are also given per lane (times 64).
+
+Each writes the full profiling commands into the summary.
 """
 
 from __future__ import annotations
@@ -49,6 +56,42 @@ def short_name(name: str) -> str:
     return re.sub(r"\(.*\)$", "", name)
 
 
+def cmd_counters(args) -> None:
+    pat = re.compile(args.kernel)
+    vals: dict[str, list[float]] = {}
+    kernels: set[str] = set()
+    for path in args.csv:
+        with open(path, newline="") as fh:
+            for r in csv.DictReader(fh):
+                if not pat.search(r["Kernel_Name"]):
+                    continue
+                kernels.add(short_name(r["Kernel_Name"]))
+                vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit(f"no dispatch of a kernel matching {args.kernel!r}")
+    out = [f"# rocprofv3 counters: {args.title}", "#"]
+    out += [f"# command: {c}" for c in args.command]
+    out += ["#", f"# kernel(s): {', '.join(sorted(kernels))}",
+            f"# per {args.unit}: {args.per:.6g} {args.unit}s per dispatch", "#",
+            f"{'counter':28s} {'dispatches':>10} {'median':>14} {'min':>14} {'max':>14} "
+            f"{'per ' + args.unit:>14} {'x64 per ' + args.unit:>16}"]
+    for name in sorted(vals):
+        v = vals[name]
+        med = statistics.median(v)
+        lane = f"{64.0 * med / args.per:16.3f}" if name.startswith("SQ_INSTS_") else f"{'':16s}"
+        out.append(f"{name:28s} {len(v):10d} {med:14.6g} {min(v):14.6g} {max(v):14.6g} "
+                   f"{med / args.per:14.6g} {lane}")
+    if args.log:
+        out += ["", "# the profiled program's own report (same run):"]
+        for path in args.log:
+            with open(path) as fh:
+                out += ["#   " + ln.rstrip() for ln in fh if ln.startswith("[profile]")]
+    text = "\n".join(out) + "\n"
+    with open(args.out, "w") as fh:
+        fh.write(text)
+    sys.stdout.write(text)
+
+
 def cmd_kernels(args) -> None:
     rows = kernel_table(args.stats)
     out = [f"# rocprofv3 kernel statistics: {args.title}", "#", f"# command: {args.command}",
@@ -62,7 +105,7 @@ def cmd_kernels(args) -> None:
         out += ["", "# the profiled program's own report (same run):"]
         with open(args.bench_log) as fh:
             out += ["#   " + ln.rstrip() for ln in fh if ln.startswith("[bench] store=")
-                    or "kernel source sha256" in ln]
+                    or ln.startswith("[profile]") or "kernel source sha256" in ln]
     text = "\n".join(out) + "\n"
     with open(args.out, "w") as fh:
         fh.write(text)
@@ -160,8 +203,20 @@ def main(argv=None) -> None:
     t.add_argument("--write-command", required=True)
     t.add_argument("--copy-mib", type=int, required=True)
     t.add_argument("--out", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("csv", nargs="+", help="counter_collection.csv of each pass")
+    c.add_argument("--kernel", default=r"render_brick_kernel<",
+                   help="pattern of the kernel names summarised")
+    c.add_argument("--per", type=float, required=True,
+                   help="units of work per dispatch (e.g. composited samples)")
+    c.add_argument("--unit", default="sample")
+    c.add_argument("--title", required=True)
+    c.add_argument("--command", action="append", required=True,
+                   help="profiling command of a pass (repeat per pass)")
+    c.add_argument("--log", action="append", help="output of a profiled program")
+    c.add_argument("--out", required=True)
     args = ap.parse_args(argv)
-    (cmd_kernels if args.cmd == "kernels" else cmd_traffic)(args)
+    {"kernels": cmd_kernels, "traffic": cmd_traffic, "counters": cmd_counters}[args.cmd](args)
 
 
 if __name__ == "__main__":

@@ -515,3 +515,13 @@ def uniform_points(rng: np.random.Generator, m: int, lo=(0.0, 0.0, 0.0),
     lo = np.asarray(lo, dtype=np.float64)
     hi = np.asarray(hi, dtype=np.float64)
     return lo + rng.random((m, 3)) * (hi - lo)
+
+
+def morton_order(xyz: np.ndarray, bits: int = 10) -> np.ndarray:
+    """Permutation that sorts points in [0,1]^3 along a Morton (Z-order) curve."""
+    q = np.clip((xyz * (1 << bits)).astype(np.int64), 0, (1 << bits) - 1)
+    code = np.zeros(len(xyz), dtype=np.int64)
+    for bit in range(bits):
+        for k in range(3):
+            code |= ((q[:, k] >> bit) & 1) << (3 * bit + k)
+    return np.argsort(code, kind="stable")
