@@ -438,16 +438,21 @@ constexpr float kCubicValueScale = 216.0f;
 constexpr float kCubicGradScale = 72.0f;
 
 __device__ __forceinline__ void cardinal3_scaled(float t, float* N, float* dN) {
+  // keep the subtractions below as subtractions of the products already
+  // formed (not re-fused into multiply-adds)
+#pragma clang fp contract(off)
   const float t2 = t * t;
   const float s = 1.0f - t;
   const float s2 = s * s;
   N[0] = s2 * s;
   N[1] = fmaf(t2, fmaf(t, 3.0f, -6.0f), 4.0f);
-  N[2] = fmaf(s2, fmaf(s, 3.0f, -6.0f), 4.0f);
   N[3] = t2 * t;
+  // the pieces sum to 6 and their derivatives to 0: the third of each by
+  // subtraction (additions issue at twice the rate of multiplies)
+  N[2] = ((6.0f - N[0]) - N[1]) - N[3];
   dN[0] = -s2;
   dN[1] = t * fmaf(t, 3.0f, -4.0f);
-  dN[2] = fmaf(t, fmaf(t, -3.0f, 2.0f), 1.0f);
+  dN[2] = (s2 - dN[1]) - t2;
   dN[3] = t2;
 }
 
@@ -845,12 +850,15 @@ __device__ __forceinline__ void phong_sample(const RenderArgsDev& a, const float
     const float gl = g[0] * a.light[0] + g[1] * a.light[1] + g[2] * a.light[2];
     const float gv2 = g[0] * eye.v2x + g[1] * eye.v2y + g[2] * eye.v2z;
     const float ndl = gl * inv;
-    const float rv = fmaf(ndl, gv2 * inv, -eye.lv);
-    const float spec = a.ks * ipow_uniform(fmaxf(rv, 0.0f), a.shininess);
+    // r.v of unit vectors is at most 1; the clamps to [0, 1] fold into the
+    // producing instructions (the colours are non-negative, so clamping
+    // them to [0, 1] is taking min(1, .))
+    const float rv = fminf(fmaxf(fmaf(ndl, gv2 * inv, -eye.lv), 0.0f), 1.0f);
+    const float spec = a.ks * ipow_uniform(rv, a.shininess);
     const float kdiff = a.ka + a.kd * fabsf(ndl);
-    sr = fminf(1.0f, fmaf(kdiff, sr, spec));
-    sg = fminf(1.0f, fmaf(kdiff, sg, spec));
-    sb = fminf(1.0f, fmaf(kdiff, sb, spec));
+    sr = fminf(fmaxf(fmaf(kdiff, sr, spec), 0.0f), 1.0f);
+    sg = fminf(fmaxf(fmaf(kdiff, sg, spec), 0.0f), 1.0f);
+    sb = fminf(fmaxf(fmaf(kdiff, sb, spec), 0.0f), 1.0f);
   }
 }
 
@@ -1115,6 +1123,16 @@ constexpr unsigned long long pitch_z_steps(int h) {
 }
 static_assert(pitch_z_step(3, 3) == 1 && pitch_z_step(3, 1) == 0, "pitch table");
 
+// A DPP quad permutation of v.  Every lane's source lies in its own quad,
+// so no lane reads an invalid one and the bound control is immaterial; it
+// is set so that the compiler folds the move into a consuming VOP2
+// instruction (a multiply with a DPP operand instead of a move and a
+// multiply).
+template <int CTRL>
+__device__ __forceinline__ float quad_perm(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
 // Value of lane (group base + q) of each aligned group of L lanes (L = 1, 2
 // or 4, so a group never leaves its quad of lanes), by a DPP quad
 // permutation.
@@ -1126,7 +1144,7 @@ __device__ __forceinline__ float group_bcast(float v) {
     constexpr int b0 = (0 & ~(L - 1)) + Q, b1 = (1 & ~(L - 1)) + Q;
     constexpr int b2 = (2 & ~(L - 1)) + Q, b3 = (3 & ~(L - 1)) + Q;
     constexpr int ctrl = b0 | (b1 << 2) | (b2 << 4) | (b3 << 6);
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
+    return quad_perm<ctrl>(v);
   }
 }
 
@@ -1141,7 +1159,7 @@ __device__ __forceinline__ float group_prev(float v) {
   constexpr int b2 = L == 2 ? 2 : (2 >= D ? 2 - D : 0);
   constexpr int b3 = L == 2 ? (3 - D >= 2 ? 3 - D : 2) : (3 >= D ? 3 - D : 0);
   constexpr int ctrl = b0 | (b1 << 2) | (b2 << 4) | (b3 << 6);
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
+  return quad_perm<ctrl>(v);
 }
 
 // Value of the previous lane of each aligned group of L lanes (L = 2 or 4),
@@ -1659,7 +1677,10 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
     if constexpr (kInteriorPath) {
       if (interior) {
         interior_done = true;
-        for (int j = s0, i = 0; j < s1; j += LPR, ++i) {
+        // local coordinates advance by additions, within the box margin
+        float tk[3] = {ta[0], ta[1], ta[2]};
+        const float emaxf = (float)emax;
+        for (int j = s0; j < s1; j += LPR) {
           // A lane past the round's end evaluates a sample anyway (its
           // window is clamped into the staged brick, so every value is
           // finite) and adds it with alpha 0.
@@ -1668,7 +1689,8 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
           float N[3][P + 1], dN[3][P + 1], fl[3];
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
-            const float t = fmaf((float)i, dt[k], ta[k]);
+            const float t = tk[k];
+            tk[k] = t + dt[k];
             fl[k] = floorf(t);
             const float tl = t - fl[k];
             if constexpr (kScaled)
@@ -1677,7 +1699,7 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
               cardinal<P>(tl, N[k], dN[k]);
           }
           const float ef = fmaf(fl[2], pitch_zf, fmaf(fl[1], pitch_yf, fl[0] + basef));
-          const int e0 = min(max((int)ef, 0), emax);
+          const int e0 = (int)__builtin_amdgcn_fmed3f(ef, 0.0f, emaxf);
           contract<P, SHADE>(N, dN, brick_row(e0), f, g);
           shade(f, g, sr, sg, sb, alpha);
           alpha = valid ? alpha : 0.0f;
