@@ -251,7 +251,10 @@ def batch_leg(b, ctx, steps: int, warmup: int, log):
     """The batching workload (64 requests over four resident BF16 models with
     Beta(2,5) knots, degrees 2/3/4/3, mixed image sizes): the same requests
     rendered one by one with mfa_render, as one batch, and as a replayed HIP
-    graph of the batch."""
+    graph of the batch, first with the default configuration, then after
+    the autotuner has chosen each model's round length and lanes per ray
+    (on the model's largest request of the batch) and the batch has been
+    prepared again."""
     import torch
     models, reqs = wl.batch_config()
     p_of = [int(max(spec.degree)) for spec, _ in models]
@@ -291,20 +294,51 @@ def batch_leg(b, ctx, steps: int, warmup: int, log):
         def batched():
             b.mfa_batch_render(ctx, batch, stream=stream)
 
+        def graph_of_batch():
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                b.mfa_batch_render(ctx, batch)
+            for _ in range(warmup):
+                g.replay()
+            return g
+
         for _ in range(warmup):
             one_by_one()
             batched()
         seq_ms, seq_lat = timed(one_by_one, steps)
         bat_ms, bat_lat = timed(batched, steps)
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            b.mfa_batch_render(ctx, batch)
-        for _ in range(warmup):
-            g.replay()
+        g = graph_of_batch()
         gr_ms, gr_lat = timed(g.replay, steps)
         del g
         log(f"batch: {len(reqs)} requests, {samples} samples; one by one {seq_ms:.3f} ms, "
             f"batch {bat_ms:.3f} ms, graph {gr_ms:.3f} ms")
+        # autotune every model on its largest request, then prepare the batch again
+        tuned = []
+        for m, h in enumerate(handles):
+            mine = [i for i, r in enumerate(reqs) if r.model == m]
+            i = max(mine, key=lambda k: reqs[k].camera.width * reqs[k].camera.height)
+            r = reqs[i]
+            res = b.mfa_autotune(ctx, h, r.camera, r.tf, r.params, outs[i], repeats=5)
+            tuned.append({"model": m, "degree": p_of[m], "round_spans": float(res.round_spans),
+                          "lanes_per_ray": int(res.lanes_per_ray),
+                          "candidates": int(res.candidates), "best_ms": float(res.best_ms),
+                          "default_ms": float(res.default_ms)})
+            log(f"autotune model {m} (p {p_of[m]}) on a {r.camera.width}x{r.camera.height} "
+                f"request: {res.round_spans} spans, {res.lanes_per_ray} lanes per ray, "
+                f"{res.best_ms:.4f} ms against {res.default_ms:.4f} ms by default")
+        b.mfa_batch_free(ctx, batch)
+        batch = None
+        batch = b.mfa_batch_create(ctx, breqs)
+        b.mfa_batch_render(ctx, batch)
+        torch.cuda.synchronize()
+        tuned_samples = sum(int(c.item()) for c in cnts)
+        for _ in range(warmup):
+            batched()
+        tb_ms, tb_lat = timed(batched, steps)
+        g = graph_of_batch()
+        tg_ms, tg_lat = timed(g.replay, steps)
+        del g
+        log(f"tuned batch: {tuned_samples} samples; batch {tb_ms:.3f} ms, graph {tg_ms:.3f} ms")
         return {"workload": "64 requests, 4 BF16 models (Beta(2,5) knots; p 2/3/4/3; 32^3, "
                             "96x128x80, 128^3, 200x200x100), images {256^2, 512^2, 768x432, "
                             "1024^2}, step 1/512, random orbit cameras",
@@ -319,7 +353,17 @@ def batch_leg(b, ctx, steps: int, warmup: int, log):
                 "graph": {"ms": gr_ms, "samples_per_s": samples / (gr_ms * 1e-3),
                           "p50_ms": float(np.percentile(gr_lat, 50)),
                           "p99_ms": float(np.percentile(gr_lat, 99)),
-                          "tflops": flops / (gr_ms * 1e-3) / 1e12}}
+                          "tflops": flops / (gr_ms * 1e-3) / 1e12},
+                "autotune": tuned,
+                "tuned": {"samples_per_batch": tuned_samples,
+                          "batch": {"ms": tb_ms, "samples_per_s": tuned_samples / (tb_ms * 1e-3),
+                                    "p50_ms": float(np.percentile(tb_lat, 50)),
+                                    "p99_ms": float(np.percentile(tb_lat, 99))},
+                          "graph": {"ms": tg_ms, "samples_per_s": tuned_samples / (tg_ms * 1e-3),
+                                    "p50_ms": float(np.percentile(tg_lat, 50)),
+                                    "p99_ms": float(np.percentile(tg_lat, 99))},
+                          "gain_over_one_by_one": seq_ms / tg_ms,
+                          "gain_over_untuned_graph": gr_ms / tg_ms}}
     finally:
         if batch is not None:
             b.mfa_batch_free(ctx, batch)

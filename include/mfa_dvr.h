@@ -293,25 +293,35 @@ typedef struct mfa_tune_result {
   float round_spans; /* chosen round length: knot spans along the fastest axis per lane */
   int32_t candidates; /* configurations timed */
   float best_ms;      /* median kernel time of the chosen configuration */
-  float default_ms;   /* median kernel time of the default (3 spans) */
+  float default_ms;   /* median kernel time of the default (3 spans, 4 lanes per ray) */
+  int32_t lanes_per_ray; /* chosen lanes per ray: 1, 2 or 4 */
 } mfa_tune_result;
 
 /* Autotuner of the ray caster for one model: renders the given request
- * (into rgba_dev, which it overwrites) with each candidate round length
- * (1.5, 2, 3, 4 and 6 knot spans per lane's round of samples; a round's
- * control points are staged in LDS once), one warm-up and `repeats` timed
- * launches each, all candidates interleaved and enqueued back to back on
- * `stream` (the call returns after synchronising it), and keeps the length
+ * (into rgba_dev, which it overwrites) with each candidate configuration,
+ * every combination of a round length (1.5, 2, 3, 4 and 6 knot spans per
+ * lane's round of samples; a round's control points are staged in LDS
+ * once) and a number of lanes sharing one ray (4, 2 or 1: a wave renders a
+ * 4x4, 8x4 or 8x8-pixel tile), one warm-up and `repeats` timed launches
+ * each, all candidates interleaved and enqueued back to back on `stream`
+ * (the call returns after synchronising it), and keeps the configuration
  * with the smallest median kernel time for every later render of the model
- * (single frames, batches prepared afterwards, servers).  The tile shape
- * (4x4 pixels, four lanes per ray) and the LDS budget are fixed by the
- * kernels' occupancy.  Results of later renders change only by rounding
- * (the FP32 sample stepping restarts from FP64 at each round).  out may be
- * null.  Errors: MFA_ERR_HANDLE, MFA_ERR_INVALID (the request, or repeats
- * outside [1, 1000]), MFA_ERR_DEVICE. */
+ * (single frames, batches prepared afterwards, servers; curvature renders
+ * keep four lanes per ray).  The LDS budget is fixed by the kernels'
+ * occupancy.  Results of later renders change only by rounding (the FP32
+ * sample stepping restarts from FP64 at each round, and each lane sums its
+ * own samples).  out may be null.  Errors: MFA_ERR_HANDLE, MFA_ERR_INVALID
+ * (the request, or repeats outside [1, 1000]), MFA_ERR_DEVICE. */
 mfa_status mfa_autotune(mfa_ctx* ctx, int64_t model, const mfa_camera* camera, const mfa_tf* tf,
                         const mfa_render_params* params, float* rgba_dev, int32_t repeats,
                         void* stream, mfa_tune_result* out);
+
+/* Set the ray caster's configuration for a model by hand (what
+ * mfa_autotune chooses): round_spans in [0.5, 16] knot spans per lane's
+ * round, lanes_per_ray 1, 2 or 4.  Applies to renders prepared after the
+ * call.  Errors: MFA_ERR_HANDLE, MFA_ERR_INVALID. */
+mfa_status mfa_model_set_tuning(mfa_ctx* ctx, int64_t model, float round_spans,
+                                int32_t lanes_per_ray);
 
 /* ----------------------------------------------------------------------
  * Serving: a render server with continuous batching.

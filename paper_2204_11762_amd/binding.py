@@ -39,7 +39,7 @@ EXPORTED = ("mfa_create", "mfa_destroy", "mfa_set_memory_budget", "mfa_model_upl
             "mfa_measure_fma_peak", "mfa_autotune", "mfa_batch_create", "mfa_batch_render",
             "mfa_batch_free", "mfa_server_create", "mfa_server_submit", "mfa_server_wait",
             "mfa_server_destroy", "mfa_validate_model", "mfa_validate_render", "mfa_last_error",
-            "mfa_version", "mfa_render_noalloc")
+            "mfa_version", "mfa_render_noalloc", "mfa_model_set_tuning")
 
 
 class MFAError(RuntimeError):
@@ -88,7 +88,7 @@ class RenderRequest(C.Structure):
 
 class TuneResult(C.Structure):
     _fields_ = [("round_spans", C.c_float), ("candidates", C.c_int32), ("best_ms", C.c_float),
-                ("default_ms", C.c_float)]
+                ("default_ms", C.c_float), ("lanes_per_ray", C.c_int32)]
 
 
 class ServerConfig(C.Structure):
@@ -128,6 +128,7 @@ def _load():
         "mfa_kernel_timing": (st, [vp, C.c_int32]),
         "mfa_autotune": (st, [vp, i64, C.POINTER(Camera), C.POINTER(TF), C.POINTER(RenderParams),
                               vp, C.c_int32, vp, C.POINTER(TuneResult)]),
+        "mfa_model_set_tuning": (st, [vp, i64, C.c_float, C.c_int32]),
         "mfa_batch_create": (st, [vp, C.POINTER(RenderRequest), C.c_int32, C.POINTER(i64)]),
         "mfa_batch_render": (st, [vp, i64, vp]),
         "mfa_batch_free": (st, [vp, i64]),
@@ -366,8 +367,8 @@ def mfa_render_curvature(ctx: int, model: int, camera, tf, curvature, params, rg
 
 
 def mfa_autotune(ctx: int, model: int, camera, tf, params, rgba, repeats: int = 5, stream=None):
-    """Tune the model's round length on one request (rgba is overwritten);
-    returns the TuneResult."""
+    """Tune the model's round length and lanes per ray on one request (rgba
+    is overwritten); returns the TuneResult."""
     import torch
     out = _dev_tensor(rgba, torch.float32, (camera.height, camera.width, 4), "rgba")
     t, keep = tf_struct(tf)
@@ -376,6 +377,12 @@ def mfa_autotune(ctx: int, model: int, camera, tf, params, rgba, repeats: int = 
                             C.byref(params_struct(params)), out, int(repeats), _stream_ptr(stream),
                             C.byref(res)))
     return res
+
+
+def mfa_model_set_tuning(ctx: int, model: int, round_spans: float, lanes_per_ray: int) -> None:
+    """Set the model's round length and lanes per ray (what mfa_autotune
+    chooses)."""
+    _check(lib.mfa_model_set_tuning(ctx, int(model), float(round_spans), int(lanes_per_ray)))
 
 
 def mfa_batch_create(ctx: int, requests) -> int:

@@ -45,6 +45,7 @@ constexpr int32_t kMaxBatch = 1 << 16;
 // Round lengths (knot spans along the fastest axis per lane's round) that
 // mfa_autotune times; 3 is the default.
 constexpr double kTuneRoundSpans[] = {1.5, 2.0, 3.0, 4.0, 6.0};
+constexpr int32_t kTuneLanes[] = {4, 2, 1};
 constexpr size_t kMaxCachedTF = 64;
 // Render launches whose kernel duration one timing record holds.
 constexpr size_t kMaxTimedLaunches = 1 << 16;
@@ -346,6 +347,7 @@ struct DeviceModel {
   int64_t nknots[3];
   int64_t batch_refs = 0;  // live batches that render this model
   double round_spans = 3.0;  // knot spans along the fastest axis per lane's round (tunable)
+  int32_t lanes_per_ray = mfa::kLanesPerRay;  // lanes sharing a ray (tunable: 1, 2 or 4)
 };
 
 // LDS plan of the brick ray caster for one request: transfer function,
@@ -392,7 +394,7 @@ void plan_bricks(const DeviceModel& dm, int ntf, double step, bool curv, bool ba
     const double span_len = (dm.hi[k] - dm.lo[k]) / dm.md.ax[k].m;
     cells = std::max(cells, step / span_len);
   }
-  const int spr = cells > 0.0 ? int(dm.round_spans * mfa::kLanesPerRay / cells) : 64;
+  const int spr = cells > 0.0 ? int(dm.round_spans * a.lpr / cells) : 64;
   a.spr = std::max(4, std::min(64, spr));
 }
 
@@ -944,6 +946,8 @@ void build_render_args(const DeviceModel& dm, const mfa_camera* cam, const mfa_t
   a.out = rgba_dev;
   a.samples = reinterpret_cast<unsigned long long*>(samples_dev);
   a.fast = dm.md.uniform && dm.md.ax[0].p >= 2 && dm.md.ax[1].p >= 2 && dm.md.ax[2].p >= 2;
+  // curvature renders use four lanes per ray (the only variant compiled)
+  a.lpr = curv ? mfa::kLanesPerRay : dm.lanes_per_ray;
   a.eq = dm.md.ax[0].p == dm.md.pmax && dm.md.ax[1].p == dm.md.pmax && dm.md.ax[2].p == dm.md.pmax;
   plan_bricks(dm, tf->n, prm->step, curv, batch, a);
   if (dm.md.rational) {
@@ -952,13 +956,13 @@ void build_render_args(const DeviceModel& dm, const mfa_camera* cam, const mfa_t
     a.spr = 0;
     a.brick_cap = 0;
   }
-  a.tile_w = mfa::kTileW;
-  a.tile_h = mfa::kTileH;
+  a.tile_w = mfa::tile_w_of(a.lpr);
+  a.tile_h = mfa::tile_h_of(a.lpr);
   a.ntiles = 0;
   a.nslots = 0;
   if (a.lds_bytes > 0) {
-    const int nsx = (cam->width + 2 * mfa::kTileW - 1) / (2 * mfa::kTileW);
-    const int nsy = (cam->height + 2 * mfa::kTileH - 1) / (2 * mfa::kTileH);
+    const int nsx = (cam->width + 2 * a.tile_w - 1) / (2 * a.tile_w);
+    const int nsy = (cam->height + 2 * a.tile_h - 1) / (2 * a.tile_h);
     a.nsx = nsx;
     a.ntiles = int32_t(int64_t(nsx) * nsy);
     const int R = std::max(1, std::min(mfa::kMaxRegion, int(std::sqrt(a.ntiles / 64.0))));
@@ -1035,11 +1039,11 @@ class BatchBuilder {
         single_.push_back(i);
         continue;
       }
-      const mfa::BatchKey k{a.m.pmax, a.m.store, a.shading, a.fast, a.eq, 0};
+      const mfa::BatchKey k{a.m.pmax, a.m.store, a.shading, a.fast, a.eq, a.lpr, 0};
       Group* gp = nullptr;
       for (auto& g : groups_)
         if (g.key.pmax == k.pmax && g.key.store == k.store && g.key.shading == k.shading &&
-            g.key.fast == k.fast && g.key.eq == k.eq)
+            g.key.fast == k.fast && g.key.eq == k.eq && g.key.lpr == k.lpr)
           gp = &g;
       if (gp == nullptr) {
         groups_.push_back(Group{k, {}, 0, 0, 0, 0, 0, 0});
@@ -1370,16 +1374,22 @@ mfa_status mfa_autotune(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, cons
   // one launch record per candidate; launches of all candidates are
   // interleaved (round robin) and enqueued back to back, with events around
   // each ray-casting kernel, and the stream is synchronised once
-  constexpr int kCand = int(sizeof(kTuneRoundSpans) / sizeof(kTuneRoundSpans[0]));
+  // candidates: every lanes-per-ray count with every round length
+  constexpr int kSpans = int(sizeof(kTuneRoundSpans) / sizeof(kTuneRoundSpans[0]));
+  constexpr int kLanes = int(sizeof(kTuneLanes) / sizeof(kTuneLanes[0]));
+  constexpr int kCand = kSpans * kLanes;
   const double saved = dm.round_spans;
+  const int32_t saved_lanes = dm.lanes_per_ray;
   std::vector<mfa::RenderArgsDev> args(kCand);
   int64_t slots = 0;
   for (int c = 0; c < kCand; ++c) {
-    dm.round_spans = kTuneRoundSpans[c];
+    dm.round_spans = kTuneRoundSpans[c % kSpans];
+    dm.lanes_per_ray = kTuneLanes[c / kSpans];
     build_render_args(dm, cam, tf, prm, rgba_dev, nullptr, tf_dev, args[c]);
     slots = std::max<int64_t>(slots, args[c].nslots);
   }
   dm.round_spans = saved;
+  dm.lanes_per_ray = saved_lanes;
   PlanScratch* ps = nullptr;
   if (args[0].ntiles > 0) {
     st = attach_plan(ctx, stream, slots, args.data(), kCand, &ps);
@@ -1405,6 +1415,7 @@ mfa_status mfa_autotune(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, cons
   if (e != hipSuccess) plan_unready(ctx, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(hs);
   double best = saved, best_ms = 1e30, default_ms = 0.0;
+  int32_t best_lanes = saved_lanes;
   for (int c = 0; c < kCand && e == hipSuccess; ++c) {
     std::vector<float> ms;
     for (int r = 1; r <= repeats && e == hipSuccess; ++r) {
@@ -1415,10 +1426,13 @@ mfa_status mfa_autotune(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, cons
     if (e != hipSuccess) break;
     std::sort(ms.begin(), ms.end());
     const double med = ms[ms.size() / 2];
-    if (kTuneRoundSpans[c] == 3.0) default_ms = med;
+    const double spans = kTuneRoundSpans[c % kSpans];
+    const int32_t lanes = kTuneLanes[c / kSpans];
+    if (spans == 3.0 && lanes == mfa::kLanesPerRay) default_ms = med;
     if (med < best_ms) {
       best_ms = med;
-      best = kTuneRoundSpans[c];
+      best = spans;
+      best_lanes = lanes;
     }
   }
   for (int i = 0; i < made; ++i) {
@@ -1428,12 +1442,29 @@ mfa_status mfa_autotune(mfa_ctx* ctx, int64_t model, const mfa_camera* cam, cons
   if (e != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("autotune launch", e));
   const int32_t tried = kCand;
   dm.round_spans = best;
+  dm.lanes_per_ray = best_lanes;
   if (out != nullptr) {
     out->round_spans = float(best);
+    out->lanes_per_ray = best_lanes;
     out->candidates = tried;
     out->best_ms = float(best_ms);
     out->default_ms = float(default_ms);
   }
+  return MFA_OK;
+}
+
+mfa_status mfa_model_set_tuning(mfa_ctx* ctx, int64_t model, float round_spans,
+                                int32_t lanes_per_ray) {
+  g_last_error.clear();
+  if (ctx == nullptr) return fail(MFA_ERR_HANDLE, "null context");
+  auto it = ctx->models.find(model);
+  if (it == ctx->models.end()) return fail(MFA_ERR_HANDLE, "unknown model handle");
+  if (!(round_spans >= 0.5f && round_spans <= 16.0f))
+    return fail(MFA_ERR_INVALID, "round_spans must be in [0.5, 16]");
+  if (lanes_per_ray != 1 && lanes_per_ray != 2 && lanes_per_ray != 4)
+    return fail(MFA_ERR_INVALID, "lanes_per_ray must be 1, 2 or 4");
+  it->second.round_spans = round_spans;
+  it->second.lanes_per_ray = lanes_per_ray;
   return MFA_OK;
 }
 

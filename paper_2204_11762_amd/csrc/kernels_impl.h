@@ -825,7 +825,7 @@ template <class TfFetch>
 __device__ __forceinline__ void tf_sample(const RenderArgsDev& a, float tf_lo, float tf_scale,
                                           float f, TfFetch tf, float& sr, float& sg, float& sb,
                                           float& alpha) {
-  float x = fmaf(f, tf_scale, -tf_lo * tf_scale);
+  float x = (f - tf_lo) * tf_scale;
   x = fminf(fmaxf(x, 0.0f), 1.0f) * (float)(a.ntf - 1);
   const int i = min((int)x, a.ntf - 2);
   const float t = x - (float)i;
@@ -2270,8 +2270,15 @@ hipError_t launch_brick(const RenderArgsDev& a, hipStream_t st, const KernelEven
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = mark(ev.begin, st);
   if (e != hipSuccess) return e;
-  render_brick_kernel<P, STORE, SHADE, FAST, EQ, kLanesPerRay, CURV>
-      <<<a.nslots, 256, a.lds_bytes, st>>>(a);
+  if constexpr (CURV) {
+    render_brick_kernel<P, STORE, SHADE, FAST, EQ, 4, true><<<a.nslots, 256, a.lds_bytes, st>>>(a);
+  } else if (a.lpr == 1) {
+    render_brick_kernel<P, STORE, SHADE, FAST, EQ, 1, false><<<a.nslots, 256, a.lds_bytes, st>>>(a);
+  } else if (a.lpr == 2) {
+    render_brick_kernel<P, STORE, SHADE, FAST, EQ, 2, false><<<a.nslots, 256, a.lds_bytes, st>>>(a);
+  } else {
+    render_brick_kernel<P, STORE, SHADE, FAST, EQ, 4, false><<<a.nslots, 256, a.lds_bytes, st>>>(a);
+  }
   e = hipGetLastError();
   return e == hipSuccess ? mark(ev.end, st) : e;
 }
@@ -2320,14 +2327,19 @@ hipError_t launch_render_ps(const RenderArgsDev& a, hipStream_t st, const Kernel
 }
 
 template <int P, int STORE, bool SHADE, bool FAST, bool EQ>
-hipError_t launch_batch_class(const BatchDev& b, int lds_bytes, hipStream_t st) {
+hipError_t launch_batch_class(const BatchDev& b, int lds_bytes, int lpr, hipStream_t st) {
   const unsigned blocks = (unsigned)((b.ntiles + 255) / 256);
   batch_zero_kernel<<<1, 256, 0, st>>>(b);
   batch_cost_kernel<<<blocks, 256, 0, st>>>(b);
   plan_scan_kernel<<<1, kBuckets, 0, st>>>(b.tile_hist);
   plan_scatter_kernel<1>
       <<<blocks, 256, 0, st>>>(b.tile_cost, b.ntiles, 1, 1, b.tile_hist, b.tile_order);
-  render_batch_kernel<P, STORE, SHADE, FAST, EQ, kLanesPerRay><<<b.ntiles, 256, lds_bytes, st>>>(b);
+  if (lpr == 1)
+    render_batch_kernel<P, STORE, SHADE, FAST, EQ, 1><<<b.ntiles, 256, lds_bytes, st>>>(b);
+  else if (lpr == 2)
+    render_batch_kernel<P, STORE, SHADE, FAST, EQ, 2><<<b.ntiles, 256, lds_bytes, st>>>(b);
+  else
+    render_batch_kernel<P, STORE, SHADE, FAST, EQ, 4><<<b.ntiles, 256, lds_bytes, st>>>(b);
   return hipGetLastError();
 }
 
@@ -2335,11 +2347,11 @@ template <int P, int STORE, bool SHADE>
 hipError_t batch_ps(const BatchDev& b, const BatchKey& k, hipStream_t st) {
   if constexpr (P >= 2) {
     if (k.fast)
-      return k.eq ? launch_batch_class<P, STORE, SHADE, true, true>(b, k.lds_bytes, st)
-                  : launch_batch_class<P, STORE, SHADE, true, false>(b, k.lds_bytes, st);
+      return k.eq ? launch_batch_class<P, STORE, SHADE, true, true>(b, k.lds_bytes, k.lpr, st)
+                  : launch_batch_class<P, STORE, SHADE, true, false>(b, k.lds_bytes, k.lpr, st);
   }
-  return k.eq ? launch_batch_class<P, STORE, SHADE, false, true>(b, k.lds_bytes, st)
-              : launch_batch_class<P, STORE, SHADE, false, false>(b, k.lds_bytes, st);
+  return k.eq ? launch_batch_class<P, STORE, SHADE, false, true>(b, k.lds_bytes, k.lpr, st)
+              : launch_batch_class<P, STORE, SHADE, false, false>(b, k.lds_bytes, k.lpr, st);
 }
 
 template <int P, int STORE>

@@ -11,11 +11,12 @@ constexpr int kMaxDegree = 4;
 // Largest number of samples one ray may take; the host rejects requests
 // whose box diagonal exceeds this many steps.
 constexpr int kMaxSamplesPerRay = 1 << 16;
-// Lanes that share one ray in the brick ray caster (1, 2 or 4); tiles are
-// 8x8, 8x4 or 4x4 pixels accordingly.
+// Lanes that share one ray in the brick ray caster (1, 2 or 4, chosen per
+// model; curvature renders always use four); a wave's tile is 8x8, 8x4 or
+// 4x4 pixels accordingly.
 constexpr int kLanesPerRay = 4;
-constexpr int kTileW = kLanesPerRay == 4 ? 4 : 8;
-constexpr int kTileH = 64 / kLanesPerRay / kTileW;
+constexpr int tile_w_of(int lpr) { return lpr == 4 ? 4 : 8; }
+constexpr int tile_h_of(int lpr) { return 64 / lpr / tile_w_of(lpr); }
 
 // Launch order of single frames: super-tiles are grouped by square regions
 // of `region` x `region` super-tiles into one group per XCD (the hardware
@@ -143,7 +144,8 @@ struct RenderArgsDev {
   int32_t nsx;          // super-tiles per image row
   int32_t region;       // side of the square regions of the XCD grouping (super-tiles)
   int32_t nslots;       // launch slots: kXcdGroups x the largest group (>= ntiles)
-  int32_t tile_w;       // tile size in pixels (kTileW x kTileH)
+  int32_t lpr;          // lanes per ray (1, 2 or 4)
+  int32_t tile_w;       // tile size in pixels (tile_w_of(lpr) x tile_h_of(lpr))
   int32_t tile_h;
   int32_t* tile_cost;   // ntiles work estimates (scratch)
   int32_t* tile_order;  // nslots super-tile indices, -1 for empty slots (scratch)
@@ -204,6 +206,7 @@ struct BatchKey {
   int32_t shading;
   int32_t fast;
   int32_t eq;
+  int32_t lpr;
   int32_t lds_bytes;
 };
 

@@ -140,3 +140,26 @@ def compare_image(gpu_img, gpu_count, wk, pix, tau, px_tol, model=None, count_ex
     rmse = float(np.sqrt((err ** 2).mean()))
     return ImageReport(rmse, float(np.abs(err).max()), int(amb.sum()), int(bad.sum()),
                        gpu_count, int(nom.samples.sum()), slack)
+
+
+def small_workload(seed, n, deg, beta, lo, hi, image, kind, shade, ert, head):
+    """(model spec, workload) of a small random parity case: a random model
+    of the given sizes, degrees and knots on the box [lo, hi], an orbit
+    (perspective) or oblique orthographic camera, a piecewise-linear table
+    over the control-point range, step ext / 97."""
+    from paper_2204_11762_amd import workloads as wl
+    W, H = image
+    rng = np.random.default_rng(seed)
+    spec = wl.random_model(rng, n=n, degree=deg, beta_knots=beta, lo=lo, hi=hi)
+    ctr = tuple((np.asarray(lo) + np.asarray(hi)) / 2)
+    ext = float(np.max(np.asarray(hi) - np.asarray(lo)))
+    if kind == "persp":
+        cam = wl.orbit_camera(W, H, 30 + 40 * seed, -20 + 15 * seed, radius=2.2 * ext, target=ctr)
+    else:
+        cam = wl.CameraSpec("ortho", (ctr[0] + 0.3, ctr[1] + 0.2, ctr[2] + 3 * ext), ctr,
+                            (0.0, 1.0, 0.0), W, H, ortho_half_w=0.6 * ext, ortho_half_h=0.7 * ext)
+    P = np.asarray(spec.ctrl)
+    tf = wl.pwl_tf(seed, P.min(), P.max(), alpha_max=0.15)
+    prm = wl.ParamSpec(step=ext / 97.0, ert_alpha=ert, shading=shade, headlight=head,
+                       light_dir=(0.3, -0.5, 0.8))
+    return spec, wl.Workload("small", spec, cam, tf, prm)

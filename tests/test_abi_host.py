@@ -216,6 +216,8 @@ def test_null_context_and_handles(b):
     assert b.lib.mfa_batch_render(None, 1, None) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_batch_free(None, 1) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_autotune(None, 1, None, None, None, None, 1, None, None) == b.MFA_ERR_HANDLE
+    assert b.lib.mfa_model_set_tuning(None, 1, 3.0, 4) == b.MFA_ERR_HANDLE
+    assert b.lib.mfa_render_noalloc(None, 1, None, None, None, None, None, None) == b.MFA_ERR_HANDLE
     sh = C.c_void_p()
     assert b.lib.mfa_server_create(None, None, C.byref(sh)) == b.MFA_ERR_HANDLE
     assert b.lib.mfa_server_submit(None, None, C.byref(bh)) == b.MFA_ERR_HANDLE

@@ -158,13 +158,16 @@ def test_batch_errors(mfa):
             b.mfa_model_free(ctx, h)
 
 
-def test_batch_config_full_size_sampled(mfa):
+@pytest.mark.parametrize("tuned", [False, True])
+def test_batch_config_full_size_sampled(mfa, tuned):
     """The batching workload at full size (64 requests, 4 BF16 models with
     Beta(2,5) knots, degrees 2/3/4/3, images up to 1024^2), rendered as one
-    batch exactly as the benchmark times it.  Every request is checked on
-    sampled pixels (hit pixels and misses): against the oracle on the
-    de-quantised model at the FP32 bar (arithmetic error), and against the
-    FP64 model at the BF16 bar (storage and arithmetic together)."""
+    batch exactly as the benchmark times it: with the default configuration,
+    and after the autotuner has chosen each model's round length and lanes
+    per ray on its largest request.  Every request is checked on sampled
+    pixels (hit pixels and misses): against the oracle on the de-quantised
+    model at the FP32 bar (arithmetic error), and against the FP64 model at
+    the BF16 bar (storage and arithmetic together)."""
     import torch
     b, ctx = mfa
     models, reqs = wl.batch_config()
@@ -172,6 +175,13 @@ def test_batch_config_full_size_sampled(mfa):
     deq = [oracle_model(spec, ctrl=quant.dequant_bf16(spec.ctrl)) for spec, _ in models]
     batch = None
     try:
+        if tuned:
+            for m, h in enumerate(handles):
+                mine = [i for i, r in enumerate(reqs) if r.model == m]
+                i = max(mine, key=lambda k: reqs[k].camera.width * reqs[k].camera.height)
+                res = b.mfa_autotune(ctx, h, reqs[i].camera, reqs[i].tf, reqs[i].params,
+                                     outs[i], repeats=2)
+                print(f"\n  model {m}: {res.round_spans} spans, {res.lanes_per_ray} lanes per ray")
         batch = b.mfa_batch_create(ctx, breqs)
         b.mfa_batch_render(ctx, batch)
         torch.cuda.synchronize()

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from gpu_helpers import (BF16_REL, BF16_RMSE, F16_RMSE, FP32_REL, FP32_RMSE, compare_image, gpu_eval,
-                         gpu_render, normwise, oracle_on_pixels)
+                         gpu_render, normwise, oracle_on_pixels, small_workload)
 from helpers import oracle_workload, oracle_model
 from oracle import bspline as ob
 from oracle import quant
@@ -73,21 +73,8 @@ SMALL = [
 @pytest.mark.parametrize("case", range(len(SMALL)))
 @pytest.mark.parametrize("store", [0, 1, 2])
 def test_small_full_frames(mfa, case, store):
-    seed, n, deg, beta, lo, hi, (W, H), kind, shade, ert, head = SMALL[case]
-    rng = np.random.default_rng(seed)
-    spec = wl.random_model(rng, n=n, degree=deg, beta_knots=beta, lo=lo, hi=hi)
-    ctr = tuple((np.asarray(lo) + np.asarray(hi)) / 2)
-    ext = float(np.max(np.asarray(hi) - np.asarray(lo)))
-    if kind == "persp":
-        cam = wl.orbit_camera(W, H, 30 + 40 * seed, -20 + 15 * seed, radius=2.2 * ext, target=ctr)
-    else:
-        cam = wl.CameraSpec("ortho", (ctr[0] + 0.3, ctr[1] + 0.2, ctr[2] + 3 * ext), ctr,
-                            (0.0, 1.0, 0.0), W, H, ortho_half_w=0.6 * ext, ortho_half_h=0.7 * ext)
-    P = np.asarray(spec.ctrl)
-    tf = wl.pwl_tf(seed, P.min(), P.max(), alpha_max=0.15)
-    prm = wl.ParamSpec(step=ext / 97.0, ert_alpha=ert, shading=shade, headlight=head,
-                       light_dir=(0.3, -0.5, 0.8))
-    wk = wl.Workload("small", spec, cam, tf, prm)
+    spec, wk = small_workload(*SMALL[case])
+    W, H = wk.camera.width, wk.camera.height
     b, ctx = mfa
     h = b.mfa_model_upload(ctx, spec, store)
     try:
@@ -282,9 +269,9 @@ def test_kernel_timing(mfa):
 
 
 def test_autotune_keeps_parity(mfa):
-    """The autotuner picks one of its candidate round lengths, never one
-    slower than the default it timed, and renders after tuning still match
-    the oracle."""
+    """The autotuner picks one of its candidate configurations (round
+    length and lanes per ray), never one slower than the default it timed,
+    and renders after tuning still match the oracle."""
     import torch
     b, ctx = mfa
     wk = wl.c2()
@@ -293,10 +280,12 @@ def test_autotune_keeps_parity(mfa):
     try:
         scratch = torch.zeros((256, 256, 4), dtype=torch.float32, device="cuda")
         res = b.mfa_autotune(ctx, h, wk.camera, wk.tf, wk.params, scratch, repeats=3)
-        print(f"\n  tuned round spans {res.round_spans}, {res.candidates} candidates, "
-              f"best {res.best_ms:.4f} ms, default {res.default_ms:.4f} ms")
-        assert res.candidates == 5
+        print(f"\n  tuned round spans {res.round_spans}, {res.lanes_per_ray} lanes per ray, "
+              f"{res.candidates} candidates, best {res.best_ms:.4f} ms, "
+              f"default {res.default_ms:.4f} ms")
+        assert res.candidates == 15
         assert res.round_spans in (1.5, 2.0, 3.0, 4.0, 6.0)
+        assert res.lanes_per_ray in (1, 2, 4)
         assert 0 < res.best_ms <= res.default_ms
         img, cnt = gpu_render(b, ctx, h, wk)
         pix = wl.pixel_subset(256, 256, 1500, seed=8)
