@@ -1250,8 +1250,9 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
       const int nk = a.m.ax[k].n + a.m.ax[k].p + 1;
       for (int i = tid; i < nk; i += 256) knots[a.knot_off[k] + i] = a.m.ax[k].knots[i];
     }
+    // the knots are read by the span search of the ray setup below
+    __syncthreads();
   }
-  __syncthreads();
   float* brick = reinterpret_cast<float*>(lds + a.lds_bricks) + wave * a.brick_cap;
   const double* K[3] = {knots + a.knot_off[0], knots + a.knot_off[1], knots + a.knot_off[2]};
   auto tf = [&](int i) { return tf_lds[i]; };
@@ -1302,6 +1303,9 @@ __device__ __forceinline__ void brick_render(const RenderArgsDev& a, int sup) {
     }
     eye = eye_terms(a, -(float)ray.d[0], -(float)ray.d[1], -(float)ray.d[2]);
   }
+  // uniform knots: the transfer function is first read by the samples, so
+  // its loads overlap the ray setup above (every wave reaches this barrier)
+  if constexpr (FAST) __syncthreads();
   auto param = [&](int s, int k) {
     return fmin(fmax(fma((double)s, ub[k], ua[k]), 0.0), 1.0);
   };
