@@ -414,13 +414,16 @@ mfa_status mfa_measure_fma_peak(mfa_ctx* ctx, double* tflops);
  * gradient query, all three derivatives at once) at n world points
  * xyz_dev (n*3 FP64, point-major).  Points outside the box are clamped to
  * it.  value_dev: n FP32; grad_dev: n*3 FP32 or null for value only.
- * n = 0 is a no-op.  Asynchronous on `stream`.  From 2^16 points on, the
- * points are binned on the device (an 8^3 grid over the box, in Morton
- * order) and evaluated bin by bin unless a probe finds neighbouring points
- * already in the same bins; results stay in the caller's order and equal
- * those of a direct query bit for bit.  This uses 6 bytes of device memory
- * per point in the stream's scratch, kept until the context is destroyed;
- * if it cannot be allocated, the points are evaluated in the given order.
+ * n = 0 is a no-op.  Asynchronous on `stream`.  From 2^16 points on (for
+ * models whose gathers would miss the caches), the points are sorted on
+ * the device by bin (a 16^3 grid over the box, in Morton order; no sort
+ * when they arrive in that order) and each bin is evaluated from its
+ * control points staged in LDS, or, for rational models and models whose
+ * bins need more than 64 KiB of LDS, gathered in bin order; results stay in
+ * the caller's order and equal those of a direct query bit for bit.  This
+ * uses 12 bytes of device memory per point in the stream's scratch, kept
+ * until the context is destroyed; if it cannot be allocated, the points
+ * are evaluated in the given order.
  * Errors: MFA_ERR_INVALID (n < 0, null buffers with n > 0), MFA_ERR_HANDLE,
  * MFA_ERR_DEVICE. */
 mfa_status mfa_eval_points(mfa_ctx* ctx, int64_t model, int64_t n, const double* xyz_dev,

@@ -348,6 +348,11 @@ struct DeviceModel {
   int64_t batch_refs = 0;  // live batches that render this model
   double round_spans = 3.0;  // knot spans along the fastest axis per lane's round (tunable)
   int32_t lanes_per_ray = mfa::kLanesPerRay;  // lanes sharing a ray (tunable: 1, 2 or 4)
+  // binned point queries: the slabs' span ranges and LDS boxes (pointers
+  // set per call), and the LDS of a workgroup (0: not binned, evaluated by
+  // gathers in bin order)
+  mfa::EvalBinDev bins{};
+  int32_t bin_lds_bytes = 0;
 };
 
 // LDS plan of the brick ray caster for one request: transfer function,
@@ -460,13 +465,56 @@ struct EvalScratch {
   void* mem = nullptr;
   int64_t points = 0;
 };
-// Point queries from this many points on may be evaluated in locality
-// order (binned on the device; skipped there when the input is already
-// local), if the model's gathers would miss the caches: when
-// sqrt(control-point bytes) * (p+1)^3 reaches kEvalOrderScore.  Below it
-// the control points stay cached and ordering costs more than it saves
-// (2^24 random points: 32^3 at degree 1 took 0.026 ns per query unordered
-// against 0.070 ordered; 128^3 at degree 4 0.358 against 0.144).
+// Layout of the ordering scratch for a capacity of `points` points: the
+// counters, the bins' starts and first work items, the digit counts of the
+// sorting workgroups, then the two buffers of keys and of point indices.
+struct EvalLayout {
+  size_t flags, totals, bin_start, item_base, hist, key0, key1, idx0, idx1, bytes;
+};
+EvalLayout eval_layout(int64_t points) {
+  EvalLayout l{};
+  const int64_t groups = (points + mfa::kEvalSortChunk - 1) / mfa::kEvalSortChunk;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = (off + bytes + 255) & ~size_t(255);
+    return at;
+  };
+  l.flags = take(64 * 4);
+  l.totals = take(size_t(mfa::kEvalDigits) * 4);
+  l.bin_start = take(size_t(mfa::kEvalBins + 1) * 4);
+  l.item_base = take(size_t(mfa::kEvalBins + 1) * 4);
+  l.hist = take(size_t(mfa::kEvalDigits) * size_t(groups) * 4);
+  l.key0 = take(size_t(points) * 2);
+  l.key1 = take(size_t(points) * 2);
+  l.idx0 = take(size_t(points) * 4);
+  l.idx1 = take(size_t(points) * 4);
+  l.bytes = off;
+  return l;
+}
+// Knot span of u on a clamped knot vector U with n control points and
+// degree p: the largest s in [p, n-1] with U[s] <= u (n-1 from U[n] on),
+// as the kernels find it.
+int64_t host_span(const double* U, int64_t n, int p, double u) {
+  if (u >= U[n]) return n - 1;
+  int64_t lo = p, hi = n;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (U[mid] <= u)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+// Point queries from this many points on are sorted by bin on the device
+// if the model's gathers would miss the caches: when sqrt(control-point
+// bytes) * (p+1)^3 reaches kEvalOrderScore.  Below it the control points
+// stay cached and ordering costs more than it saves (2^24 random points
+// with the gathers in bin order: 32^3 at degree 1 took 0.026 ns per query
+// unordered against 0.070 ordered; 128^3 at degree 4 0.358 against 0.144).
+// Sorted points are evaluated bin by bin from LDS where the model's slab
+// boxes fit (non-rational models), else gathered in bin order.
 constexpr int64_t kEvalOrderMin = int64_t(1) << 16;
 constexpr double kEvalOrderScore = 4.0e4;
 constexpr size_t kMaxPlanStreams = 16;
@@ -634,8 +682,7 @@ mfa_status attach_eval(mfa_ctx* ctx, void* stream, int64_t points, mfa::EvalOrde
       }
     }
     EvalScratch es;
-    const size_t bytes = size_t(2 * mfa::kEvalBins + 64) * 4 + size_t(points) * 6 + 256;
-    const hipError_t e = hipMalloc(&es.mem, bytes);
+    const hipError_t e = hipMalloc(&es.mem, eval_layout(points).bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(MFA_ERR_NOMEM, hip_msg("hipMalloc (point order)", e));
@@ -643,12 +690,17 @@ mfa_status attach_eval(mfa_ctx* ctx, void* stream, int64_t points, mfa::EvalOrde
     es.points = points;
     it = ctx->evals.emplace(stream, es).first;
   }
-  unsigned* base = static_cast<unsigned*>(it->second.mem);
-  o.counts = base;
-  o.cursor = base + mfa::kEvalBins;
-  o.flags = base + 2 * mfa::kEvalBins;
-  o.order = reinterpret_cast<int32_t*>(base + 2 * mfa::kEvalBins + 64);
-  o.bin = reinterpret_cast<uint16_t*>(o.order + it->second.points);
+  const EvalLayout l = eval_layout(it->second.points);
+  unsigned char* base = static_cast<unsigned char*>(it->second.mem);
+  o.flags = reinterpret_cast<unsigned*>(base + l.flags);
+  o.totals = reinterpret_cast<unsigned*>(base + l.totals);
+  o.bin_start = reinterpret_cast<int32_t*>(base + l.bin_start);
+  o.item_base = reinterpret_cast<int32_t*>(base + l.item_base);
+  o.hist = reinterpret_cast<unsigned*>(base + l.hist);
+  o.key[0] = reinterpret_cast<uint16_t*>(base + l.key0);
+  o.key[1] = reinterpret_cast<uint16_t*>(base + l.key1);
+  o.idx[0] = reinterpret_cast<int32_t*>(base + l.idx0);
+  o.idx[1] = reinterpret_cast<int32_t*>(base + l.idx1);
   return MFA_OK;
 }
 
@@ -836,6 +888,35 @@ mfa_status mfa_model_upload(mfa_ctx* ctx, const mfa_model_desc* d, int64_t* mode
   dm.md.nx = int32_t(n[0]);
   dm.md.nxy = int32_t(n[0] * n[1]);
   dm.md.pmax = pmax;
+  // slab span ranges of the binned point queries: slab j of an axis holds
+  // the parameters in [j/16, (j+1)/16), the last one also 1
+  {
+    mfa::EvalBinDev& bd = dm.bins;
+    int nspan = 0;
+    for (int k = 0; k < 3; ++k) {
+      int most = 0;
+      for (int j = 0; j < mfa::kEvalSlabs; ++j) {
+        const int64_t lo_s = host_span(d->knots[k], n[k], d->degree[k],
+                                       double(j) / double(mfa::kEvalSlabs));
+        const int64_t hi_s = j + 1 == mfa::kEvalSlabs
+                                 ? n[k] - 1
+                                 : host_span(d->knots[k], n[k], d->degree[k],
+                                             double(j + 1) / double(mfa::kEvalSlabs));
+        bd.span_lo[k][j] = int32_t(lo_s);
+        bd.span_hi[k][j] = int32_t(hi_s);
+        most = std::max(most, int(hi_s - lo_s + 1));
+      }
+      bd.ext[k] = most + pmax;
+      nspan = std::max(nspan, most);
+    }
+    bd.nspan = nspan;
+    bd.tstride = mfa::table_stride(pmax);
+    const int64_t box = int64_t(bd.ext[0]) * bd.ext[1] * bd.ext[2];
+    const int64_t lds = box > mfa::kEvalBinMaxLds
+                            ? int64_t(mfa::kEvalBinMaxLds) + 1
+                            : int64_t(mfa::eval_bin_lds_bytes(nspan, bd.tstride, int(box)));
+    dm.bin_lds_bytes = (!rational && lds <= mfa::kEvalBinMaxLds) ? int32_t(lds) : 0;
+  }
 
   const int64_t id = ctx->next_id++;
   ctx->models.emplace(id, dm);
@@ -1580,6 +1661,10 @@ mfa_status eval_common(mfa_ctx* ctx, int64_t model, int64_t n, const double* xyz
                        std::pow(double(dm.md.pmax + 1), 3.0);
   if (n >= kEvalOrderMin && n <= int64_t(INT32_MAX) && score >= kEvalOrderScore) {
     mfa::EvalOrderDev o{};
+    // binned evaluation from LDS where the model's slabs fit: always
+    // sorted; otherwise gathers, in bin order unless the probe finds the
+    // points already local
+    const bool binned = dm.bin_lds_bytes > 0;
     const mfa_status st = attach_eval(ctx, stream, n, o);
     if (st == MFA_ERR_NOMEM) {
       // the order is an optimisation: without its scratch, evaluate the
@@ -1596,9 +1681,23 @@ mfa_status eval_common(mfa_ctx* ctx, int64_t model, int64_t n, const double* xyz
       o.lo[k] = dm.md.ax[k].lo;
       o.inv_ext[k] = dm.md.ax[k].inv_ext;
     }
+    o.force = binned ? 1 : 0;
+    o.bins = binned ? 1 : 0;
+    o.groups = int32_t((n + mfa::kEvalSortChunk - 1) / mfa::kEvalSortChunk);
     const hipError_t eo = mfa::launch_eval_order(o, static_cast<hipStream_t>(stream));
     if (eo != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("point order launch", eo));
-    a.order = o.order;
+    if (binned) {
+      mfa::EvalBinDev bd = dm.bins;
+      bd.order = o.idx[mfa::kEvalPasses % 2];
+      bd.bin_start = o.bin_start;
+      bd.item_base = o.item_base;
+      bd.flags = o.flags;
+      const hipError_t eb =
+          mfa::launch_eval_bins(a, bd, dm.bin_lds_bytes, static_cast<hipStream_t>(stream));
+      if (eb != hipSuccess) return fail(MFA_ERR_DEVICE, hip_msg("binned eval launch", eb));
+      return MFA_OK;
+    }
+    a.order = o.idx[mfa::kEvalPasses % 2];
     a.use_order = o.flags + 1;
   }
   const hipError_t e = mfa::launch_eval(a, static_cast<hipStream_t>(stream));

@@ -49,6 +49,12 @@ extern template hipError_t batch_for_store<2>(const BatchDev&, const BatchKey&, 
 extern template hipError_t eval_for_store<0>(const EvalArgsDev&, hipStream_t);
 extern template hipError_t eval_for_store<1>(const EvalArgsDev&, hipStream_t);
 extern template hipError_t eval_for_store<2>(const EvalArgsDev&, hipStream_t);
+extern template hipError_t eval_bins_for_store<0>(const EvalArgsDev&, const EvalBinDev&, int,
+                                                  hipStream_t);
+extern template hipError_t eval_bins_for_store<1>(const EvalArgsDev&, const EvalBinDev&, int,
+                                                  hipStream_t);
+extern template hipError_t eval_bins_for_store<2>(const EvalArgsDev&, const EvalBinDev&, int,
+                                                  hipStream_t);
 
 hipError_t launch_fma_peak(float* out, int blocks, int iters, hipStream_t st) {
   fma_peak_kernel<<<blocks, 256, 0, st>>>(out, iters, 0.999999f, 1e-6f);
@@ -86,14 +92,36 @@ hipError_t launch_render_batch(const BatchDev& b, const BatchKey& k, hipStream_t
 
 hipError_t launch_eval_order(const EvalOrderDev& o, hipStream_t st) {
   if (o.n <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((o.n + kEvalOrderChunk - 1) / kEvalOrderChunk);
-  if (o.n < int64_t(64) * kEvalProbeWaves) return hipErrorInvalidValue;
-  eval_order_zero<<<1, kEvalBins, 0, st>>>(o);
-  eval_order_probe<<<kEvalProbeWaves / 4, 256, 0, st>>>(o);
-  eval_order_bin<<<blocks, 256, 0, st>>>(o);
-  eval_order_scan<<<1, kEvalBins, 0, st>>>(o);
-  eval_order_scatter<<<blocks, 256, 0, st>>>(o);
+  if (o.n < int64_t(64) * kEvalProbeWaves || o.n > int64_t(INT32_MAX)) return hipErrorInvalidValue;
+  if (o.groups != (o.n + kEvalSortChunk - 1) / kEvalSortChunk) return hipErrorInvalidValue;
+  if (o.bins && !o.force) return hipErrorInvalidValue;
+  const unsigned groups = (unsigned)o.groups;
+  eval_order_zero<<<1, 256, 0, st>>>(o);
+  if (!o.force) eval_order_probe<<<kEvalProbeWaves / 4, 256, 0, st>>>(o);
+  eval_sort_count<0><<<groups, 256, 0, st>>>(o);
+  eval_sort_scan<<<kEvalDigits, 256, 0, st>>>(o, 1);
+  eval_sort_scatter<0><<<groups, 256, 0, st>>>(o);
+  eval_sort_count<1><<<groups, 256, 0, st>>>(o);
+  eval_sort_scan<<<kEvalDigits, 256, 0, st>>>(o, 0);
+  eval_sort_scatter<1><<<groups, 256, 0, st>>>(o);
+  static_assert(kEvalPasses == 2, "the launches above are the passes");
+  if (o.bins) {
+    eval_bin_mark<<<(unsigned)((o.n + 255) / 256), 256, 0, st>>>(o);
+    eval_bin_items<<<1, 1024, 0, st>>>(o);
+  }
   return hipGetLastError();
+}
+
+hipError_t launch_eval_bins(const EvalArgsDev& a, const EvalBinDev& d, int lds_bytes,
+                            hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  if (lds_bytes <= 0 || lds_bytes > kEvalBinMaxLds) return hipErrorInvalidValue;
+  switch (a.m.store) {
+    case 0: return eval_bins_for_store<0>(a, d, lds_bytes, st);
+    case 1: return eval_bins_for_store<1>(a, d, lds_bytes, st);
+    case 2: return eval_bins_for_store<2>(a, d, lds_bytes, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_eval(const EvalArgsDev& a, hipStream_t st) {

@@ -23,7 +23,9 @@
 // for curvature transfer functions) gives each lane one ray of a 16x16
 // tile.  In both, neighbouring rays run in one wave, so their gathers share
 // cache lines.  Point queries (eval_kernel, eval_hess_kernel) give each
-// lane one point; the latter also returns the second derivatives.
+// lane one point; the latter also returns the second derivatives.  Large
+// point queries are sorted by bin first (eval_sort_*) and evaluated bin by
+// bin from control points staged in LDS (eval_bin_kernel).
 //
 // Mixed per-axis degrees run in the kernel of the largest degree P: an axis
 // of degree q < P uses the window of P+1 control points that starts at its
@@ -2119,36 +2121,58 @@ __global__ __launch_bounds__(256) void eval_hess_kernel(EvalArgsDev a) {
 }
 
 // ---------------------------------------------------------------------------
-// locality order of point queries: a counting sort by bin
+// locality order of point queries: a radix sort by cell
 // ---------------------------------------------------------------------------
 
-// Bin of a point: its cell on an 8^3 grid over the box, the three 3-bit
-// cell indices interleaved (Morton order, x lowest).
-__device__ __forceinline__ unsigned eval_bin(const EvalOrderDev& o, int64_t i) {
+// Sort key of a point: its bin, the cell on a 16^3 grid over the box, the
+// three 4-bit slab indices interleaved (Morton order, x lowest).  The
+// parameter is the one the evaluation forms; u * 16 is exact, so slab j
+// holds exactly the parameters in [j/16, (j+1)/16) (and 1 in the last
+// slab).
+__device__ __forceinline__ unsigned eval_key(const EvalOrderDev& o, int64_t i) {
+  constexpr int C = kEvalKeyBits / 3;
   unsigned code = 0u;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const double u = fmin(fmax((o.xyz[3 * i + k] - o.lo[k]) * o.inv_ext[k], 0.0), 1.0);
-    const unsigned c = (unsigned)min((int)(u * (double)(1 << kEvalBinBits)),
-                                     (1 << kEvalBinBits) - 1);
+    const unsigned c = (unsigned)min((int)(u * (double)(1 << C)), (1 << C) - 1);
 #pragma unroll
-    for (int b = 0; b < kEvalBinBits; ++b) code |= ((c >> b) & 1u) << (3 * b + k);
+    for (int b = 0; b < C; ++b) code |= ((c >> b) & 1u) << (3 * b + k);
   }
   return code;
 }
+static_assert(kEvalKeyBits == 3 * kEvalBinBits, "the key is the bin");
 
-__global__ __launch_bounds__(kEvalBins) void eval_order_zero(EvalOrderDev o) {
-  o.counts[threadIdx.x] = 0u;
-  if (threadIdx.x < 2) o.flags[threadIdx.x] = 0u;
+// Whether to form the keys: always when forced; else kEvalProbeWaves
+// waves, spread evenly over the points, each compare the bins of 64
+// consecutive points, and the keys are formed when more than one
+// neighbouring pair in eight changes bin.  The first count then notes
+// whether the keys are out of order (flags[3]); only then do the sorting
+// passes run and the evaluation follow the order (flags[1], set by the
+// first scan).
+constexpr int kEvalProbeWaves = 256;
+__device__ __forceinline__ bool eval_form_keys(const EvalOrderDev& o) {
+  return o.force != 0 || (uint64_t)o.flags[0] * 8u > (uint64_t)kEvalProbeWaves * 63u;
 }
 
-// Whether to order: kEvalProbeWaves waves, spread evenly over the points,
-// each compare the bins of 64 consecutive points; the order is used when
-// more than one neighbouring pair in eight changes bin.  Every kernel of
-// the ordering takes the decision from the probe's count alone.
-constexpr int kEvalProbeWaves = 256;
-__device__ __forceinline__ bool eval_use_order(const EvalOrderDev& o) {
-  return (uint64_t)o.flags[0] * 8u > (uint64_t)kEvalProbeWaves * 63u;
+// Lanes of the wave whose digit equals this lane's (among the valid lanes):
+// six ballots, one per digit bit.
+__device__ __forceinline__ unsigned long long match_digit(unsigned d, bool valid) {
+  unsigned long long m = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < kEvalDigitBits; ++b) {
+    const bool bit = ((d >> b) & 1u) != 0u;
+    const unsigned long long bb = __ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
+// Counters, and the bin bounds of the binned evaluation set to "empty at n".
+__global__ __launch_bounds__(256) void eval_order_zero(EvalOrderDev o) {
+  if (threadIdx.x < 4) o.flags[threadIdx.x] = 0u;
+  if (o.bins)
+    for (int b = threadIdx.x; b <= kEvalBins; b += 256) o.bin_start[b] = (int32_t)o.n;
 }
 
 // Needs n >= 64 kEvalProbeWaves (the host orders from 2^16 points on).
@@ -2156,82 +2180,470 @@ __global__ __launch_bounds__(256) void eval_order_probe(EvalOrderDev o) {
   const int lane = threadIdx.x & 63;
   const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t i = (int64_t)w * (o.n / kEvalProbeWaves) + lane;
-  const unsigned code = eval_bin(o, i);
+  const unsigned code = eval_key(o, i);
   const unsigned prev = (unsigned)__shfl_up((int)code, 1, 64);
   const unsigned long long m = __ballot(lane > 0 && prev != code);
   if (lane == 0 && m != 0ull) atomicAdd(&o.flags[0], (unsigned)__popcll(m));
 }
 
-// Workgroup g bins points [g C, g C + C) (C = kEvalOrderChunk; thread t
-// takes g C + t + 256 j): bin numbers and points per bin, counted in LDS
-// with one global atomic per bin and workgroup.
-__global__ __launch_bounds__(256) void eval_order_bin(EvalOrderDev o) {
-  if (!eval_use_order(o)) return;
-  __shared__ unsigned hist[kEvalBins];
-  const int tid = threadIdx.x;
-  for (int b = tid; b < kEvalBins; b += 256) hist[b] = 0u;
+// Digit of a key in pass PASS (least significant first).
+template <int PASS>
+__device__ __forceinline__ unsigned eval_digit(unsigned key) {
+  return (key >> (PASS * kEvalDigitBits)) & (unsigned)(kEvalDigits - 1);
+}
+
+// Digit counts of workgroup g's points [g C, g C + C) (C = kEvalSortChunk),
+// written digit-major (digit d at d * groups + g); each wave adds its
+// lanes of one digit at once.  The first pass also forms every point's key
+// and notes whether any key is below its predecessor's.
+template <int PASS>
+__global__ __launch_bounds__(256) void eval_sort_count(EvalOrderDev o) {
+  if constexpr (PASS == 0) {
+    if (!eval_form_keys(o)) return;
+  } else {
+    if (o.flags[1] == 0u) return;
+  }
+  __shared__ unsigned h[kEvalDigits];
+  __shared__ unsigned h_desc;
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < kEvalDigits) h[tid] = 0u;
+  if (tid == 0) h_desc = 0u;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kEvalOrderChunk;
-  for (int j = 0; j < kEvalOrderChunk / 256; ++j) {
+  const int64_t base = (int64_t)blockIdx.x * kEvalSortChunk;
+  bool descent = false;
+  for (int j = 0; j < kEvalSortChunk / 256; ++j) {
     const int64_t i = base + j * 256 + tid;
-    if (i < o.n) {
-      const unsigned code = eval_bin(o, i);
-      o.bin[i] = (uint16_t)code;
-      atomicAdd(&hist[code], 1u);
+    const bool valid = i < o.n;
+    unsigned key = 0u;
+    if (valid) {
+      if constexpr (PASS == 0) {
+        key = eval_key(o, i);
+        o.key[0][i] = (uint16_t)key;
+      } else {
+        key = o.key[PASS & 1][i];
+      }
+    }
+    if constexpr (PASS == 0) {
+      unsigned prev = (unsigned)__shfl_up((int)key, 1, 64);
+      if (lane == 0 && i > 0 && valid) prev = eval_key(o, i - 1);
+      descent |= valid && i > 0 && key < prev;
+    }
+    const unsigned d = eval_digit<PASS>(key);
+    const unsigned long long m = match_digit(d, valid);
+    if (valid && (m >> lane) == 1ull) atomicAdd(&h[d], (unsigned)__popcll(m));
+  }
+  if constexpr (PASS == 0) {
+    if (__ballot(descent) != 0ull && lane == 0) h_desc = 1u;
+  }
+  __syncthreads();
+  if (tid < kEvalDigits) o.hist[(int64_t)tid * o.groups + blockIdx.x] = h[tid];
+  // one flag update per workgroup, none once another has set it
+  if (PASS == 0 && tid == 0 && h_desc != 0u && o.flags[3] == 0u) atomicOr(&o.flags[3], 1u);
+}
+
+__device__ __forceinline__ unsigned wave_inclusive_scan(unsigned v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const unsigned o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Exclusive prefix sum of v over a workgroup of 1024 threads (thread
+// order); total receives the sum.  wsum: 16 words of LDS.
+__device__ __forceinline__ unsigned block_scan_1024(unsigned v, unsigned* wsum,
+                                                    unsigned& total) {
+  const int w = threadIdx.x >> 6;
+  const unsigned incl = wave_inclusive_scan(v);
+  if (__lane_id() == 63) wsum[w] = incl;
+  __syncthreads();
+  unsigned before = 0u, all = 0u;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const unsigned x = wsum[k];
+    before += k < w ? x : 0u;
+    all += x;
+  }
+  __syncthreads();
+  total = all;
+  return before + incl - v;
+}
+
+// Exclusive prefix sums of the digit counts over the workgroups, in place:
+// workgroup d scans digit d's row of `groups` counts, 2048 at a time, and
+// records the row's total.  The scatter adds the totals of the smaller
+// digits.  The first pass's scan also records whether the points are
+// sorted and evaluated in that order (flags[1]).
+__global__ __launch_bounds__(256) void eval_sort_scan(EvalOrderDev o, int first) {
+  __shared__ unsigned wsum[4];
+  const bool use = first ? (eval_form_keys(o) && o.flags[3] != 0u) : o.flags[1] != 0u;
+  if (first && blockIdx.x == 0 && threadIdx.x == 0) o.flags[1] = use ? 1u : 0u;
+  if (!use) return;
+  constexpr int E = 8;  // counts per thread and tile
+  unsigned* row = o.hist + (int64_t)blockIdx.x * o.groups;
+  const int tid = threadIdx.x, w = tid >> 6;
+  unsigned carry = 0u;
+  for (int t0 = 0; t0 < o.groups; t0 += 256 * E) {
+    unsigned v[E], sum = 0u;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = t0 + tid * E + e;
+      v[e] = i < o.groups ? row[i] : 0u;
+      sum += v[e];
+    }
+    const unsigned incl = wave_inclusive_scan(sum);
+    if (__lane_id() == 63) wsum[w] = incl;
+    __syncthreads();
+    unsigned before = carry, all = carry;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      before += k < w ? wsum[k] : 0u;
+      all += wsum[k];
+    }
+    __syncthreads();
+    unsigned run = before + incl - sum;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = t0 + tid * E + e;
+      if (i < o.groups) row[i] = run;
+      run += v[e];
+    }
+    carry = all;
+  }
+  if (tid == 0) o.totals[blockIdx.x] = carry;
+}
+
+// Stable scatter of workgroup g's points by digit.  The points are first
+// ordered by digit in LDS, 256 per round in point order: a wave ranks its
+// lanes among those with the same digit, and the waves' counts per digit
+// give each wave its first position per digit, after the positions of the
+// rounds before.  Then each digit's points, contiguous in LDS, are written
+// to the digit's range (coalesced runs).  The workgroup's count of a digit
+// is the difference of neighbouring scanned counts.  Pass r reads the keys
+// and indices of buffer r % 2 (the first pass: the keys formed by its
+// count, indices implicit) and writes buffer (r + 1) % 2.
+template <int PASS>
+__global__ __launch_bounds__(256) void eval_sort_scatter(EvalOrderDev o) {
+  if (o.flags[1] == 0u) return;
+  constexpr int J = kEvalSortChunk / 256;
+  static_assert(kEvalDigits == 64, "one wave forms the digits' positions");
+  __shared__ unsigned lkey[kEvalSortChunk];
+  __shared__ int32_t lidx[kEvalSortChunk];
+  __shared__ unsigned gbase[kEvalDigits];  // first sorted position of each digit's points
+  __shared__ unsigned lbase[kEvalDigits];  // their first position in LDS
+  __shared__ unsigned run[kEvalDigits];    // next position in LDS
+  __shared__ unsigned wcnt[4][kEvalDigits];
+  __shared__ unsigned woff[4][kEvalDigits];
+  const uint16_t* kin = o.key[PASS & 1];
+  const int32_t* iin = o.idx[PASS & 1];
+  uint16_t* kout = o.key[(PASS + 1) & 1];
+  int32_t* iout = o.idx[(PASS + 1) & 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g = blockIdx.x;
+  const int64_t base = (int64_t)g * kEvalSortChunk;
+  const int cnt = (int)min((int64_t)kEvalSortChunk, o.n - base);
+  unsigned key[J];
+  int32_t idx[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int l = j * 256 + tid;
+    const bool valid = l < cnt;
+    key[j] = valid ? kin[base + l] : 0u;
+    if constexpr (PASS == 0)
+      idx[j] = (int32_t)(base + l);
+    else
+      idx[j] = valid ? iin[base + l] : 0;
+  }
+  for (int k = tid; k < 4 * kEvalDigits; k += 256) wcnt[k / kEvalDigits][k % kEvalDigits] = 0u;
+  if (tid < kEvalDigits) {
+    const unsigned* row = o.hist + (int64_t)tid * o.groups;
+    const unsigned t = o.totals[tid];
+    const unsigned c = (g + 1 < o.groups ? row[g + 1] : t) - row[g];
+    const unsigned lb = wave_inclusive_scan(c) - c;
+    lbase[tid] = lb;
+    run[tid] = lb;
+    gbase[tid] = wave_inclusive_scan(t) - t + row[g];
+  }
+  __syncthreads();
+  const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const bool valid = j * 256 + tid < cnt;
+    const unsigned d = eval_digit<PASS>(key[j]);
+    const unsigned long long m = match_digit(d, valid);
+    const unsigned rank = (unsigned)__popcll(m & below);
+    // the highest lane of each digit's group records the group's size
+    if (valid && (m >> lane) == 1ull) wcnt[w][d] = (unsigned)__popcll(m);
+    __syncthreads();
+    if (tid < kEvalDigits) {
+      unsigned r = run[tid];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        woff[v][tid] = r;
+        r += wcnt[v][tid];
+        wcnt[v][tid] = 0u;
+      }
+      run[tid] = r;
+    }
+    __syncthreads();
+    if (valid) {
+      const unsigned pos = woff[w][d] + rank;
+      lkey[pos] = key[j];
+      lidx[pos] = idx[j];
     }
   }
   __syncthreads();
-  for (int b = tid; b < kEvalBins; b += 256)
-    if (hist[b] != 0u) atomicAdd(&o.counts[b], hist[b]);
+  for (int e = tid; e < cnt; e += 256) {
+    const unsigned k = lkey[e];
+    const unsigned d = eval_digit<PASS>(k);
+    const unsigned pos = gbase[d] + ((unsigned)e - lbase[d]);
+    kout[pos] = (uint16_t)k;
+    iout[pos] = lidx[e];
+  }
 }
 
-// Exclusive prefix sum of the bin counts into the cursors, and the
-// decision for the evaluation kernel.
-__global__ __launch_bounds__(kEvalBins) void eval_order_scan(EvalOrderDev o) {
-  const bool use = eval_use_order(o);
-  if (threadIdx.x == 0) o.flags[1] = use ? 1u : 0u;
-  if (!use) return;
-  __shared__ unsigned part[kEvalBins];
+// First sorted position of every non-empty bin (the keys are sorted, as
+// formed or by the passes, so a bin starts where the bin number changes).
+__global__ __launch_bounds__(256) void eval_bin_mark(EvalOrderDev o) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= o.n) return;
+  const uint16_t* key = o.key[o.flags[1] != 0u ? (kEvalPasses & 1) : 0];
+  const unsigned k = key[i];
+  if (i == 0 || (unsigned)key[i - 1] != k) o.bin_start[k] = (int32_t)i;
+}
+
+// Bounds and work items of the bins (one workgroup of 1024 threads, four
+// bins each): an empty bin starts where the next non-empty one does (a
+// suffix minimum by doubling in LDS), bin b holds
+// ceil(count / kEvalItemPoints) work items, and their exclusive prefix sums
+// give each bin's first item; flags[2] is the number of items.
+__global__ __launch_bounds__(1024) void eval_bin_items(EvalOrderDev o) {
+  __shared__ int32_t S[kEvalBins + 1];
+  __shared__ unsigned wsum[16];
   const int tid = threadIdx.x;
-  const unsigned v = o.counts[tid];
-  part[tid] = v;
+  for (int b = tid; b <= kEvalBins; b += 1024) S[b] = o.bin_start[b];
   __syncthreads();
   for (int off = 1; off < kEvalBins; off <<= 1) {
-    const unsigned x = tid >= off ? part[tid - off] : 0u;
+    int32_t v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = 4 * tid + q;
+      v[q] = b + off <= kEvalBins ? min(S[b], S[b + off]) : S[b];
+    }
     __syncthreads();
-    part[tid] += x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) S[4 * tid + q] = v[q];
     __syncthreads();
   }
-  o.cursor[tid] = part[tid] - v;
+  unsigned items[4], sum = 0u;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int b = 4 * tid + q;
+    const unsigned cnt = (unsigned)(S[b + 1] - S[b]);
+    items[q] = (cnt + (unsigned)kEvalItemPoints - 1u) / (unsigned)kEvalItemPoints;
+    sum += items[q];
+  }
+  unsigned total;
+  unsigned run = block_scan_1024(sum, wsum, total);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int b = 4 * tid + q;
+    o.bin_start[b] = S[b];
+    o.item_base[b] = (int32_t)run;
+    run += items[q];
+  }
+  if (tid == 0) {
+    o.item_base[kEvalBins] = (int32_t)total;
+    o.flags[2] = total;
+  }
 }
 
-// Point indices bin by bin: workgroup g takes the points it binned, ranks
-// them within their bins in LDS, reserves one range per bin with a global
-// atomic, and writes them there (the order within a bin is arbitrary: every
-// point's result is independent of it).
-__global__ __launch_bounds__(256) void eval_order_scatter(EvalOrderDev o) {
-  if (!eval_use_order(o)) return;
-  __shared__ unsigned cnt[kEvalBins];
+// ---------------------------------------------------------------------------
+// binned evaluation of point queries from LDS
+// ---------------------------------------------------------------------------
+
+// Work item g (see EvalBinDev): its bin (the largest b whose first item is
+// at most g; empty bins share their first item with the next bin), its
+// share of the bin's points, then the bin's knots, basis-table rows and
+// box of control points in LDS.  Each point is evaluated as by
+// eval_kernel / eval_hess_kernel, with the same span (the bisection starts
+// from the slab's span range, which holds it), the same basis arithmetic
+// and the same control-point values, so the results are the same bits.
+template <int P, int STORE, int MODE>  // MODE 0: value, 1: and gradient, 2: and Hessian
+__global__ __launch_bounds__(256) void eval_bin_kernel(EvalArgsDev a, EvalBinDev d) {
+  extern __shared__ __align__(16) unsigned char eval_lds[];
+  constexpr bool GRAD = MODE >= 1;
+  const int g = blockIdx.x;
+  if (g >= (int)d.flags[2]) return;
+  int lo = 0, hi = kEvalBins;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (d.item_base[mid] <= g)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const int bin = lo;
+  const int items = d.item_base[bin + 1] - d.item_base[bin];
+  const int j = g - d.item_base[bin];
+  const int bs = d.bin_start[bin];
+  const int64_t cnt = (int64_t)(d.bin_start[bin + 1] - bs);
+  const int first = bs + (int)(cnt * j / items);
+  const int last = bs + (int)(cnt * (j + 1) / items);
+
+  const int kn = eval_bin_knot_slots(d.nspan);
+  double* K = reinterpret_cast<double*>(eval_lds);
+  float* T = reinterpret_cast<float*>(K + 3 * kn);
+  float* B = T + 3 * d.nspan * d.tstride;
   const int tid = threadIdx.x;
-  for (int b = tid; b < kEvalBins; b += 256) cnt[b] = 0u;
-  __syncthreads();
-  constexpr int J = kEvalOrderChunk / 256;
-  const int64_t base = (int64_t)blockIdx.x * kEvalOrderChunk;
-  unsigned code[J], rank[J];
+  int slo[3], shi[3], x0[3];
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int64_t i = base + j * 256 + tid;
-    code[j] = i < o.n ? (unsigned)o.bin[i] : 0u;
-    rank[j] = i < o.n ? atomicAdd(&cnt[code[j]], 1u) : 0u;
+  for (int k = 0; k < 3; ++k) {
+    int slab = 0;
+#pragma unroll
+    for (int b = 0; b < kEvalBinBits; ++b) slab |= ((bin >> (3 * b + k)) & 1) << b;
+    slo[k] = d.span_lo[k][slab];
+    shi[k] = d.span_hi[k][slab];
+    x0[k] = slo[k] - a.m.ax[k].p;
+  }
+  // knots U[slo .. shi+1] and table rows of spans slo .. shi
+  for (int e = tid; e < 3 * kn; e += 256) {
+    const int k = e / kn, r = e - k * kn;
+    if (r <= shi[k] - slo[k] + 1) K[e] = a.m.ax[k].knots[slo[k] + r];
+  }
+  {
+    const int per_axis = d.nspan * d.tstride;
+    for (int e = tid; e < 3 * per_axis; e += 256) {
+      const int k = e / per_axis, rem = e - k * per_axis;
+      const int r = rem / d.tstride, c = rem - r * d.tstride;
+      const int ts = table_stride(a.m.ax[k].p);
+      if (r <= shi[k] - slo[k] && c < ts)
+        T[e] = a.m.ax[k].tab[(size_t)(x0[k] + r) * (size_t)ts + c];
+    }
+  }
+  // box of control points, entries past the grid 0
+  const int ex = d.ext[0], ey = d.ext[1], ez = d.ext[2];
+  {
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.m.ctrl, a.m.ctrl_bytes);
+    const int nx = a.m.ax[0].n, ny = a.m.ax[1].n, nz = a.m.ax[2].n;
+    const int box = ex * ey * ez;
+    // (ix, iy, iz) of element e = tid + 256 r, advanced incrementally
+    int iz = tid / (ex * ey);
+    int iy = (tid - iz * ex * ey) / ex;
+    int ix = tid - iz * ex * ey - iy * ex;
+    const int sz = 256 / (ex * ey);
+    const int sy = (256 - sz * ex * ey) / ex;
+    const int sx = 256 - sz * ex * ey - sy * ex;
+    for (int e = tid; e < box; e += 256) {
+      const int gx = x0[0] + ix, gy = x0[1] + iy, gz = x0[2] + iz;
+      float v = 0.0f;
+      if (gx < nx && gy < ny && gz < nz) {
+        const int gi = gx + a.m.nx * gy + a.m.nxy * gz;
+        if constexpr (STORE == 0) {
+          v = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)gi * 4u, 0, 0));
+        } else {
+          const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)(gi >> 1) * 4u, 0, 0);
+          v = (gi & 1) ? h16_hi<STORE>(w) : h16_lo<STORE>(w);
+        }
+      }
+      B[e] = v;
+      ix += sx;
+      iy += sy;
+      iz += sz;
+      if (ix >= ex) {
+        ix -= ex;
+        ++iy;
+      }
+      if (iy >= ey) {
+        iy -= ey;
+        ++iz;
+      }
+    }
   }
   __syncthreads();
-  for (int b = tid; b < kEvalBins; b += 256)
-    if (cnt[b] != 0u) cnt[b] = atomicAdd(&o.cursor[b], cnt[b]);
-  __syncthreads();
+
+  double un[3];
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int64_t i = base + j * 256 + tid;
-    if (i < o.n) o.order[cnt[code[j]] + rank[j]] = (int32_t)i;
+  for (int k = 0; k < 3; ++k) un[k] = a.m.ax[k].knots[a.m.ax[k].n];
+  const int pitch_z = ex * ey;
+  // sorted by the passes (else the points came in key order)
+  const bool permuted = d.flags[1] != 0u;
+  for (int t = first + tid; t < last; t += 256) {
+    const int64_t i = permuted ? (int64_t)d.order[t] : (int64_t)t;
+    double u[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double x = a.xyz[3 * i + k];
+      const double v = (x - a.m.ax[k].lo) * a.m.ax[k].inv_ext;
+      u[k] = fmin(fmax(v, 0.0), 1.0);
+    }
+    float N[3][P + 1], dN[3][P + 1], ddN[3][P + 1];
+    int off[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double* Kk = K + k * kn - slo[k];  // Kk[s] = U[s] for s in [slo, shi + 1]
+      int s;
+      if (u[k] >= un[k]) {
+        s = a.m.ax[k].n - 1;
+      } else {
+        int l = slo[k], h = shi[k] + 1;  // U[l] <= u < U[h]
+        while (h - l > 1) {
+          const int mid = (l + h) >> 1;
+          if (Kk[mid] <= u[k])
+            l = mid;
+          else
+            h = mid;
+        }
+        s = l;
+      }
+      const float dd = (float)(u[k] - Kk[s]);
+      const float* row = T + (k * d.nspan + (s - slo[k])) * d.tstride;
+      if constexpr (MODE == 2)
+        axis_basis2<P>(a.m.ax[k].p, row, dd, N[k], dN[k], ddN[k]);
+      else
+        axis_basis<P>(a.m.ax[k].p, row, dd, N[k], dN[k]);
+      off[k] = s - slo[k];
+    }
+    const int e0 = off[0] + ex * off[1] + pitch_z * off[2];
+    auto fetch = [&](int b, int c, float (&row)[P + 1]) {
+      const float* r = B + e0 + b * ex + c * pitch_z;
+#pragma unroll
+      for (int q = 0; q <= P; ++q) row[q] = r[q];
+    };
+    float f, gr[3];
+    if constexpr (MODE == 2) {
+      float h[6];
+      contract_hess<P>(N, dN, ddN, fetch, f, gr, h);
+      const float sx = a.m.ax[0].gscale, sy = a.m.ax[1].gscale, sz = a.m.ax[2].gscale;
+      gr[0] *= sx;
+      gr[1] *= sy;
+      gr[2] *= sz;
+      h[0] *= sx * sx;
+      h[1] *= sy * sy;
+      h[2] *= sz * sz;
+      h[3] *= sx * sy;
+      h[4] *= sx * sz;
+      h[5] *= sy * sz;
+      a.value[i] = f;
+      if (a.grad != nullptr) {
+        a.grad[3 * i + 0] = gr[0];
+        a.grad[3 * i + 1] = gr[1];
+        a.grad[3 * i + 2] = gr[2];
+      }
+      float* o = a.hess + 6 * i;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) o[c] = h[c];
+    } else {
+      contract<P, GRAD>(N, dN, fetch, f, gr);
+      a.value[i] = f;
+      if constexpr (GRAD) {
+        a.grad[3 * i + 0] = gr[0] * a.m.ax[0].gscale;
+        a.grad[3 * i + 1] = gr[1] * a.m.ax[1].gscale;
+        a.grad[3 * i + 2] = gr[2] * a.m.ax[2].gscale;
+      }
+    }
   }
 }
 
@@ -2395,6 +2807,18 @@ hipError_t launch_eval_p(const EvalArgsDev& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int P, int STORE>
+hipError_t launch_eval_bins_p(const EvalArgsDev& a, const EvalBinDev& d, int lds, hipStream_t st) {
+  const unsigned blocks = (unsigned)((a.n + kEvalItemPoints - 1) / kEvalItemPoints) + kEvalBins;
+  if (a.hess)
+    eval_bin_kernel<P, STORE, 2><<<blocks, 256, lds, st>>>(a, d);
+  else if (a.grad)
+    eval_bin_kernel<P, STORE, 1><<<blocks, 256, lds, st>>>(a, d);
+  else
+    eval_bin_kernel<P, STORE, 0><<<blocks, 256, lds, st>>>(a, d);
+  return hipGetLastError();
+}
+
 template <int STORE>
 hipError_t dispatch_render(const RenderArgsDev& a, hipStream_t st, const KernelEvents& ev) {
   switch (a.m.pmax) {
@@ -2432,6 +2856,18 @@ hipError_t batch_for_store(const BatchDev& b, const BatchKey& k, hipStream_t st)
 template <int STORE>
 hipError_t eval_for_store(const EvalArgsDev& a, hipStream_t st) {
   return dispatch_eval<STORE>(a, st);
+}
+template <int STORE>
+hipError_t eval_bins_for_store(const EvalArgsDev& a, const EvalBinDev& d, int lds,
+                               hipStream_t st) {
+  if (a.m.rational) return hipErrorInvalidValue;  // the host sends these to eval_kernel
+  switch (a.m.pmax) {
+    case 1: return launch_eval_bins_p<1, STORE>(a, d, lds, st);
+    case 2: return launch_eval_bins_p<2, STORE>(a, d, lds, st);
+    case 3: return launch_eval_bins_p<3, STORE>(a, d, lds, st);
+    case 4: return launch_eval_bins_p<4, STORE>(a, d, lds, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace mfa

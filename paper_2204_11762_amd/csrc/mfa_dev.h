@@ -168,23 +168,66 @@ struct EvalArgsDev {
   const unsigned* use_order;
 };
 
-// Locality ordering of large point queries: the points are binned on an
-// 8^3 grid over the box, the bins numbered in Morton order, and evaluated
-// bin by bin, unless consecutive points already share bins.  A workgroup
-// bins kEvalOrderChunk points with LDS counters.
-constexpr int kEvalBinBits = 3;
+// Locality ordering of large point queries.  A point's key is its bin, its
+// cell on a 16^3 grid over the box (16 slabs per axis), the three 4-bit
+// slab indices interleaved (Morton order, x lowest).  Unless the keys come
+// in order already, the points are sorted by key with a
+// least-significant-digit radix sort of two 6-bit digits: each pass counts
+// the digits of kEvalSortChunk points per workgroup, scans the counts per
+// digit, and scatters the points stably.
+constexpr int kEvalBinBits = 4;
+constexpr int kEvalSlabs = 1 << kEvalBinBits;
 constexpr int kEvalBins = 1 << (3 * kEvalBinBits);
-constexpr int kEvalOrderChunk = 4096;
+constexpr int kEvalKeyBits = 12;
+constexpr int kEvalDigitBits = 6;
+constexpr int kEvalDigits = 1 << kEvalDigitBits;
+constexpr int kEvalPasses = kEvalKeyBits / kEvalDigitBits;
+static_assert(kEvalPasses * kEvalDigitBits == kEvalKeyBits && kEvalKeyBits % 3 == 0,
+              "whole digits of a three-axis key");
+constexpr int kEvalSortChunk = 4096;
+// Work item of the binned evaluation: at most this many points of one bin.
+constexpr int kEvalItemPoints = 4096;
+// Largest LDS of a binned-evaluation workgroup; models whose slabs need
+// more are evaluated by gathers in bin order.
+constexpr int kEvalBinMaxLds = 64 * 1024;
 struct EvalOrderDev {
   const double* xyz;
   int64_t n;              // <= INT32_MAX
   double lo[3];
   double inv_ext[3];
-  uint16_t* bin;          // n bin numbers
-  unsigned* counts;       // kEvalBins points per bin
-  unsigned* cursor;       // kEvalBins next free slot per bin
-  unsigned* flags;        // [0] bin changes among the probed neighbours, [1] use the order
-  int32_t* order;         // n point indices, bin by bin
+  int32_t force;          // 1: order whatever the probe finds
+  int32_t bins;           // 1: also form the bins' bounds and work items
+  int32_t groups;         // sorting workgroups, ceil(n / kEvalSortChunk)
+  unsigned* flags;        // [0] bin changes among the probed neighbours,
+                          // [1] points sorted by the passes (evaluated in that order),
+                          // [2] work items of the bins, [3] keys formed out of order
+  uint16_t* key[2];       // n keys each: pass r reads key[r % 2], writes key[(r + 1) % 2]
+  int32_t* idx[2];        // n point indices each, likewise (the first pass reads none);
+                          // after the last pass idx[kEvalPasses % 2] is the order
+  unsigned* hist;         // kEvalDigits * groups digit counts, then their scan per digit
+  unsigned* totals;       // kEvalDigits: points per digit
+  int32_t* bin_start;     // kEvalBins + 1: first sorted position of each bin
+  int32_t* item_base;     // kEvalBins + 1: first work item of each bin
+};
+
+// Binned evaluation (non-rational models): work item g takes up to
+// kEvalItemPoints points of one bin in the sorted order, stages in LDS the
+// knots, basis tables and control points that the bin's windows can touch,
+// and evaluates its points from LDS.  Slab j of axis k holds parameters in
+// [j/16, (j+1)/16) (the last slab also 1); its points' knot spans lie in
+// [span_lo[k][j], span_hi[k][j]].  The staged box of control points starts
+// at span_lo - p per axis and has ext[k] = (most spans of a slab) + pmax
+// entries (entries past the grid are staged as 0).
+struct EvalBinDev {
+  const int32_t* order;   // point indices in sorted order (used when flags[1])
+  const int32_t* bin_start;
+  const int32_t* item_base;
+  const unsigned* flags;
+  int32_t span_lo[3][kEvalSlabs];
+  int32_t span_hi[3][kEvalSlabs];
+  int32_t ext[3];
+  int32_t nspan;          // most spans of a slab on any axis
+  int32_t tstride;        // table row stride in LDS (floats)
 };
 
 // The requests of a render batch that share one kernel variant (a class):
@@ -241,6 +284,19 @@ hipError_t launch_render(const RenderArgsDev& a, hipStream_t stream, const Kerne
 hipError_t launch_render_batch(const BatchDev& b, const BatchKey& k, hipStream_t stream);
 hipError_t launch_eval(const EvalArgsDev& a, hipStream_t stream);
 hipError_t launch_eval_order(const EvalOrderDev& o, hipStream_t stream);
+// Binned evaluation after launch_eval_order with bins = 1; lds_bytes from
+// eval_bin_lds_bytes().
+hipError_t launch_eval_bins(const EvalArgsDev& a, const EvalBinDev& d, int lds_bytes,
+                            hipStream_t stream);
+// LDS of a binned-evaluation workgroup: per axis an even number of knot
+// slots (at least nspan + 1 doubles), then per axis nspan table rows of
+// tstride floats, then the box of control points (FP32).
+__host__ __device__ constexpr int eval_bin_knot_slots(int nspan) {
+  return (nspan + 2) & ~1;
+}
+__host__ __device__ constexpr int eval_bin_lds_bytes(int nspan, int tstride, int box) {
+  return 3 * eval_bin_knot_slots(nspan) * 8 + 3 * nspan * tstride * 4 + box * 4;
+}
 // Initial state of a single frame's planning scratch: kPlanWords zero
 // counters at hist.
 hipError_t launch_plan_init(unsigned* hist, hipStream_t stream);
