@@ -616,26 +616,87 @@ __device__ __forceinline__ void contract_hess(const float (&N)[3][P + 1],
 // value and gradient query at arbitrary points (global-memory gathers)
 // ---------------------------------------------------------------------------
 
+// Knot span of u on axis A, the largest s in [p, n-1] with U[s] <= u (n-1
+// from U[n] on).  Uniform knots: walked from the cell of u m, which is the
+// span or next to it.
+__device__ __forceinline__ int query_span(const AxisDev& A, bool uniform, double u) {
+  if (uniform) {
+    const int s0 = min(A.p + (int)(u * A.m), A.n - 1);
+    return span_walk(A.knots, A.n, A.p, u, s0);
+  }
+  return span_search(A.knots, A.n, A.p, u);
+}
+
+// Whether span s of an axis with uniform knots is interior: the 2q knots
+// around it (U_{s-q+1} .. U_{s+q}) are equally spaced, so the cardinal
+// pieces give its basis functions.
+__device__ __forceinline__ bool uniform_interior(const AxisDev& A, int s) {
+  const int q = A.p, c = s - q, m = A.n - q;
+  return c >= q - 1 && c <= m - q;
+}
+
+// Basis functions and u-derivatives of one axis at u in span s.  Uniform
+// knots on an interior span: the cardinal pieces at t = u m - (s - p), the
+// derivatives times m; otherwise the triangle with the span's table row at
+// d = u - U_s.
+template <int P>
+__device__ __forceinline__ void query_basis(const AxisDev& A, bool uniform, int s, double u,
+                                            double us, const float* row, float (&N)[P + 1],
+                                            float (&dN)[P + 1]) {
+  if (uniform && uniform_interior(A, s)) {
+    const float t = (float)(u * A.m - (double)(s - A.p));
+    cardinal_window<P>(A.p, t, N, dN);
+    const float mf = (float)A.m;
+#pragma unroll
+    for (int r = 0; r <= P; ++r) dN[r] *= mf;
+  } else {
+    axis_basis<P>(A.p, row, (float)(u - us), N, dN);
+  }
+}
+
+// The same with second u-derivatives (times m^2 on interior spans).
+template <int P>
+__device__ __forceinline__ void query_basis2(const AxisDev& A, bool uniform, int s, double u,
+                                             double us, const float* row, float (&N)[P + 1],
+                                             float (&dN)[P + 1], float (&ddN)[P + 1]) {
+  if (uniform && uniform_interior(A, s)) {
+    const float t = (float)(u * A.m - (double)(s - A.p));
+    cardinal_window<P>(A.p, t, N, dN);
+    cardinal_dd_window<P>(A.p, t, ddN);
+    const float mf = (float)A.m, m2 = mf * mf;
+#pragma unroll
+    for (int r = 0; r <= P; ++r) {
+      dN[r] *= mf;
+      ddN[r] *= m2;
+    }
+  } else {
+    axis_basis2<P>(A.p, row, (float)(u - us), N, dN, ddN);
+  }
+}
+
 // Value f and world-space gradient g at parameters u (each in [0,1]).
 // span[] carries the spans between calls along one ray; first = true
-// locates them from scratch.  RAT: rs holds w*P and rsw holds w; the value
+// locates them from scratch.  CARD: on uniform knots, spans walked from
+// the cell of u m and cardinal pieces on interior spans (the point
+// queries); the global-memory caster keeps the bisection and the triangle,
+// which it needs fewer scalar registers for.  RAT: rs holds w*P and rsw holds w; the value
 // is the quotient of the two contractions and the gradient follows from the
 // quotient rule, (grad A - f grad D) / D.
-template <int P, int STORE, bool GRAD, bool RAT>
+template <int P, int STORE, bool GRAD, bool RAT, bool CARD = true>
 __device__ __forceinline__ void query(const ModelDev& m, __amdgpu_buffer_rsrc_t rs,
                                       __amdgpu_buffer_rsrc_t rsw, const double (&u)[3],
                                       int (&span)[3], bool first, float& f, float (&g)[3]) {
   float N[3][P + 1], dN[3][P + 1];
   int w[3];
+  const bool uni = CARD && m.uniform != 0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const AxisDev& A = m.ax[k];
-    const int s = first ? span_search(A.knots, A.n, A.p, u[k])
+    const int s = first ? query_span(A, uni, u[k])
                         : span_walk(A.knots, A.n, A.p, u[k], span[k]);
     span[k] = s;
-    const float d = (float)(u[k] - A.knots[s]);
     const float* row = A.tab + (size_t)(s - A.p) * (size_t)table_stride(A.p);
-    axis_basis<P>(A.p, row, d, N[k], dN[k]);
+    query_basis<P>(A, uni, s, u[k], A.knots[s], row, N[k], dN[k]);
     w[k] = s - A.p;
   }
   const int e0 = w[0] + m.nx * w[1] + m.nxy * w[2];
@@ -670,21 +731,21 @@ __device__ __forceinline__ void query(const ModelDev& m, __amdgpu_buffer_rsrc_t 
 // parameters u of a non-rational model; span[] as in query().  The
 // parametric second derivative d2f/du_k du_l is scaled by the two
 // reciprocal box extents.
-template <int P, int STORE>
+template <int P, int STORE, bool CARD = true>
 __device__ __forceinline__ void query_hess(const ModelDev& m, __amdgpu_buffer_rsrc_t rs,
                                            const double (&u)[3], int (&span)[3], bool first,
                                            float& f, float (&g)[3], float (&h)[6]) {
   float N[3][P + 1], dN[3][P + 1], ddN[3][P + 1];
   int w[3];
+  const bool uni = CARD && m.uniform != 0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const AxisDev& A = m.ax[k];
-    const int s = first ? span_search(A.knots, A.n, A.p, u[k])
+    const int s = first ? query_span(A, uni, u[k])
                         : span_walk(A.knots, A.n, A.p, u[k], span[k]);
     span[k] = s;
-    const float d = (float)(u[k] - A.knots[s]);
     const float* row = A.tab + (size_t)(s - A.p) * (size_t)table_stride(A.p);
-    axis_basis2<P>(A.p, row, d, N[k], dN[k], ddN[k]);
+    query_basis2<P>(A, uni, s, u[k], A.knots[s], row, N[k], dN[k], ddN[k]);
     w[k] = s - A.p;
   }
   const int e0 = w[0] + m.nx * w[1] + m.nxy * w[2];
@@ -998,7 +1059,7 @@ __global__ __launch_bounds__(256) void render_global_kernel(RenderArgsDev a) {
         // curvature transfer function: the curvature table's colour, its
         // opacity times the value table's
         float h[6], k1, k2;
-        query_hess<P, STORE>(a.m, rs, u, span, s == 0, f, g, h);
+        query_hess<P, STORE, false>(a.m, rs, u, span, s == 0, f, g, h);
         tf_sample(a, a.tf_lo, a.tf_scale, f, tf, sr, sg, sb, alpha);
         principal_curvatures(g, h, k1, k2);
         const float4 cc = curvature_lookup(a, k1, k2);
@@ -1008,7 +1069,7 @@ __global__ __launch_bounds__(256) void render_global_kernel(RenderArgsDev a) {
         alpha *= cc.w;
         phong_sample<SHADE>(a, g, eye, sr, sg, sb);
       } else {
-        query<P, STORE, SHADE, RAT>(a.m, rs, rsw, u, span, s == 0, f, g);
+        query<P, STORE, SHADE, RAT, false>(a.m, rs, rsw, u, span, s == 0, f, g);
         shade_sample<SHADE>(a, a.tf_lo, a.tf_scale, f, g, eye, tf, sr, sg, sb, alpha);
       }
       ++count;
@@ -2203,32 +2264,50 @@ __global__ __launch_bounds__(256) void eval_sort_count(EvalOrderDev o) {
   } else {
     if (o.flags[1] == 0u) return;
   }
+  constexpr int J = kEvalSortChunk / 256;
   __shared__ unsigned h[kEvalDigits];
+  __shared__ unsigned last[J][4];  // first pass: each wave's last key per round
   __shared__ unsigned h_desc;
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (tid < kEvalDigits) h[tid] = 0u;
   if (tid == 0) h_desc = 0u;
-  __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kEvalSortChunk;
+  // the thread's keys first (their loads in flight together)
+  unsigned key[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int64_t i = base + j * 256 + tid;
+    if constexpr (PASS == 0)
+      key[j] = i < o.n ? eval_key(o, i) : 0u;
+    else
+      key[j] = i < o.n ? (unsigned)o.key[PASS & 1][i] : 0u;
+  }
   bool descent = false;
-  for (int j = 0; j < kEvalSortChunk / 256; ++j) {
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
     const int64_t i = base + j * 256 + tid;
     const bool valid = i < o.n;
-    unsigned key = 0u;
-    if (valid) {
-      if constexpr (PASS == 0) {
-        key = eval_key(o, i);
-        o.key[0][i] = (uint16_t)key;
-      } else {
-        key = o.key[PASS & 1][i];
+    if constexpr (PASS == 0) {
+      if (valid) o.key[0][i] = (uint16_t)key[j];
+      const unsigned prev = (unsigned)__shfl_up((int)key[j], 1, 64);
+      descent |= valid && lane > 0 && key[j] < prev;
+      if (lane == 63) last[j][w] = key[j];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int64_t i = base + j * 256 + tid;
+    const bool valid = i < o.n;
+    if constexpr (PASS == 0) {
+      // a wave's first lane against the point before it
+      if (lane == 0 && valid && i > 0) {
+        const unsigned prev = w > 0 ? last[j][w - 1]
+                              : j > 0 ? last[j - 1][3] : eval_key(o, i - 1);
+        descent |= key[j] < prev;
       }
     }
-    if constexpr (PASS == 0) {
-      unsigned prev = (unsigned)__shfl_up((int)key, 1, 64);
-      if (lane == 0 && i > 0 && valid) prev = eval_key(o, i - 1);
-      descent |= valid && i > 0 && key < prev;
-    }
-    const unsigned d = eval_digit<PASS>(key);
+    const unsigned d = eval_digit<PASS>(key[j]);
     const unsigned long long m = match_digit(d, valid);
     if (valid && (m >> lane) == 1ull) atomicAdd(&h[d], (unsigned)__popcll(m));
   }
@@ -2468,9 +2547,9 @@ __global__ __launch_bounds__(1024) void eval_bin_items(EvalOrderDev o) {
 // at most g; empty bins share their first item with the next bin), its
 // share of the bin's points, then the bin's knots, basis-table rows and
 // box of control points in LDS.  Each point is evaluated as by
-// eval_kernel / eval_hess_kernel, with the same span (the bisection starts
-// from the slab's span range, which holds it), the same basis arithmetic
-// and the same control-point values, so the results are the same bits.
+// eval_kernel / eval_hess_kernel, with the same span (searched within the
+// slab's span range, which holds it), the same basis arithmetic and the
+// same control-point values, so the results are the same bits.
 template <int P, int STORE, int MODE>  // MODE 0: value, 1: and gradient, 2: and Hessian
 __global__ __launch_bounds__(256) void eval_bin_kernel(EvalArgsDev a, EvalBinDev d) {
   extern __shared__ __align__(16) unsigned char eval_lds[];
@@ -2536,29 +2615,44 @@ __global__ __launch_bounds__(256) void eval_bin_kernel(EvalArgsDev a, EvalBinDev
     const int sz = 256 / (ex * ey);
     const int sy = (256 - sz * ex * ey) / ex;
     const int sx = 256 - sz * ex * ey - sy * ex;
-    for (int e = tid; e < box; e += 256) {
-      const int gx = x0[0] + ix, gy = x0[1] + iy, gz = x0[2] + iz;
-      float v = 0.0f;
-      if (gx < nx && gy < ny && gz < nz) {
-        const int gi = gx + a.m.nx * gy + a.m.nxy * gz;
-        if constexpr (STORE == 0) {
-          v = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)gi * 4u, 0, 0));
-        } else {
-          const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)(gi >> 1) * 4u, 0, 0);
-          v = (gi & 1) ? h16_hi<STORE>(w) : h16_lo<STORE>(w);
+    // kStage elements per thread in flight: their loads first, then the
+    // LDS stores (element e + 256 j of a batch)
+    constexpr int kStage = 8;
+    for (int e = tid; e < box; e += 256 * kStage) {
+      uint32_t raw[kStage];
+      int gi[kStage];
+#pragma unroll
+      for (int j = 0; j < kStage; ++j) {
+        const int gx = x0[0] + ix, gy = x0[1] + iy, gz = x0[2] + iz;
+        const bool in = e + 256 * j < box && gx < nx && gy < ny && gz < nz;
+        gi[j] = in ? gx + a.m.nx * gy + a.m.nxy * gz : -1;
+        const uint32_t off = STORE == 0 ? (uint32_t)max(gi[j], 0) * 4u
+                                        : (uint32_t)(max(gi[j], 0) >> 1) * 4u;
+        raw[j] = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+        ix += sx;
+        iy += sy;
+        iz += sz;
+        if (ix >= ex) {
+          ix -= ex;
+          ++iy;
+        }
+        if (iy >= ey) {
+          iy -= ey;
+          ++iz;
         }
       }
-      B[e] = v;
-      ix += sx;
-      iy += sy;
-      iz += sz;
-      if (ix >= ex) {
-        ix -= ex;
-        ++iy;
-      }
-      if (iy >= ey) {
-        iy -= ey;
-        ++iz;
+#pragma unroll
+      for (int j = 0; j < kStage; ++j) {
+        if (e + 256 * j < box) {
+          float v = 0.0f;
+          if (gi[j] >= 0) {
+            if constexpr (STORE == 0)
+              v = __uint_as_float(raw[j]);
+            else
+              v = (gi[j] & 1) ? h16_hi<STORE>(raw[j]) : h16_lo<STORE>(raw[j]);
+          }
+          B[e + 256 * j] = v;
+        }
       }
     }
   }
@@ -2567,6 +2661,7 @@ __global__ __launch_bounds__(256) void eval_bin_kernel(EvalArgsDev a, EvalBinDev
   double un[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) un[k] = a.m.ax[k].knots[a.m.ax[k].n];
+  const bool uni = a.m.uniform != 0;
   const int pitch_z = ex * ey;
   // sorted by the passes (else the points came in key order)
   const bool permuted = d.flags[1] != 0u;
@@ -2583,10 +2678,17 @@ __global__ __launch_bounds__(256) void eval_bin_kernel(EvalArgsDev a, EvalBinDev
     int off[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
+      const AxisDev& A = a.m.ax[k];
       const double* Kk = K + k * kn - slo[k];  // Kk[s] = U[s] for s in [slo, shi + 1]
       int s;
       if (u[k] >= un[k]) {
-        s = a.m.ax[k].n - 1;
+        s = A.n - 1;
+      } else if (uni) {
+        // walked from the cell of u m within the slab's range, which holds
+        // the span
+        s = min(max(A.p + (int)(u[k] * A.m), slo[k]), shi[k]);
+        while (s < shi[k] && Kk[s + 1] <= u[k]) ++s;
+        while (s > slo[k] && Kk[s] > u[k]) --s;
       } else {
         int l = slo[k], h = shi[k] + 1;  // U[l] <= u < U[h]
         while (h - l > 1) {
@@ -2598,12 +2700,11 @@ __global__ __launch_bounds__(256) void eval_bin_kernel(EvalArgsDev a, EvalBinDev
         }
         s = l;
       }
-      const float dd = (float)(u[k] - Kk[s]);
       const float* row = T + (k * d.nspan + (s - slo[k])) * d.tstride;
       if constexpr (MODE == 2)
-        axis_basis2<P>(a.m.ax[k].p, row, dd, N[k], dN[k], ddN[k]);
+        query_basis2<P>(A, uni, s, u[k], Kk[s], row, N[k], dN[k], ddN[k]);
       else
-        axis_basis<P>(a.m.ax[k].p, row, dd, N[k], dN[k]);
+        query_basis<P>(A, uni, s, u[k], Kk[s], row, N[k], dN[k]);
       off[k] = s - slo[k];
     }
     const int e0 = off[0] + ex * off[1] + pitch_z * off[2];
