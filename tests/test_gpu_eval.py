@@ -191,12 +191,12 @@ def _morton_sorted(xyz, bits=10):
 
 def test_locality_order_equals_direct(mfa):
     """From 2^16 points on, queries of a model whose gathers miss the
-    caches are binned on the device and evaluated bin by bin (unless
-    neighbouring points already share bins).  Each
-    point's value, gradient and second derivatives are those of the same
-    point queried directly, bit for bit: scattered points (reordered),
-    points sorted along a Morton curve (left in place), and points outside
-    the box; the oracle checks a sample."""
+    caches are sorted by bin on the device (no sort when they arrive in bin
+    order) and evaluated bin by bin.  Each point's value, gradient and
+    second derivatives are those of the same point queried directly, bit
+    for bit: scattered points (sorted), points sorted along a Morton curve
+    (left in place), and points outside the box; the oracle checks a
+    sample."""
     torch = __import__("torch")
     b, ctx = mfa
     rng = np.random.default_rng(77)
