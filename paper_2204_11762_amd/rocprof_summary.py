@@ -105,6 +105,8 @@ def cmd_kernels(args) -> None:
         out += ["", "# the profiled program's own report (same run):"]
         with open(args.bench_log) as fh:
             out += ["#   " + ln.rstrip() for ln in fh if ln.startswith("[bench] store=")
+                    or ln.startswith("[bench] batch:") or ln.startswith("[bench] tuned batch:")
+                    or ln.startswith("[bench] autotune model")
                     or ln.startswith("[profile]") or "kernel source sha256" in ln]
     text = "\n".join(out) + "\n"
     with open(args.out, "w") as fh:
