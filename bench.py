@@ -786,9 +786,10 @@ def main():
                          / (head["nominal_kern_ms"] * 1e-3) / PEAK_FP32_VALU,
                          "kernel_ms": head["nominal_kern_ms"],
                          "call_ms": head["nominal_ms"],
-                         "note": "the same frame with termination off (the survey's roofline "
-                                 "configuration): composited samples x F(p) over the mean "
-                                 "duration of the ray-casting kernel"}},
+                         "note": "the same frame with termination off (the configuration "
+                                 "the VALU roofline fraction is defined on): composited "
+                                 "samples x F(p) over the mean duration of the ray-casting "
+                                 "kernel"}},
         "legs": {k: summary(v, k) for k, v in legs.items()},
     }
     if value_only is not None:
