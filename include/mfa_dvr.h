@@ -377,7 +377,9 @@ mfa_status mfa_server_submit(mfa_server* server, const mfa_render_request* req,
  * finish; on completion fill *info (nullable), forget the ticket and
  * return the request's status.  Errors: MFA_ERR_TIMEOUT (not finished; the
  * ticket stays valid), MFA_ERR_HANDLE (unknown or already waited-for
- * ticket), MFA_ERR_DEVICE (the request failed on the device). */
+ * ticket; of several threads waiting for one ticket, one receives the
+ * record and the others this), MFA_ERR_DEVICE (the request failed on the
+ * device). */
 mfa_status mfa_server_wait(mfa_server* server, int64_t ticket, int64_t timeout_us,
                            mfa_request_info* info);
 

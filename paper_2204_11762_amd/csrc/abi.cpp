@@ -2018,15 +2018,23 @@ mfa_status mfa_server_wait(mfa_server* sv, int64_t ticket, int64_t timeout_us,
   g_last_error.clear();
   if (sv == nullptr) return fail(MFA_ERR_HANDLE, "null server");
   std::unique_lock<std::mutex> lk(sv->mu);
-  auto it = sv->tickets.find(ticket);
-  if (it == sv->tickets.end()) return fail(MFA_ERR_HANDLE, "unknown ticket");
-  auto ready = [&] { return sv->tickets[ticket].finished; };
+  if (sv->tickets.find(ticket) == sv->tickets.end())
+    return fail(MFA_ERR_HANDLE, "unknown ticket");
+  // finished, or forgotten by another thread's wait on the same ticket
+  auto ready = [&] {
+    const auto jt = sv->tickets.find(ticket);
+    return jt == sv->tickets.end() || jt->second.finished;
+  };
   if (timeout_us < 0)
     sv->done_cv.wait(lk, ready);
   else if (!sv->done_cv.wait_for(lk, std::chrono::microseconds(timeout_us), ready))
     return fail(MFA_ERR_TIMEOUT, "request not finished");
-  const TicketState ts = sv->tickets[ticket];
-  sv->tickets.erase(ticket);
+  const auto it = sv->tickets.find(ticket);
+  if (it == sv->tickets.end()) return fail(MFA_ERR_HANDLE, "ticket already waited for");
+  const TicketState ts = it->second;
+  sv->tickets.erase(it);
+  // other waiters on this ticket see it gone
+  sv->done_cv.notify_all();
   if (info != nullptr) *info = ts.info;
   if (ts.info.status != MFA_OK) return fail(ts.info.status, "request failed on the device");
   return MFA_OK;

@@ -152,6 +152,46 @@ def test_server_errors(mfa):
             b.mfa_model_free(ctx, h)
 
 
+
+def test_server_two_waits_on_one_ticket(mfa):
+    """Two host threads waiting for the same ticket: one receives the
+    request's record, the other the error for an already waited-for ticket;
+    neither is left waiting (each wait has a 10 s limit, so a wait that
+    missed the other's hand-over shows up as a time-out, not a hang)."""
+    import torch
+    b, ctx = mfa
+    models, reqs = _requests(35, 1)
+    handles = _upload(b, ctx, models)
+    r = reqs[0]
+    out = torch.zeros((r.camera.height, r.camera.width, 4), dtype=torch.float32, device="cuda")
+    try:
+        server = b.mfa_server_create(ctx)
+        try:
+            results = [None, None]
+
+            def wait(k, ticket):
+                try:
+                    results[k] = b.mfa_server_wait(server, ticket, 10_000_000)
+                except b.MFAError as exc:
+                    results[k] = exc.status
+
+            for _ in range(3):
+                t = b.mfa_server_submit(server, handles[r.model], r.camera, r.tf, r.params, out)
+                ths = [threading.Thread(target=wait, args=(k, t)) for k in range(2)]
+                for th in ths:
+                    th.start()
+                for th in ths:
+                    th.join()
+                infos = [x for x in results if isinstance(x, b.RequestInfo)]
+                errors = [x for x in results if not isinstance(x, b.RequestInfo)]
+                assert len(infos) == 1 and infos[0].status == b.MFA_OK, results
+                assert errors == [b.MFA_ERR_HANDLE], results
+        finally:
+            b.mfa_server_destroy(server)
+    finally:
+        for h in handles:
+            b.mfa_model_free(ctx, h)
+
 # Requests shaped like the serving workload: (model of the serving set, image
 # size, samples per unit length).  Models 9, 10, 11 and 15 are the 256^3 ones
 # (p 2 FP32 Beta, p 3 BF16 uniform, p 4 BF16 Beta, p 2 BF16 Beta).
