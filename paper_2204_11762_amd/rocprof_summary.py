@@ -92,6 +92,13 @@ def cmd_counters(args) -> None:
     sys.stdout.write(text)
 
 
+# lines of the profiled program's report that a kernel table quotes: the
+# per-leg figures of the bench and of profile_frames
+BENCH_LINES = ("[bench] store=", "[bench] batch:", "[bench] tuned batch:",
+               "[bench] autotune model", "[bench] serve:", "[bench] curvature:",
+               "[bench] eval sweep", "[profile]")
+
+
 def cmd_kernels(args) -> None:
     rows = kernel_table(args.stats)
     out = [f"# rocprofv3 kernel statistics: {args.title}", "#", f"# command: {args.command}",
@@ -104,10 +111,8 @@ def cmd_kernels(args) -> None:
     if args.bench_log:
         out += ["", "# the profiled program's own report (same run):"]
         with open(args.bench_log) as fh:
-            out += ["#   " + ln.rstrip() for ln in fh if ln.startswith("[bench] store=")
-                    or ln.startswith("[bench] batch:") or ln.startswith("[bench] tuned batch:")
-                    or ln.startswith("[bench] autotune model")
-                    or ln.startswith("[profile]") or "kernel source sha256" in ln]
+            out += ["#   " + ln.rstrip() for ln in fh
+                    if ln.startswith(BENCH_LINES) or "kernel source sha256" in ln]
     text = "\n".join(out) + "\n"
     with open(args.out, "w") as fh:
         fh.write(text)

@@ -45,14 +45,16 @@ def test_kernel_table_sorted_by_total_and_names_shortened(tmp_path):
     assert rs.short_name(rows[1]["name"]) == "plan_cost_kernel"
     log = tmp_path / "bench.log"
     log.write_text(f"[bench] kernel source sha256 {SHA}\n[bench] store=bf16: x\nnoise\n"
-                   "[bench] batch: 64 requests\n")
+                   "[bench] batch: 64 requests\n[bench] serve: 800 requests\n"
+                   "[bench] eval fp32 random: 1 ms\n")
     out = tmp_path / "k.txt"
     rs.main(["kernels", str(stats), "--title", "t", "--command", "cmd", "--out", str(out),
              "--bench-log", str(log)])
     text = out.read_text()
     assert "# command: cmd" in text and "650.00" in text
     assert "[bench] store=bf16: x" in text and "[bench] batch: 64 requests" in text
-    assert "noise" not in text
+    assert "[bench] serve: 800 requests" in text
+    assert "noise" not in text and "eval fp32 random" not in text
 
 
 def test_counters_median_per_unit_and_per_lane(tmp_path):
